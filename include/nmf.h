@@ -1,0 +1,183 @@
+/*
+ * nmf.h -- C ABI of the enforced-sparsity NMF library for AMD MI355X (gfx950).
+ *
+ * The library factors a sparse non-negative term/document matrix A (n x m)
+ * as A ~ U V^T with U (n x k) >= 0 and V (m x k) >= 0, minimising
+ * ||A - U V^T|| (Eqs. (1)-(2) of Gavin, Gadepally and Kepner, "Enforced Sparse
+ * Non-Negative Matrix Factorization").  One iteration is Algorithm 2:
+ *   V = A^T U (U^T U)^-1, negatives set to zero, keep the t_v largest;
+ *   U = A V (V^T V)^-1,  negatives set to zero, keep the t_u largest;
+ * with the "keep the t largest" rule of Section 2 applied to every column of
+ * U and V separately (the column-wise variant of Section 4) by default.
+ *
+ * Conventions shared by every entry point:
+ *  - Status codes only; nothing is thrown across the ABI.  nmf_last_error()
+ *    returns a message for the last failing call on a handle.
+ *  - Dense matrices are row-major, element type given by nmf_config.dtype
+ *    (float for NMF_F32, double for NMF_F64).
+ *  - "Host or device" pointers: the library asks the HIP runtime which one a
+ *    pointer is and copies accordingly.  The caller keeps ownership of every
+ *    array it passes; nothing is retained after a call returns.
+ *  - All device memory the library uses lives in one caller-provided
+ *    workspace (sized by nmf_workspace_size); the library never allocates
+ *    device memory itself.
+ *  - Asynchronous calls enqueue work on the handle's HIP stream and return at
+ *    once.  Calls marked "synchronizes" wait for that stream.
+ *  - Numerical failures detected on the device (NMF_ERR_NOT_SPD,
+ *    NMF_ERR_NONFINITE) are sticky: they surface at the next synchronizing
+ *    call, and every later kernel of the handle does nothing.
+ *  - A handle is not thread-safe; use one handle per thread.
+ */
+#ifndef NMF_H
+#define NMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmf_handle nmf_handle;
+
+typedef enum {
+  NMF_OK = 0,
+  NMF_ERR_INVALID_ARG = -1,   /* bad size, null pointer, malformed CSR      */
+  NMF_ERR_INVALID_INPUT = -2, /* negative, NaN or Inf value in A or factors  */
+  NMF_ERR_UNSUPPORTED = -3,   /* k > 128, unknown dtype or mode              */
+  NMF_ERR_NOT_SPD = -4,       /* Gram matrix not positive definite           */
+  NMF_ERR_NONFINITE = -5,     /* NaN/Inf produced (e.g. ||U_i|| = 0 in R)    */
+  NMF_ERR_DEVICE = -6,        /* a HIP runtime call failed                   */
+  NMF_ERR_STATE = -7,         /* call not valid in the handle's state        */
+  NMF_ERR_WORKSPACE = -8      /* workspace too small or misaligned           */
+} nmf_status;
+
+/* Sparsity enforcement mode. */
+enum {
+  NMF_MODE_COLUMN = 0, /* t largest per column (Section 4)                    */
+  NMF_MODE_NONE = 1,   /* projection only: Algorithm 1                        */
+  NMF_MODE_WHOLE = 2   /* t largest of the whole matrix (Algorithm 2 printed) */
+};
+
+/* Arithmetic type of A, U, V and of the sparse products.  The k x k Gram
+ * factorisation and the solve are always float64. */
+enum { NMF_F32 = 0, NMF_F64 = 1 };
+
+/* nmf_config.flags */
+enum {
+  NMF_FLAG_NO_METRICS = 1 /* skip the per-iteration E and R (history keeps nnz) */
+};
+
+typedef struct {
+  int64_t n;     /* terms (rows of A, rows of U)                  */
+  int64_t m;     /* documents (columns of A, rows of V)           */
+  int32_t k;     /* topics, 1 <= k <= min(n, m, 128)               */
+  int32_t mode;  /* NMF_MODE_*                                     */
+  int64_t t_u;   /* kept entries per column of U (>= 1)            */
+  int64_t t_v;   /* kept entries per column of V (>= 1)            */
+  int32_t dtype; /* NMF_F32 | NMF_F64                              */
+  int32_t flags; /* NMF_FLAG_*                                     */
+} nmf_config;
+
+/* Bytes of device workspace a handle for this configuration and this many
+ * nonzeros of A needs.  Pure host computation; no device is touched.
+ * Errors: NMF_ERR_INVALID_ARG / NMF_ERR_UNSUPPORTED for a bad config. */
+nmf_status nmf_workspace_size(const nmf_config* cfg, int64_t nnz, size_t* bytes);
+
+/* Create a handle for A given in CSR over term rows: a_rowptr[n+1] (int64,
+ * a_rowptr[0] = 0, non-decreasing, a_rowptr[n] = nnz), a_col[nnz] (int32,
+ * strictly increasing within a row, in [0, m)), a_val[nnz] (dtype, finite,
+ * >= 0).  u0 is the initial guess U0 (n x k, finite, >= 0) of Algorithms 1-2;
+ * v0 (m x k) is optional (NULL) and only serves nmf_error before the first
+ * step.  workspace/ws_bytes: device memory of at least nmf_workspace_size()
+ * bytes, 256-byte aligned, owned by the caller and not touched by anyone else
+ * while the handle lives.  hip_stream: the hipStream_t every kernel of this
+ * handle runs on (NULL = the default stream).  Copies A, U0 (and V0) into the
+ * workspace, builds the transposed copy of A, and synchronizes.
+ * Errors: INVALID_ARG (malformed CSR, sizes), INVALID_INPUT (negative or
+ * non-finite values, ||A|| = 0), UNSUPPORTED, WORKSPACE, DEVICE.  On error
+ * *out is NULL. */
+nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col,
+                      const void* a_val, int64_t nnz, const void* u0, const void* v0,
+                      void* workspace, size_t ws_bytes, void* hip_stream, nmf_handle** out);
+
+/* Enqueue `iters` iterations of Algorithm 2 (V half-step first, from the
+ * current U), each followed by R and E of Section 3.1 unless
+ * NMF_FLAG_NO_METRICS.  Asynchronous.  iters >= 0. */
+nmf_status nmf_als_step(nmf_handle* h, int32_t iters);
+
+/* One half-step only: which = 0 solves V from the current U (Algorithm 2
+ * steps 1-2), which = 1 solves U from the current V (steps 3-4; the previous
+ * U becomes U_{i-1}).  No metrics are recorded.  Asynchronous. */
+nmf_status nmf_half_step(nmf_handle* h, int32_t which);
+
+/* Relative error E = ||A - U V^T||_F / ||A||_F (Section 3.1) of the current
+ * U and V.  Synchronizes.  NMF_ERR_STATE if no V exists yet (no step taken
+ * and no v0 given). */
+nmf_status nmf_error(nmf_handle* h, double* E);
+
+/* Relative residual R = ||U_i - U_{i-1}||_F / ||U_i||_F (Section 3.1) of the
+ * last completed iteration.  Synchronizes.  NMF_ERR_STATE before the first
+ * iteration. */
+nmf_status nmf_residual(nmf_handle* h, double* R);
+
+/* Per-iteration record, oldest first, of up to `cap` of the most recent
+ * iterations: E, R, nnz(U), nnz(V) (any of the arrays may be NULL).  *len
+ * receives the number written.  Synchronizes.  With NMF_FLAG_NO_METRICS, E
+ * and R are NaN. */
+nmf_status nmf_history(nmf_handle* h, double* E, double* R, int64_t* nnz_u, int64_t* nnz_v,
+                       int32_t cap, int32_t* len);
+
+/* Largest nnz(U) + nnz(V) held at the end of any half-step so far, counting
+ * U0 (the storage high-water mark of Section 3.2).  Synchronizes. */
+nmf_status nmf_max_nnz(nmf_handle* h, int64_t* max_nnz_uv);
+
+/* Copy the current factors out as dense row-major arrays (host or device):
+ * u_dense n x k, v_dense m x k; either may be NULL.  Synchronizes. */
+nmf_status nmf_get_factors(nmf_handle* h, void* u_dense, void* v_dense);
+
+/* Export the current factors in the row-compressed sparse form the library
+ * stores: row_ptr int32[rows+1], topic uint8[nnz], val dtype[nnz], topics
+ * ascending within a row.  Pass NULL arrays to query only *nnz.  Host or
+ * device pointers.  which = 0 for U, 1 for V.  Synchronizes. */
+nmf_status nmf_get_sparse(nmf_handle* h, int32_t which, int32_t* row_ptr, uint8_t* topic,
+                          void* val, int64_t* nnz);
+
+/* Replace the state: u (n x k, required), u_prev (n x k, U_{i-1} for the
+ * next residual; NULL = same as u), v (m x k, NULL = keep).  Dense row-major,
+ * host or device, finite and >= 0; zeros are not stored.  Used to resume a
+ * run or to start a half-step from a given state.  Synchronizes.
+ * Errors: INVALID_ARG, INVALID_INPUT. */
+nmf_status nmf_set_factors(nmf_handle* h, const void* u, const void* u_prev, const void* v);
+
+/* The clamped pre-selection matrix of the last half-step of each kind:
+ * which = 0: max(0, A^T U (U^T U)^-1) (m x k); which = 1: max(0, A V (V^T V)^-1)
+ * (n x k).  Dense row-major, host or device.  Synchronizes. */
+nmf_status nmf_get_pre(nmf_handle* h, int32_t which, void* dst);
+
+/* Squared loss L = ||A - U V^T||_F^2 = ||A||^2 - 2 tr(U^T A V) + tr(U^T U V^T V)
+ * (the squared objective of Eq. (2)) for caller-given dense U (n x k) and
+ * V (m x k), device pointers of the handle's dtype.  *loss_dev is a device
+ * float64.  Uses the handle's copy of A.  Asynchronous. */
+nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* loss_dev);
+
+/* Gradient of that loss scaled by the device scalar *g_scale (float64; pass
+ * NULL for 1): gU = g (-2 A V + 2 U V^T V), gV = g (-2 A^T U + 2 V U^T U).
+ * Device pointers, dtype of the handle, gU n x k and gV m x k (either may be
+ * NULL to skip).  Asynchronous. */
+nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const double* g_scale,
+                        void* gU, void* gV);
+
+/* Message for the last error on this handle (or of the last failed
+ * nmf_create when h is NULL).  Never NULL. */
+const char* nmf_last_error(const nmf_handle* h);
+
+/* Release the handle (host memory only; the workspace stays the caller's).
+ * Waits for the handle's stream.  NULL is allowed. */
+void nmf_destroy(nmf_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMF_H */

@@ -1,0 +1,407 @@
+// Per-iteration metrics of Section 3.1 and the small helpers around them.
+//
+//   R = ||U_i - U_{i-1}||_F / ||U_i||_F, formed directly from the two
+//       stored factors row by row (no cancellation, so R can fall to the
+//       rounding floor);
+//   E = ||A - U V^T||_F / ||A||_F with
+//       ||A - U V^T||^2 = ||A||^2 - 2 <U, A V> + <U^T U, V^T V>,
+//       where A V is the raw product kept by the U half-step and the two
+//       Gram matrices come from the Gram kernels.
+// Every sum is float64 over fixed blocks, added in block order by the last
+// block to finish, so the history is reproducible bit for bit.
+#include <cmath>
+
+#include "nmf_device.h"
+
+namespace nmfk {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// sums three doubles over the block into out[0..2] (thread 0 holds them)
+__device__ __forceinline__ void block_sum3(double a, double b, double c, double* sh, double* out) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = __lane_id(), wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[wv * 3 + 0] = a;
+    sh[wv * 3 + 1] = b;
+    sh[wv * 3 + 2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0, y = 0, z = 0;
+    for (int w = 0; w < 4; ++w) {
+      x += sh[w * 3 + 0];
+      y += sh[w * 3 + 1];
+      z += sh[w * 3 + 2];
+    }
+    out[0] = x;
+    out[1] = y;
+    out[2] = z;
+  }
+}
+
+struct MetArgs {
+  int64_t n;
+  int32_t k;
+  const int32_t* slot_new;
+  const int32_t* slot_old;
+  const void* dense_new;
+  const void* dense_old;
+  const void* C;  // raw A V (n x k), or nullptr
+  double* partials;
+  int32_t* ticket;
+  const double* GU;
+  const double* GV;
+  const double* nA2;
+  double* ring;
+  int64_t* it;
+  const int32_t* nnz_u;
+  const int32_t* nnz_v;
+  const int32_t* dead_u;
+  const int32_t* dead_v;
+  int32_t record;  // 0: only nnz / dead counts (E, R = NaN)
+  int32_t* status;
+};
+
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
+  __shared__ double sh[12];
+  __shared__ double tot[3];
+  __shared__ int last;
+  if (*a.status != 0) return;
+  const int k = a.k;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  double d2 = 0.0, n2 = 0.0, x = 0.0;
+  if (a.record) {
+    const int P = gridDim.x;
+    const int64_t lo = a.n * blockIdx.x / P;
+    const int64_t hi = a.n * (blockIdx.x + 1) / P;
+    const T* __restrict__ Dn = static_cast<const T*>(a.dense_new);
+    const T* __restrict__ Do = static_cast<const T*>(a.dense_old);
+    const T* __restrict__ C = static_cast<const T*>(a.C);
+    for (int64_t base = lo + wv * 64; base < hi; base += 256) {
+      const int64_t r = base + lane;
+      int sn = -1, so = -1;
+      if (r < hi) {
+        sn = a.slot_new[r];
+        so = a.slot_old[r];
+      }
+      uint64_t todo = __ballot(sn >= 0 || so >= 0);
+      while (todo) {
+        const int b = __ffsll(static_cast<long long>(todo)) - 1;
+        todo &= todo - 1;
+        const int64_t row = base + b;
+        const int s1 = __shfl(sn, b, 64);
+        const int s0 = __shfl(so, b, 64);
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+          const int c = lane + 64 * q;
+          if (c < k) {
+            const double un = s1 >= 0 ? static_cast<double>(Dn[static_cast<int64_t>(s1) * k + c]) : 0.0;
+            const double uo = s0 >= 0 ? static_cast<double>(Do[static_cast<int64_t>(s0) * k + c]) : 0.0;
+            const double dd = un - uo;
+            d2 = fma(dd, dd, d2);
+            n2 = fma(un, un, n2);
+            if (C != nullptr && s1 >= 0) x = fma(un, static_cast<double>(C[row * k + c]), x);
+          }
+        }
+      }
+    }
+  }
+  block_sum3(d2, n2, x, sh, tot);
+  if (threadIdx.x == 0) {
+    double* p = a.partials + blockIdx.x * 4;
+    p[0] = tot[0];
+    p[1] = tot[1];
+    p[2] = tot[2];
+  }
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1) == static_cast<int>(gridDim.x) - 1;
+  __syncthreads();
+  if (!last) return;
+  fence_acquire();
+  // quadratic term <G_U, G_V>, summed by thread 0 in fixed order below
+  double q = 0.0;
+  if (a.record && a.GU != nullptr)
+    for (int i = threadIdx.x; i < k * k; i += 256) q = fma(a.GU[i], a.GV[i], q);
+  __syncthreads();
+  block_sum3(q, 0.0, 0.0, sh, tot);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double D = 0, N = 0, X = 0;
+  for (int b = 0; b < static_cast<int>(gridDim.x); ++b) {
+    const double* p = a.partials + b * 4;
+    D += __builtin_nontemporal_load(&p[0]);
+    N += __builtin_nontemporal_load(&p[1]);
+    X += __builtin_nontemporal_load(&p[2]);
+  }
+  const int64_t it = *a.it;
+  double* rec = a.ring + (it % kHistRing) * H_FIELDS;
+  double E = __builtin_nan(""), R = __builtin_nan("");
+  if (a.record) {
+    R = sqrt(D) / sqrt(N);
+    const double nA2 = *a.nA2;
+    const double e2 = nA2 - 2.0 * X + tot[0];
+    E = sqrt(e2 > 0.0 ? e2 : 0.0) / sqrt(nA2);
+    if (!isfinite(R) || !isfinite(E)) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
+  }
+  rec[H_E] = E;
+  rec[H_R] = R;
+  rec[H_NNZU] = static_cast<double>(*a.nnz_u);
+  rec[H_NNZV] = static_cast<double>(*a.nnz_v);
+  rec[H_DEADU] = static_cast<double>(*a.dead_u);
+  rec[H_DEADV] = static_cast<double>(*a.dead_v);
+  *a.it = it + 1;
+  *a.ticket = 0;
+}
+
+// <U, C> for dense U, C (n x k) and L = ||A||^2 - 2 <U, C> + <G_U, G_V>
+template <typename T>
+__global__ __launch_bounds__(256) void k_loss(int64_t count, const T* U, const T* C,
+                                              const double* GU, const double* GV, int k,
+                                              const double* nA2, double* partials, int32_t* ticket,
+                                              double* out) {
+  __shared__ double sh[12];
+  __shared__ double tot[3];
+  __shared__ int last;
+  const int P = gridDim.x;
+  const int64_t lo = count * blockIdx.x / P;
+  const int64_t hi = count * (blockIdx.x + 1) / P;
+  double x = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256)
+    x = fma(static_cast<double>(U[i]), static_cast<double>(C[i]), x);
+  block_sum3(x, 0.0, 0.0, sh, tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot[0];
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == P - 1;
+  __syncthreads();
+  if (!last) return;
+  fence_acquire();
+  double q = 0.0;
+  for (int i = threadIdx.x; i < k * k; i += 256) q = fma(GU[i], GV[i], q);
+  __syncthreads();
+  block_sum3(q, 0.0, 0.0, sh, tot);
+  if (threadIdx.x != 0) return;
+  double X = 0.0;
+  for (int b = 0; b < P; ++b) X += __builtin_nontemporal_load(&partials[b]);
+  *out = *nA2 - 2.0 * X + tot[0];
+  *ticket = 0;
+}
+
+// out = g * (-2 B + 2 F G) for dense F, B (rows x k), G (k x k, float64)
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_grad(const T* F, const T* B, const double* G,
+                                              const double* g_scale, int64_t rows, int k, T* out) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sG = reinterpret_cast<double*>(smem);
+  for (int i = threadIdx.x; i < k * k; i += 256) sG[i] = G[i];
+  __syncthreads();
+  const double gs = g_scale ? *g_scale : 1.0;
+  const int lane = lane_id();
+  const int64_t wg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
+  for (int64_t r = wg; r < rows; r += nw) {
+    double acc[KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) acc[q] = 0.0;
+    for (int a = 0; a < k; ++a) {
+      const double f = static_cast<double>(F[r * k + a]);
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) {
+        const int c = lane + 64 * q;
+        if (c < k) acc[q] = fma(f, sG[a * k + c], acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      if (c < k) {
+        const double b = static_cast<double>(B[r * k + c]);
+        out[r * k + c] = static_cast<T>(gs * (2.0 * acc[q] - 2.0 * b));
+      }
+    }
+  }
+}
+
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_densify(const int32_t* slot, const T* dense, int64_t rows,
+                                                 int k, T* out) {
+  const int lane = lane_id();
+  const int64_t wg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
+  for (int64_t r = wg; r < rows; r += nw) {
+    const int s = slot[r];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      if (c < k) out[r * k + c] = s >= 0 ? dense[static_cast<int64_t>(s) * k + c] : T(0);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_check(const T* x, int64_t count, int32_t* flag) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t st = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  bool bad = false;
+  for (int64_t i = i0; i < count; i += st) {
+    const T v = x[i];
+    if (!(v >= T(0)) || !isfinite(v)) bad = true;
+  }
+  if (__ballot(bad) != 0 && __lane_id() == 0) atomicOr(flag, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sumsq(const T* x, int64_t count, double* partials,
+                                               int32_t* ticket, double* out) {
+  __shared__ double sh[12];
+  __shared__ double tot[3];
+  __shared__ int last;
+  const int P = gridDim.x;
+  const int64_t lo = count * blockIdx.x / P;
+  const int64_t hi = count * (blockIdx.x + 1) / P;
+  double s = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double v = static_cast<double>(x[i]);
+    s = fma(v, v, s);
+  }
+  block_sum3(s, 0.0, 0.0, sh, tot);
+  if (threadIdx.x == 0) partials[blockIdx.x] = tot[0];
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == P - 1;
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  fence_acquire();
+  double S = 0.0;
+  for (int b = 0; b < P; ++b) S += __builtin_nontemporal_load(&partials[b]);
+  *out = S;
+  *ticket = 0;
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
+  const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t st = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = i0; i < count; i += st) p[i] = v;
+}
+
+int grid_for(int64_t work, int per_block, int cap) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return static_cast<int>(b);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const T* C, bool record) {
+  MetArgs a{};
+  a.n = h->n;
+  a.k = h->k;
+  a.slot_new = Unew.slot;
+  a.slot_old = Uold.slot;
+  a.dense_new = Unew.dense;
+  a.dense_old = Uold.dense;
+  a.C = C;
+  a.partials = h->met.partials;
+  a.ticket = h->met.ticket;
+  a.GU = h->gU.G;
+  a.GV = h->gV.G;
+  a.nA2 = h->met.nA2;
+  a.ring = h->met.ring;
+  a.it = h->met.it;
+  a.nnz_u = Unew.counts;
+  a.nnz_v = h->V.counts;
+  a.dead_u = h->gU.dead;
+  a.dead_v = h->gV.dead;
+  a.record = record ? 1 : 0;
+  a.status = h->status;
+  if (h->k > 64)
+    hipLaunchKernelGGL((k_metrics<T, 2>), dim3(kMetricBlocks), dim3(256), 0, h->stream, a);
+  else
+    hipLaunchKernelGGL((k_metrics<T, 1>), dim3(kMetricBlocks), dim3(256), 0, h->stream, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t loss_dot(nmf_handle* h, const T* U, const T* C, const double* GU, const double* GV,
+                    double* loss_out) {
+  hipLaunchKernelGGL((k_loss<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, h->n * h->k, U, C, GU,
+                     GV, h->k, h->met.nA2, h->met.loss_parts, h->met.ticket, loss_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t grad_combine(nmf_handle* h, const T* F, const T* B, const double* G,
+                        const double* g_scale, int64_t rows, T* out) {
+  const int blocks = grid_for(rows, 4, h->num_cus * 8);
+  const size_t lds = static_cast<size_t>(h->k) * h->k * sizeof(double);
+  if (h->k > 64)
+    hipLaunchKernelGGL((k_grad<T, 2>), dim3(blocks), dim3(256), lds, h->stream, F, B, G, g_scale, rows,
+                       h->k, out);
+  else
+    hipLaunchKernelGGL((k_grad<T, 1>), dim3(blocks), dim3(256), lds, h->stream, F, B, G, g_scale, rows,
+                       h->k, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t densify(nmf_handle* h, const Factor& F, T* out) {
+  const int blocks = grid_for(F.rows, 4, h->num_cus * 8);
+  if (h->k > 64)
+    hipLaunchKernelGGL((k_densify<T, 2>), dim3(blocks), dim3(256), 0, h->stream, F.slot,
+                       static_cast<const T*>(F.dense), F.rows, h->k, out);
+  else
+    hipLaunchKernelGGL((k_densify<T, 1>), dim3(blocks), dim3(256), 0, h->stream, F.slot,
+                       static_cast<const T*>(F.dense), F.rows, h->k, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t check_input(nmf_handle* h, const T* x, int64_t count, int32_t* flag) {
+  if (count == 0) return hipSuccess;
+  const int blocks = grid_for(count, 256 * 8, h->num_cus * 8);
+  hipLaunchKernelGGL((k_check<T>), dim3(blocks), dim3(256), 0, h->stream, x, count, flag);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t sum_squares(nmf_handle* h, const T* x, int64_t count, double* out) {
+  hipLaunchKernelGGL((k_sumsq<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, x, count,
+                     h->met.loss_parts, h->met.ticket, out);
+  return hipGetLastError();
+}
+
+hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t count) {
+  if (count == 0) return hipSuccess;
+  const int blocks = grid_for(count, 256 * 4, 1024);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+#define NMF_INST(T)                                                                            \
+  template hipError_t metrics<T>(nmf_handle*, const Factor&, const Factor&, const T*, bool);  \
+  template hipError_t loss_dot<T>(nmf_handle*, const T*, const T*, const double*,             \
+                                  const double*, double*);                                    \
+  template hipError_t grad_combine<T>(nmf_handle*, const T*, const T*, const double*,         \
+                                      const double*, int64_t, T*);                            \
+  template hipError_t densify<T>(nmf_handle*, const Factor&, T*);                             \
+  template hipError_t check_input<T>(nmf_handle*, const T*, int64_t, int32_t*);               \
+  template hipError_t sum_squares<T>(nmf_handle*, const T*, int64_t, double*);
+NMF_INST(float)
+NMF_INST(double)
+#undef NMF_INST
+
+}  // namespace nmfk

@@ -1,0 +1,391 @@
+// Per-column top-t selection of a clamped pre-selection matrix X (rows x k,
+// row-major): Section 2's rule (keep the t largest entries) applied to every
+// column separately as in Section 4.  Exactly min(t, #positive) entries
+// survive per column; among entries equal to the t-th largest value the
+// lowest rows win, i.e. the kept set is the t largest under the order
+// (value descending, row ascending).  Only strictly positive entries are
+// candidates (zeros are never stored).
+//
+// Radix select on the IEEE bits of the positive values (they order like
+// unsigned integers):
+//  1. hist:    per-column histogram of the first digit (the 8 bits under
+//              the sign bit: the exponent for float32), block-private in LDS,
+//              flushed with integer atomics.  The last block to finish picks,
+//              per column, the digit b1 holding the t-th largest entry.
+//  2. collect: one pass over X: entries whose digit is above b1 are kept
+//              (bit set in the per-row keep mask); entries with digit b1 are
+//              appended to the column's candidate list.
+//  3. refine:  one block per column narrows the candidates digit by digit
+//              (remaining value bits, then the row bits for the tie-break),
+//              keeping whole digits above the threshold, until few enough
+//              remain to sort in LDS.
+// Only integer atomics are used, so the kept set does not depend on
+// scheduling; the row-compressed factor is then built in row order from the
+// keep masks (k_repack.hip).
+#include "nmf_device.h"
+
+namespace nmfk {
+
+namespace {
+
+constexpr int kRowsPerBlock = 64;  // rows of X per hist/collect block
+constexpr int kPadBins = kBins + 1;
+
+struct SelArgs {
+  const void* X;
+  int64_t rows;
+  int32_t k;
+  int32_t mw;  // mask words per row
+  int64_t t;
+  int32_t mode;
+  uint32_t* hist;
+  ColSel* sel;
+  int32_t* cand_cnt;  // padded: column c at cand_cnt[c * kCntStride]
+  void* candA;
+  void* candB;
+  int64_t stride;
+  uint32_t* mask;
+  int32_t* ticket;
+  int32_t* status;
+};
+
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_hist(SelArgs a) {
+  using KO = KeyOf<T>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins]
+  __shared__ int last;
+  if (*a.status != 0) return;
+  const int k = a.k;
+  for (int i = threadIdx.x; i < k * kPadBins; i += 256) h[i] = 0;
+  __syncthreads();
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock;
+  int64_t r_end = r_begin + kRowsPerBlock;
+  if (r_end > a.rows) r_end = a.rows;
+  for (int64_t r = r_begin + wv; r < r_end; r += 4) {
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      if (c < k) {
+        const auto key = KO::key(X[r * k + c]);
+        if (key != 0) atomicAdd(&h[c * kPadBins + top_digit<T>(key)], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k * kBins; i += 256) {
+    const int c = i / kBins, d = i - c * kBins;
+    const uint32_t v = h[c * kPadBins + d];
+    if (v) atomicAdd(&a.hist[i], v);
+  }
+  fence_release();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&a.ticket[0], 1) == static_cast<int>(gridDim.x) - 1;
+  __syncthreads();
+  if (!last) return;
+  fence_acquire();
+  // last block: choose the threshold digit of every column and clear the
+  // global histogram for the next use
+  for (int c = threadIdx.x; c < k; c += 256) {
+    uint32_t* hc = a.hist + static_cast<int64_t>(c) * kBins;
+    int64_t npos = 0;
+    for (int d = 0; d < kBins; ++d) npos += __hip_atomic_load(&hc[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ColSel s;
+    s.npos = static_cast<int32_t>(npos);
+    s.all = (a.mode == NMF_MODE_NONE || npos <= a.t) ? 1 : 0;
+    s.b1 = -1;
+    s.need = 0;
+    if (!s.all) {
+      int64_t above = 0;
+      for (int d = kBins - 1; d >= 0; --d) {
+        const int64_t hd = __hip_atomic_load(&hc[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (above + hd >= a.t) {
+          s.b1 = d;
+          s.need = static_cast<int32_t>(a.t - above);
+          break;
+        }
+        above += hd;
+      }
+    }
+    a.sel[c] = s;
+    for (int d = 0; d < kBins; ++d) hc[d] = 0;
+  }
+  if (threadIdx.x == 0) a.ticket[0] = 0;
+}
+
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_collect(SelArgs a) {
+  using KO = KeyOf<T>;
+  using C = Cand<T>;
+  __shared__ int32_t lcnt[kMaxK];
+  __shared__ int32_t lbase[kMaxK];
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* stage = reinterpret_cast<C*>(smem);  // [k][kRowsPerBlock]
+  if (*a.status != 0) return;
+  const int k = a.k;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  for (int i = threadIdx.x; i < k; i += 256) lcnt[i] = 0;
+  ColSel s[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    s[q] = c < k ? a.sel[c] : ColSel{0, 0, 1, 0};
+  }
+  __syncthreads();
+  const T* __restrict__ X = static_cast<const T*>(a.X);
+  const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock;
+  int64_t r_end = r_begin + kRowsPerBlock;
+  if (r_end > a.rows) r_end = a.rows;
+  for (int64_t r = r_begin + wv; r < r_end; r += 4) {
+    uint64_t keep_bits[KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      bool keep = false;
+      if (c < k) {
+        const auto key = KO::key(X[r * k + c]);
+        if (key != 0) {
+          const int d = top_digit<T>(key);
+          keep = s[q].all || d > s[q].b1;
+          if (!s[q].all && d == s[q].b1) {
+            const int pos = atomicAdd(&lcnt[c], 1);
+            C cd;
+            cd.key = key;
+            cd.row = static_cast<uint32_t>(r);
+            stage[c * kRowsPerBlock + pos] = cd;
+          }
+        }
+      }
+      keep_bits[q] = __ballot(keep);
+    }
+    // the wave owns row r: write its keep-mask words directly
+    if (lane < a.mw) {
+      const int q = lane >> 1;
+      const uint64_t b = keep_bits[q < KPL ? q : 0];
+      const uint32_t word = (lane & 1) ? static_cast<uint32_t>(b >> 32) : static_cast<uint32_t>(b);
+      if (word) atomicOr(&a.mask[r * a.mw + lane], word);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += 256) {
+    const int n = lcnt[c];
+    lbase[c] = n ? atomicAdd(&a.cand_cnt[c * kCntStride], n) : 0;
+  }
+  __syncthreads();
+  C* __restrict__ out = static_cast<C*>(a.candA);
+  for (int c = wv; c < k; c += 4) {
+    const int n = lcnt[c];
+    for (int i = lane; i < n; i += 64)
+      out[static_cast<int64_t>(c) * a.stride + lbase[c] + i] = stage[c * kRowsPerBlock + i];
+  }
+}
+
+// digit of a candidate under the compound order; `kb` value bits and `rb`
+// row bits remain below the digits already fixed
+template <typename T>
+__device__ __forceinline__ int cand_digit(const Cand<T>& cd, int kb, int rb, int* width) {
+  if (kb > 0) {
+    const int w = kb < 8 ? kb : 8;
+    *width = w;
+    return static_cast<int>((cd.key >> (kb - w)) & ((1u << w) - 1));
+  }
+  const int w = rb < 8 ? rb : 8;
+  *width = w;
+  const uint32_t nr = ~cd.row;
+  return static_cast<int>((nr >> (rb - w)) & ((1u << w) - 1));
+}
+
+__device__ __forceinline__ void mark(uint32_t* mask, int mw, uint32_t row, int c) {
+  atomicOr(&mask[static_cast<int64_t>(row) * mw + (c >> 5)], 1u << (c & 31));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_refine(SelArgs a) {
+  using C = Cand<T>;
+  __shared__ uint32_t h[kBins];
+  __shared__ int s_bin, s_need, s_n, s_cnt;
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* srt = reinterpret_cast<C*>(smem);  // [kSmall]
+  if (*a.status != 0) return;
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ColSel s = a.sel[c];
+  int* cnt_ptr = &a.cand_cnt[c * kCntStride];
+  if (s.all || s.need <= 0) {
+    if (tid == 0) *cnt_ptr = 0;
+    return;
+  }
+  int n = __hip_atomic_load(cnt_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int need = s.need;
+  C* src = static_cast<C*>(a.candA) + static_cast<int64_t>(c) * a.stride;
+  C* dst = static_cast<C*>(a.candB) + static_cast<int64_t>(c) * a.stride;
+  int kb = KeyOf<T>::bits - 9;
+  int rb = 32;
+  while (n > kSmall && (kb > 0 || rb > 0)) {
+    for (int i = tid; i < kBins; i += 256) h[i] = 0;
+    __syncthreads();
+    int width;
+    for (int i = tid; i < n; i += 256) atomicAdd(&h[cand_digit<T>(src[i], kb, rb, &width)], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      int above = 0;
+      int bin = 0;
+      for (int d = kBins - 1; d >= 0; --d) {
+        const int hd = static_cast<int>(h[d]);
+        if (above + hd >= need) {
+          bin = d;
+          break;
+        }
+        above += hd;
+      }
+      s_bin = bin;
+      s_need = need - above;
+      s_n = static_cast<int>(h[bin]);
+      s_cnt = 0;
+    }
+    __syncthreads();
+    const int bin = s_bin;
+    for (int i = tid; i < n; i += 256) {
+      const C cd = src[i];
+      const int d = cand_digit<T>(cd, kb, rb, &width);
+      if (d > bin) {
+        mark(a.mask, a.mw, cd.row, c);
+      } else if (d == bin) {
+        const int pos = atomicAdd(&s_cnt, 1);
+        dst[pos] = cd;
+      }
+    }
+    if (kb > 0)
+      kb -= kb < 8 ? kb : 8;
+    else
+      rb -= rb < 8 ? rb : 8;
+    need = s_need;
+    n = s_n;
+    C* tmp = src;
+    src = dst;
+    dst = tmp;
+    __syncthreads();
+  }
+  // finish: sort the remaining candidates by the compound order (bitonic in
+  // LDS) and keep the first `need`.  Distinct rows make every compound key
+  // distinct, so at most one candidate can survive all digits; more means a
+  // corrupted list, reported instead of overrunning the LDS buffer.
+  if (n > kSmall) {
+    if (tid == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_DEVICE));
+    return;
+  }
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int i = tid; i < np; i += 256) {
+    if (i < n) {
+      srt[i] = src[i];
+    } else {
+      C z;
+      z.key = 0;
+      z.row = 0xFFFFFFFFu;
+      srt[i] = z;
+    }
+  }
+  __syncthreads();
+  for (int size = 2; size <= np; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < np; i += 256) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const C x = srt[i], y = srt[j];
+          // descending blocks put the "before" element first
+          const bool swap = desc ? cand_before<T>(y, x) : cand_before<T>(x, y);
+          if (swap) {
+            srt[i] = y;
+            srt[j] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < need && i < n; i += 256) mark(a.mask, a.mw, srt[i].row, c);
+  if (tid == 0) *cnt_ptr = 0;
+}
+
+template <typename T, int KPL>
+hipError_t run(nmf_handle* h, SelArgs& a) {
+  const int blocks = static_cast<int>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
+  if (blocks == 0) return hipSuccess;
+  const size_t hbytes = static_cast<size_t>(a.k) * kPadBins * sizeof(uint32_t);
+  const size_t stage = static_cast<size_t>(a.k) * kRowsPerBlock * sizeof(Cand<T>);
+  hipLaunchKernelGGL((k_hist<T, KPL>), dim3(blocks), dim3(256), hbytes, h->stream, a);
+  hipLaunchKernelGGL((k_collect<T, KPL>), dim3(blocks), dim3(256), stage, h->stream, a);
+  hipLaunchKernelGGL((k_refine<T>), dim3(a.k), dim3(256), kSmall * sizeof(Cand<T>), h->stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int mode,
+                       const Factor& out_f) {
+  (void)out_f;
+  SelArgs a{};
+  a.X = X;
+  a.rows = rows;
+  a.k = h->k;
+  a.mw = h->mask_words;
+  a.t = t;
+  a.mode = mode;
+  a.hist = h->sel.hist;
+  a.sel = h->sel.sel;
+  a.cand_cnt = h->sel.cand_cnt;
+  a.candA = h->sel.candA;
+  a.candB = h->sel.candB;
+  a.stride = h->sel.cand_stride;
+  a.mask = h->sel.mask;
+  a.ticket = h->sel.ticket;
+  a.status = h->status;
+  return h->k > 64 ? run<T, 2>(h, a) : run<T, 1>(h, a);
+}
+
+// Keep every nonzero entry (used to load given factors).
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_mark_nonzero(const T* X, int64_t rows, int k, int mw,
+                                                      uint32_t* mask) {
+  const int lane = lane_id();
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  uint64_t bits[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    bits[q] = __ballot(c < k && X[r * k + c] != T(0));
+  }
+  if (lane < mw) {
+    const int q = lane >> 1;
+    const uint64_t b = bits[q < KPL ? q : 0];
+    mask[r * mw + lane] = (lane & 1) ? static_cast<uint32_t>(b >> 32) : static_cast<uint32_t>(b);
+  }
+}
+
+template <typename T>
+hipError_t mark_nonzero(nmf_handle* h, const T* X, int64_t rows) {
+  const int blocks = static_cast<int>((rows + 3) / 4);
+  if (blocks == 0) return hipSuccess;
+  if (h->k > 64)
+    hipLaunchKernelGGL((k_mark_nonzero<T, 2>), dim3(blocks), dim3(256), 0, h->stream, X, rows, h->k,
+                       h->mask_words, h->sel.mask);
+  else
+    hipLaunchKernelGGL((k_mark_nonzero<T, 1>), dim3(blocks), dim3(256), 0, h->stream, X, rows, h->k,
+                       h->mask_words, h->sel.mask);
+  return hipGetLastError();
+}
+
+template hipError_t select_topt<float>(nmf_handle*, const float*, int64_t, int64_t, int, const Factor&);
+template hipError_t select_topt<double>(nmf_handle*, const double*, int64_t, int64_t, int, const Factor&);
+template hipError_t mark_nonzero<float>(nmf_handle*, const float*, int64_t);
+template hipError_t mark_nonzero<double>(nmf_handle*, const double*, int64_t);
+
+}  // namespace nmfk

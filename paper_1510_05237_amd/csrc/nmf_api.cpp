@@ -1,0 +1,749 @@
+// Host side of the C ABI (include/nmf.h): argument validation, the workspace
+// plan, the one-time set-up of A (CSR copy, transposed copy, SpMM work plans),
+// and the launch sequence of every ALS iteration.  All device work is done by
+// the kernels in k_*.hip; nothing here computes the factorization.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nmf_internal.h"
+
+using namespace nmfk;
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+nmf_status fail(nmf_handle* h, nmf_status st, const std::string& msg) {
+  if (h)
+    h->last_error = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+#define HIPCHK(h, expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((h), NMF_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_device_ptr(const void* p) {
+  if (p == nullptr) return false;
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  const hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+         attr.type == hipMemoryTypeUnified;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Sequential carve-up of the workspace; the same walk sizes it (base == 0).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(char* b) : base(b) {}
+  template <typename P>
+  P* take(size_t count) {
+    off = align_up(off, 256);
+    P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+    off += count * sizeof(P);
+    return p;
+  }
+};
+
+struct PlanSizes {
+  int64_t items, heavy, parts;
+};
+
+PlanSizes plan_bounds(int64_t rows, int64_t nnz) {
+  const int64_t chunks = (nnz + kChunk - 1) / kChunk;
+  return PlanSizes{rows + 2 * chunks + 1, chunks + 1, 2 * chunks + 1};
+}
+
+struct HostPlan {
+  std::vector<WorkItem> items;
+  std::vector<int32_t> nchunks, part0;
+  int32_t parts = 0;
+};
+
+// Work items for one orientation: groups of up to kRowGroup consecutive
+// short rows (total at most kChunk nonzeros), and kChunk-long pieces of
+// every longer row.
+HostPlan build_plan(const int64_t* rp, int64_t rows, int max_rows) {
+  HostPlan p;
+  int64_t r = 0;
+  while (r < rows) {
+    const int64_t len = rp[r + 1] - rp[r];
+    if (len > kChunk) {
+      const int32_t nch = static_cast<int32_t>((len + kChunk - 1) / kChunk);
+      const int32_t hidx = static_cast<int32_t>(p.nchunks.size());
+      p.nchunks.push_back(nch);
+      p.part0.push_back(p.parts);
+      for (int32_t j = 0; j < nch; ++j) {
+        WorkItem w;
+        w.r0 = static_cast<int32_t>(r);
+        w.r1 = static_cast<int32_t>(r + 1);
+        w.p0 = rp[r] + static_cast<int64_t>(j) * kChunk;
+        w.p1 = std::min(rp[r + 1], w.p0 + kChunk);
+        w.heavy = hidx;
+        w.part = p.parts + j;
+        p.items.push_back(w);
+      }
+      p.parts += nch;
+      ++r;
+      continue;
+    }
+    const int64_t start = r;
+    int64_t total = 0;
+    while (r < rows && r - start < max_rows) {
+      const int64_t l = rp[r + 1] - rp[r];
+      if (l > kChunk || (r > start && total + l > kChunk)) break;
+      total += l;
+      ++r;
+    }
+    WorkItem w;
+    w.r0 = static_cast<int32_t>(start);
+    w.r1 = static_cast<int32_t>(r);
+    w.p0 = w.p1 = 0;
+    w.heavy = -1;
+    w.part = -1;
+    p.items.push_back(w);
+  }
+  return p;
+}
+
+struct Layout {
+  size_t bytes = 0;
+};
+
+// Assign every device buffer of a handle (h may be a dummy when sizing).
+size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const PlanSizes& pa,
+             const PlanSizes& pt) {
+  Carver cv(base);
+  const int64_t n = c.n, m = c.m;
+  const int k = c.k;
+  const size_t elt = c.dtype == NMF_F64 ? 8 : 4;
+  const size_t cand = c.dtype == NMF_F64 ? 16 : 8;
+  const int64_t rmax = std::max(n, m);
+  const int mw = (k + 31) / 32;
+  // A and its transpose
+  h->planA.rows = n;
+  h->planA.rowptr = cv.take<int64_t>(n + 1);
+  h->planA.col = cv.take<int32_t>(nnz);
+  h->planA.val = cv.take<char>(nnz * elt);
+  h->planAt.rows = m;
+  h->planAt.rowptr = cv.take<int64_t>(m + 1);
+  h->planAt.col = cv.take<int32_t>(nnz);
+  h->planAt.val = cv.take<char>(nnz * elt);
+  for (int o = 0; o < 2; ++o) {
+    Plan& p = o == 0 ? h->planA : h->planAt;
+    const PlanSizes& s = o == 0 ? pa : pt;
+    p.items = cv.take<WorkItem>(s.items);
+    p.heavy_ticket = cv.take<int32_t>(s.heavy);
+    p.heavy_nchunks = cv.take<int32_t>(s.heavy);
+    p.heavy_part0 = cv.take<int32_t>(s.heavy);
+    p.partials = cv.take<char>(s.parts * k * elt);
+  }
+  auto factor = [&](Factor& f, int64_t rows) {
+    f.rows = rows;
+    f.row_ptr = cv.take<int32_t>(rows + 1);
+    f.topic = cv.take<uint8_t>(rows * k);
+    f.val = cv.take<char>(rows * k * elt);
+    f.slot = cv.take<int32_t>(rows);
+    f.rowid = cv.take<int32_t>(rows);
+    f.dense = cv.take<char>(rows * k * elt);
+    f.counts = cv.take<int32_t>(4);
+  };
+  factor(h->U[0], n);
+  factor(h->U[1], n);
+  factor(h->V, m);
+  h->vpre = cv.take<char>(m * k * elt);
+  h->upre = cv.take<char>(n * k * elt);
+  h->cbuf = cv.take<char>(n * k * elt);
+  h->lossB = cv.take<char>(m * k * elt);
+  h->lossC = cv.take<char>(n * k * elt);
+  h->sel.hist = cv.take<uint32_t>(static_cast<size_t>(k) * kBins);
+  h->sel.sel = cv.take<ColSel>(k);
+  h->sel.cand_cnt = cv.take<int32_t>(static_cast<size_t>(k) * kCntStride);
+  h->sel.cand_stride = rmax;
+  h->sel.candA = cv.take<char>(static_cast<size_t>(k) * rmax * cand);
+  h->sel.candB = cv.take<char>(static_cast<size_t>(k) * rmax * cand);
+  h->sel.mask = cv.take<uint32_t>(rmax * mw);
+  h->sel.ticket = cv.take<int32_t>(16);
+  h->sel.scan_part = cv.take<int32_t>(2 * ((rmax + 255) / 256 + 1));
+  h->gram_partials = cv.take<char>(static_cast<size_t>(kGramBlocks) * k * (k + 1) / 2 * elt);
+  h->gram_ticket = cv.take<int32_t>(4);
+  h->gU.G = cv.take<double>(static_cast<size_t>(k) * k);
+  h->gU.W = cv.take<double>(static_cast<size_t>(k) * k);
+  h->gU.dead = cv.take<int32_t>(4);
+  h->gV.G = cv.take<double>(static_cast<size_t>(k) * k);
+  h->gV.W = cv.take<double>(static_cast<size_t>(k) * k);
+  h->gV.dead = cv.take<int32_t>(4);
+  h->lossG = cv.take<double>(2 * static_cast<size_t>(k) * k);
+  h->met.partials = cv.take<double>(kMetricBlocks * 4);
+  h->met.ticket = cv.take<int32_t>(4);
+  h->met.ring = cv.take<double>(static_cast<size_t>(kHistRing) * H_FIELDS);
+  h->met.it = cv.take<int64_t>(1);
+  h->met.max_nnz = cv.take<int64_t>(1);
+  h->met.nA2 = cv.take<double>(1);
+  h->met.loss_parts = cv.take<double>(kMetricBlocks);
+  h->met.out = cv.take<double>(4);
+  h->status = cv.take<int32_t>(4);
+  h->scratch_i = cv.take<int32_t>(4);
+  return align_up(cv.off, 256);
+}
+
+nmf_status check_config(const nmf_config* c) {
+  if (c == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "config is NULL");
+  if (c->n < 1 || c->m < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "n and m must be >= 1");
+  if (c->n >= (int64_t(1) << 31) || c->m >= (int64_t(1) << 31))
+    return fail(nullptr, NMF_ERR_UNSUPPORTED, "n and m must be below 2^31");
+  if (c->k < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "k must be >= 1");
+  if (c->k > kMaxK) return fail(nullptr, NMF_ERR_UNSUPPORTED, "k must be <= 128");
+  if (c->k > c->n || c->k > c->m) return fail(nullptr, NMF_ERR_INVALID_ARG, "k must be <= min(n, m)");
+  if (c->t_u < 1 || c->t_v < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "t_u and t_v must be >= 1");
+  if (c->mode != NMF_MODE_COLUMN && c->mode != NMF_MODE_NONE)
+    return fail(nullptr, NMF_ERR_UNSUPPORTED, "mode not supported");
+  if (c->dtype != NMF_F32 && c->dtype != NMF_F64) return fail(nullptr, NMF_ERR_UNSUPPORTED, "dtype");
+  if (c->n * static_cast<int64_t>(c->k) >= (int64_t(1) << 31) ||
+      c->m * static_cast<int64_t>(c->k) >= (int64_t(1) << 31))
+    return fail(nullptr, NMF_ERR_UNSUPPORTED, "rows * k must be below 2^31");
+  return NMF_OK;
+}
+
+template <typename T>
+bool values_ok(const T* v, int64_t count, bool* any_pos) {
+  bool pos = false;
+  for (int64_t i = 0; i < count; ++i) {
+    const T x = v[i];
+    if (!(x >= T(0)) || !std::isfinite(x)) return false;
+    if (x > T(0)) pos = true;
+  }
+  if (any_pos) *any_pos = pos;
+  return true;
+}
+
+// host <- or -> device copy on the handle's stream, then wait
+nmf_status copy_sync(nmf_handle* h, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return NMF_OK;
+  HIPCHK(h, hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return NMF_OK;
+}
+
+nmf_status sync_status(nmf_handle* h) {
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int32_t st = 0;
+  HIPCHK(h, hipMemcpy(&st, h->status, sizeof(st), hipMemcpyDeviceToHost));
+  if (st == NMF_ERR_NOT_SPD) return fail(h, NMF_ERR_NOT_SPD, "Gram matrix is not positive definite");
+  if (st == NMF_ERR_NONFINITE) return fail(h, NMF_ERR_NONFINITE, "non-finite value (e.g. ||U|| = 0)");
+  if (st != 0) return fail(h, static_cast<nmf_status>(st), "device error");
+  return NMF_OK;
+}
+
+// Load a dense rows x k factor (host or device) into a stored factor.
+template <typename T>
+nmf_status load_factor(nmf_handle* h, const void* src, Factor& f) {
+  const size_t bytes = static_cast<size_t>(f.rows) * h->k * sizeof(T);
+  T* stage = static_cast<T*>(h->sel.candB);
+  if (!is_device_ptr(src)) {
+    if (!values_ok(static_cast<const T*>(src), f.rows * h->k, nullptr))
+      return fail(h, NMF_ERR_INVALID_INPUT, "factor has a negative or non-finite value");
+    nmf_status s = copy_sync(h, stage, src, bytes);
+    if (s != NMF_OK) return s;
+  } else {
+    HIPCHK(h, hipMemcpyAsync(stage, src, bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->scratch_i, 0, sizeof(int32_t), h->stream));
+    HIPCHK(h, check_input<T>(h, stage, f.rows * h->k, h->scratch_i));
+    int32_t flag = 0;
+    HIPCHK(h, hipMemcpyAsync(&flag, h->scratch_i, sizeof(flag), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (flag) return fail(h, NMF_ERR_INVALID_INPUT, "factor has a negative or non-finite value");
+  }
+  HIPCHK(h, mark_nonzero<T>(h, stage, f.rows));
+  HIPCHK(h, repack<T>(h, stage, f.rows, f));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status refresh_max(nmf_handle* h) {
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int32_t cu[4] = {0}, cv[4] = {0};
+  HIPCHK(h, hipMemcpy(cu, h->U[h->cur_u].counts, sizeof(cu), hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(cv, h->V.counts, sizeof(cv), hipMemcpyDeviceToHost));
+  int64_t cur = static_cast<int64_t>(cu[0]) + (h->have_v ? cv[0] : 0);
+  int64_t old = 0;
+  HIPCHK(h, hipMemcpy(&old, h->met.max_nnz, sizeof(old), hipMemcpyDeviceToHost));
+  if (cur > old) HIPCHK(h, hipMemcpy(h->met.max_nnz, &cur, sizeof(cur), hipMemcpyHostToDevice));
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status v_half(nmf_handle* h) {
+  Factor& U = h->U[h->cur_u];
+  T* vpre = static_cast<T*>(h->vpre);
+  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr));
+  HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
+  HIPCHK(h, repack<T>(h, vpre, h->m, h->V));
+  HIPCHK(h, gram<T>(h, h->V, h->gV));
+  h->have_v = true;
+  h->have_pre_v = true;
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status u_half(nmf_handle* h, bool keep_c) {
+  const int nxt = 1 - h->cur_u;
+  Factor& Un = h->U[nxt];
+  T* upre = static_cast<T*>(h->upre);
+  HIPCHK(h, spmm<T>(h, h->planA, h->V, h->gV.W, upre, keep_c ? static_cast<T*>(h->cbuf) : nullptr,
+                    false, nullptr));
+  HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
+  HIPCHK(h, repack<T>(h, upre, h->n, Un));
+  HIPCHK(h, gram<T>(h, Un, h->gU));
+  h->have_pre_u = true;
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status do_steps(nmf_handle* h, int32_t iters) {
+  const bool rec = !(h->cfg.flags & NMF_FLAG_NO_METRICS);
+  for (int32_t i = 0; i < iters; ++i) {
+    nmf_status s = v_half<T>(h);
+    if (s != NMF_OK) return s;
+    s = u_half<T>(h, rec);
+    if (s != NMF_OK) return s;
+    const int nxt = 1 - h->cur_u;
+    HIPCHK(h, metrics<T>(h, h->U[nxt], h->U[h->cur_u], rec ? static_cast<T*>(h->cbuf) : nullptr, rec));
+    h->cur_u = nxt;
+    ++h->iters_done;
+    h->metrics_valid = rec;
+  }
+  return NMF_OK;
+}
+
+template <typename T>
+nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in, const void* val_in,
+                     const void* u0, const void* v0) {
+  const int64_t n = h->n, m = h->m, nnz = h->nnz;
+  // A on the host for validation, the transpose and the work plans
+  std::vector<int64_t> rp_h;
+  std::vector<int32_t> col_h;
+  std::vector<T> val_h;
+  const int64_t* rp = rp_in;
+  const int32_t* col = col_in;
+  const T* val = static_cast<const T*>(val_in);
+  if (is_device_ptr(rp_in)) {
+    rp_h.resize(n + 1);
+    HIPCHK(h, hipMemcpy(rp_h.data(), rp_in, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    rp = rp_h.data();
+  }
+  if (rp[0] != 0 || rp[n] != nnz) return fail(h, NMF_ERR_INVALID_ARG, "row pointer must start at 0 and end at nnz");
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return fail(h, NMF_ERR_INVALID_ARG, "row pointer decreases");
+  if (nnz > 0 && is_device_ptr(col_in)) {
+    col_h.resize(nnz);
+    HIPCHK(h, hipMemcpy(col_h.data(), col_in, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    col = col_h.data();
+  }
+  if (nnz > 0 && is_device_ptr(val_in)) {
+    val_h.resize(nnz);
+    HIPCHK(h, hipMemcpy(val_h.data(), val_in, nnz * sizeof(T), hipMemcpyDeviceToHost));
+    val = val_h.data();
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      const int32_t j = col[p];
+      if (j < 0 || j >= m) return fail(h, NMF_ERR_INVALID_ARG, "column index out of range");
+      if (p > rp[i] && j <= col[p - 1]) return fail(h, NMF_ERR_INVALID_ARG, "column indices not strictly increasing in a row");
+    }
+  }
+  bool any_pos = false;
+  if (!values_ok(val, nnz, &any_pos)) return fail(h, NMF_ERR_INVALID_INPUT, "A has a negative or non-finite value");
+  if (!any_pos) return fail(h, NMF_ERR_INVALID_INPUT, "||A|| = 0");
+  // transpose (stable counting sort: rows ascending within each column)
+  std::vector<int64_t> cp(m + 1, 0);
+  for (int64_t p = 0; p < nnz; ++p) ++cp[col[p] + 1];
+  for (int64_t j = 0; j < m; ++j) cp[j + 1] += cp[j];
+  std::vector<int32_t> crow(nnz);
+  std::vector<T> cval(nnz);
+  {
+    std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+        const int64_t q = cur[col[p]]++;
+        crow[q] = static_cast<int32_t>(i);
+        cval[q] = val[p];
+      }
+  }
+  // rows per light item = the epilogue row group of the SpMM instantiation
+  const int group = spmm_row_group(h->k);
+  HostPlan pa = build_plan(rp, n, group);
+  HostPlan pt = build_plan(cp.data(), m, group);
+  const PlanSizes ba = plan_bounds(n, nnz), bt = plan_bounds(m, nnz);
+  if (static_cast<int64_t>(pa.items.size()) > ba.items || static_cast<int64_t>(pt.items.size()) > bt.items ||
+      pa.parts > ba.parts || pt.parts > bt.parts)
+    return fail(h, NMF_ERR_WORKSPACE, "internal: work plan exceeds its bound");
+  auto upload_plan = [&](Plan& p, const HostPlan& hp) -> nmf_status {
+    p.n_items = static_cast<int32_t>(hp.items.size());
+    p.n_heavy = static_cast<int32_t>(hp.nchunks.size());
+    p.n_parts = hp.parts;
+    HIPCHK(h, hipMemcpy(p.items, hp.items.data(), hp.items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    if (!hp.nchunks.empty()) {
+      HIPCHK(h, hipMemcpy(p.heavy_nchunks, hp.nchunks.data(), hp.nchunks.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemcpy(p.heavy_part0, hp.part0.data(), hp.part0.size() * 4, hipMemcpyHostToDevice));
+      HIPCHK(h, hipMemset(p.heavy_ticket, 0, hp.nchunks.size() * 4));
+    }
+    return NMF_OK;
+  };
+  nmf_status s;
+  if ((s = upload_plan(h->planA, pa)) != NMF_OK) return s;
+  if ((s = upload_plan(h->planAt, pt)) != NMF_OK) return s;
+  HIPCHK(h, hipMemcpy(h->planA.rowptr, rp, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planA.col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planA.val, val, nnz * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.rowptr, cp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz * sizeof(T), hipMemcpyHostToDevice));
+  // state that must start at zero
+  const int k = h->k;
+  HIPCHK(h, hipMemset(h->sel.hist, 0, static_cast<size_t>(k) * kBins * 4));
+  HIPCHK(h, hipMemset(h->sel.cand_cnt, 0, static_cast<size_t>(k) * kCntStride * 4));
+  HIPCHK(h, hipMemset(h->sel.mask, 0, static_cast<size_t>(std::max(n, m)) * h->mask_words * 4));
+  HIPCHK(h, hipMemset(h->sel.ticket, 0, 16 * 4));
+  HIPCHK(h, hipMemset(h->gram_ticket, 0, 16));
+  HIPCHK(h, hipMemset(h->met.ticket, 0, 16));
+  HIPCHK(h, hipMemset(h->met.it, 0, 8));
+  HIPCHK(h, hipMemset(h->met.max_nnz, 0, 8));
+  HIPCHK(h, hipMemset(h->status, 0, 16));
+  HIPCHK(h, hipMemset(h->gU.dead, 0, 16));
+  HIPCHK(h, hipMemset(h->gV.dead, 0, 16));
+  for (int f = 0; f < 3; ++f) {
+    Factor& F = f < 2 ? h->U[f] : h->V;
+    HIPCHK(h, hipMemset(F.counts, 0, 16));
+  }
+  HIPCHK(h, sum_squares<T>(h, static_cast<const T*>(h->planA.val), nnz, h->met.nA2));
+  // initial factors
+  if ((s = load_factor<T>(h, u0, h->U[0])) != NMF_OK) return s;
+  if ((s = load_factor<T>(h, u0, h->U[1])) != NMF_OK) return s;
+  h->cur_u = 0;
+  if (v0 != nullptr) {
+    if ((s = load_factor<T>(h, v0, h->V)) != NMF_OK) return s;
+    h->have_v = true;
+    HIPCHK(h, gram<T>(h, h->V, h->gV));
+  }
+  HIPCHK(h, gram<T>(h, h->U[0], h->gU));
+  if ((s = refresh_max<T>(h)) != NMF_OK) return s;
+  return sync_status(h);
+}
+
+template <typename T>
+nmf_status do_error(nmf_handle* h, double* E) {
+  if (!h->have_v) return fail(h, NMF_ERR_STATE, "no V yet: take a step or pass v0");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  if (h->metrics_valid && h->iters_done > 0) {
+    int64_t it = 0;
+    HIPCHK(h, hipMemcpy(&it, h->met.it, 8, hipMemcpyDeviceToHost));
+    double rec[H_FIELDS];
+    HIPCHK(h, hipMemcpy(rec, h->met.ring + ((it - 1) % kHistRing) * H_FIELDS, sizeof(rec), hipMemcpyDeviceToHost));
+    *E = rec[H_E];
+    return NMF_OK;
+  }
+  // on demand: C = A V (raw), then ||A||^2 - 2 <U, C> + <G_U, G_V>
+  T* C = static_cast<T*>(h->cbuf);
+  HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr));
+  HIPCHK(h, densify<T>(h, h->U[h->cur_u], static_cast<T*>(h->lossC)));
+  HIPCHK(h, loss_dot<T>(h, static_cast<const T*>(h->lossC), C, h->gU.G, h->gV.G, h->met.out));
+  s = sync_status(h);
+  if (s != NMF_OK) return s;
+  double L = 0, nA2 = 0;
+  HIPCHK(h, hipMemcpy(&L, h->met.out, 8, hipMemcpyDeviceToHost));
+  HIPCHK(h, hipMemcpy(&nA2, h->met.nA2, 8, hipMemcpyDeviceToHost));
+  *E = std::sqrt(L > 0 ? L : 0.0) / std::sqrt(nA2);
+  return NMF_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+nmf_status nmf_workspace_size(const nmf_config* cfg, int64_t nnz, size_t* bytes) {
+  nmf_status s = check_config(cfg);
+  if (s != NMF_OK) return s;
+  if (nnz < 0 || bytes == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "nnz < 0 or bytes NULL");
+  nmf_handle dummy;
+  dummy.cfg = *cfg;
+  *bytes = carve(&dummy, nullptr, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
+  return NMF_OK;
+}
+
+nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col,
+                      const void* a_val, int64_t nnz, const void* u0, const void* v0,
+                      void* workspace, size_t ws_bytes, void* hip_stream, nmf_handle** out) {
+  if (out == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  nmf_status s = check_config(cfg);
+  if (s != NMF_OK) return s;
+  if (a_rowptr == nullptr || (nnz > 0 && (a_col == nullptr || a_val == nullptr)) || u0 == nullptr)
+    return fail(nullptr, NMF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if (nnz < 1) return fail(nullptr, NMF_ERR_INVALID_INPUT, "||A|| = 0 (no nonzeros)");
+  if (nnz >= (int64_t(1) << 40)) return fail(nullptr, NMF_ERR_UNSUPPORTED, "nnz too large");
+  size_t need = 0;
+  nmf_workspace_size(cfg, nnz, &need);
+  if (workspace == nullptr || ws_bytes < need)
+    return fail(nullptr, NMF_ERR_WORKSPACE, "workspace smaller than nmf_workspace_size()");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(nullptr, NMF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!is_device_ptr(workspace)) return fail(nullptr, NMF_ERR_WORKSPACE, "workspace must be device memory");
+  nmf_handle* h = new (std::nothrow) nmf_handle();
+  if (h == nullptr) return fail(nullptr, NMF_ERR_DEVICE, "out of host memory");
+  h->cfg = *cfg;
+  h->n = cfg->n;
+  h->m = cfg->m;
+  h->k = cfg->k;
+  h->nnz = nnz;
+  h->elt = cfg->dtype == NMF_F64 ? 8 : 4;
+  h->mask_words = (cfg->k + 31) / 32;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(workspace);
+  h->ws_bytes = ws_bytes;
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, NMF_ERR_DEVICE, "no HIP device");
+  }
+  carve(h, h->ws, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
+  s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)
+                  : do_create<float>(h, a_rowptr, a_col, a_val, u0, v0);
+  if (s != NMF_OK) {
+    g_create_error = h->last_error;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return NMF_OK;
+}
+
+nmf_status nmf_als_step(nmf_handle* h, int32_t iters) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  if (iters < 0) return fail(h, NMF_ERR_INVALID_ARG, "iters < 0");
+  return h->elt == 8 ? do_steps<double>(h, iters) : do_steps<float>(h, iters);
+}
+
+nmf_status nmf_half_step(nmf_handle* h, int32_t which) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  if (which != 0 && which != 1) return fail(h, NMF_ERR_INVALID_ARG, "which must be 0 or 1");
+  if (which == 1 && !h->have_v) return fail(h, NMF_ERR_STATE, "no V yet");
+  nmf_status s;
+  if (which == 0) {
+    s = h->elt == 8 ? v_half<double>(h) : v_half<float>(h);
+  } else {
+    s = h->elt == 8 ? u_half<double>(h, false) : u_half<float>(h, false);
+    if (s == NMF_OK) h->cur_u = 1 - h->cur_u;
+  }
+  h->metrics_valid = false;
+  return s;
+}
+
+nmf_status nmf_error(nmf_handle* h, double* E) {
+  if (h == nullptr || E == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  return h->elt == 8 ? do_error<double>(h, E) : do_error<float>(h, E);
+}
+
+nmf_status nmf_residual(nmf_handle* h, double* R) {
+  if (h == nullptr || R == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  if (h->iters_done == 0) return fail(h, NMF_ERR_STATE, "no iteration completed");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  int64_t it = 0;
+  HIPCHK(h, hipMemcpy(&it, h->met.it, 8, hipMemcpyDeviceToHost));
+  if (it == 0) return fail(h, NMF_ERR_STATE, "no iteration completed");
+  double rec[H_FIELDS];
+  HIPCHK(h, hipMemcpy(rec, h->met.ring + ((it - 1) % kHistRing) * H_FIELDS, sizeof(rec), hipMemcpyDeviceToHost));
+  *R = rec[H_R];
+  return NMF_OK;
+}
+
+nmf_status nmf_history(nmf_handle* h, double* E, double* R, int64_t* nnz_u, int64_t* nnz_v,
+                       int32_t cap, int32_t* len) {
+  if (h == nullptr || len == nullptr || cap < 0) return fail(h, NMF_ERR_INVALID_ARG, "bad argument");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  int64_t it = 0;
+  HIPCHK(h, hipMemcpy(&it, h->met.it, 8, hipMemcpyDeviceToHost));
+  std::vector<double> ring(static_cast<size_t>(kHistRing) * H_FIELDS);
+  HIPCHK(h, hipMemcpy(ring.data(), h->met.ring, ring.size() * 8, hipMemcpyDeviceToHost));
+  int64_t have = std::min<int64_t>(it, kHistRing);
+  int64_t cnt = std::min<int64_t>(have, cap);
+  for (int64_t i = 0; i < cnt; ++i) {
+    const int64_t idx = (it - cnt + i) % kHistRing;
+    const double* r = &ring[idx * H_FIELDS];
+    if (E) E[i] = r[H_E];
+    if (R) R[i] = r[H_R];
+    if (nnz_u) nnz_u[i] = static_cast<int64_t>(r[H_NNZU]);
+    if (nnz_v) nnz_v[i] = static_cast<int64_t>(r[H_NNZV]);
+  }
+  *len = static_cast<int32_t>(cnt);
+  return NMF_OK;
+}
+
+nmf_status nmf_max_nnz(nmf_handle* h, int64_t* max_nnz_uv) {
+  if (h == nullptr || max_nnz_uv == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  HIPCHK(h, hipMemcpy(max_nnz_uv, h->met.max_nnz, 8, hipMemcpyDeviceToHost));
+  return NMF_OK;
+}
+
+nmf_status nmf_get_factors(nmf_handle* h, void* u_dense, void* v_dense) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  for (int f = 0; f < 2; ++f) {
+    void* dst = f == 0 ? u_dense : v_dense;
+    if (dst == nullptr) continue;
+    if (f == 1 && !h->have_v) return fail(h, NMF_ERR_STATE, "no V yet");
+    Factor& F = f == 0 ? h->U[h->cur_u] : h->V;
+    const size_t bytes = static_cast<size_t>(F.rows) * h->k * h->elt;
+    void* stage = is_device_ptr(dst) ? dst : h->sel.candB;
+    if (h->elt == 8)
+      HIPCHK(h, densify<double>(h, F, static_cast<double*>(stage)));
+    else
+      HIPCHK(h, densify<float>(h, F, static_cast<float*>(stage)));
+    if (stage != dst) {
+      s = copy_sync(h, dst, stage, bytes);
+      if (s != NMF_OK) return s;
+    }
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return NMF_OK;
+}
+
+nmf_status nmf_get_sparse(nmf_handle* h, int32_t which, int32_t* row_ptr, uint8_t* topic, void* val,
+                          int64_t* nnz) {
+  if (h == nullptr || nnz == nullptr || (which != 0 && which != 1))
+    return fail(h, NMF_ERR_INVALID_ARG, "bad argument");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  if (which == 1 && !h->have_v) return fail(h, NMF_ERR_STATE, "no V yet");
+  Factor& F = which == 0 ? h->U[h->cur_u] : h->V;
+  int32_t counts[4];
+  HIPCHK(h, hipMemcpy(counts, F.counts, sizeof(counts), hipMemcpyDeviceToHost));
+  *nnz = counts[0];
+  if (row_ptr && (s = copy_sync(h, row_ptr, F.row_ptr, (F.rows + 1) * 4)) != NMF_OK) return s;
+  if (topic && (s = copy_sync(h, topic, F.topic, counts[0])) != NMF_OK) return s;
+  if (val && (s = copy_sync(h, val, F.val, static_cast<size_t>(counts[0]) * h->elt)) != NMF_OK) return s;
+  return NMF_OK;
+}
+
+nmf_status nmf_set_factors(nmf_handle* h, const void* u, const void* u_prev, const void* v) {
+  if (h == nullptr || u == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "handle or u is NULL");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  const bool f64 = h->elt == 8;
+  const int prev = 1 - h->cur_u;
+  s = f64 ? load_factor<double>(h, u_prev ? u_prev : u, h->U[prev]) : load_factor<float>(h, u_prev ? u_prev : u, h->U[prev]);
+  if (s != NMF_OK) return s;
+  s = f64 ? load_factor<double>(h, u, h->U[h->cur_u]) : load_factor<float>(h, u, h->U[h->cur_u]);
+  if (s != NMF_OK) return s;
+  if (v != nullptr) {
+    s = f64 ? load_factor<double>(h, v, h->V) : load_factor<float>(h, v, h->V);
+    if (s != NMF_OK) return s;
+    h->have_v = true;
+    HIPCHK(h, f64 ? gram<double>(h, h->V, h->gV) : gram<float>(h, h->V, h->gV));
+  }
+  HIPCHK(h, f64 ? gram<double>(h, h->U[h->cur_u], h->gU) : gram<float>(h, h->U[h->cur_u], h->gU));
+  h->metrics_valid = false;
+  return sync_status(h);
+}
+
+nmf_status nmf_get_pre(nmf_handle* h, int32_t which, void* dst) {
+  if (h == nullptr || dst == nullptr || (which != 0 && which != 1))
+    return fail(h, NMF_ERR_INVALID_ARG, "bad argument");
+  if ((which == 0 && !h->have_pre_v) || (which == 1 && !h->have_pre_u))
+    return fail(h, NMF_ERR_STATE, "no such half-step has run");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  const int64_t rows = which == 0 ? h->m : h->n;
+  return copy_sync(h, dst, which == 0 ? h->vpre : h->upre, static_cast<size_t>(rows) * h->k * h->elt);
+}
+
+nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* loss_dev) {
+  if (h == nullptr || U == nullptr || V == nullptr || loss_dev == nullptr)
+    return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  double* GU = h->lossG;
+  double* GV = h->lossG + static_cast<size_t>(h->k) * h->k;
+  if (h->elt == 8) {
+    HIPCHK(h, spmm<double>(h, h->planA, h->V, nullptr, static_cast<double*>(h->lossC), nullptr, true, static_cast<const double*>(V)));
+    HIPCHK(h, gram_dense<double>(h, static_cast<const double*>(U), h->n, GU));
+    HIPCHK(h, gram_dense<double>(h, static_cast<const double*>(V), h->m, GV));
+    HIPCHK(h, loss_dot<double>(h, static_cast<const double*>(U), static_cast<const double*>(h->lossC), GU, GV, loss_dev));
+  } else {
+    HIPCHK(h, spmm<float>(h, h->planA, h->V, nullptr, static_cast<float*>(h->lossC), nullptr, true, static_cast<const float*>(V)));
+    HIPCHK(h, gram_dense<float>(h, static_cast<const float*>(U), h->n, GU));
+    HIPCHK(h, gram_dense<float>(h, static_cast<const float*>(V), h->m, GV));
+    HIPCHK(h, loss_dot<float>(h, static_cast<const float*>(U), static_cast<const float*>(h->lossC), GU, GV, loss_dev));
+  }
+  return NMF_OK;
+}
+
+nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const double* g_scale, void* gU,
+                        void* gV) {
+  if (h == nullptr || U == nullptr || V == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  double* GU = h->lossG;
+  double* GV = h->lossG + static_cast<size_t>(h->k) * h->k;
+  if (h->elt == 8) {
+    using T = double;
+    if (gU) {
+      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, static_cast<T*>(h->lossC), nullptr, true, static_cast<const T*>(V)));
+      HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(V), h->m, GV));
+      HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(U), static_cast<const T*>(h->lossC), GV, g_scale, h->n, static_cast<T*>(gU)));
+    }
+    if (gV) {
+      HIPCHK(h, spmm<T>(h, h->planAt, h->U[0], nullptr, static_cast<T*>(h->lossB), nullptr, true, static_cast<const T*>(U)));
+      HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(U), h->n, GU));
+      HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(V), static_cast<const T*>(h->lossB), GU, g_scale, h->m, static_cast<T*>(gV)));
+    }
+  } else {
+    using T = float;
+    if (gU) {
+      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, static_cast<T*>(h->lossC), nullptr, true, static_cast<const T*>(V)));
+      HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(V), h->m, GV));
+      HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(U), static_cast<const T*>(h->lossC), GV, g_scale, h->n, static_cast<T*>(gU)));
+    }
+    if (gV) {
+      HIPCHK(h, spmm<T>(h, h->planAt, h->U[0], nullptr, static_cast<T*>(h->lossB), nullptr, true, static_cast<const T*>(U)));
+      HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(U), h->n, GU));
+      HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(V), static_cast<const T*>(h->lossB), GU, g_scale, h->m, static_cast<T*>(gV)));
+    }
+  }
+  return NMF_OK;
+}
+
+const char* nmf_last_error(const nmf_handle* h) {
+  return h ? h->last_error.c_str() : g_create_error.c_str();
+}
+
+void nmf_destroy(nmf_handle* h) {
+  if (h == nullptr) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+}  // extern "C"

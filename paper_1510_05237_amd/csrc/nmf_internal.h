@@ -1,0 +1,188 @@
+// Internal declarations shared by the host library (nmf_api.cpp) and the HIP
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/nmf.h"
+
+namespace nmfk {
+
+constexpr int kMaxK = 128;       // topics supported (2 per lane at most)
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kChunk = 4096;     // nonzeros per SpMM work item; longer rows are split
+constexpr int kRowGroup = 8;     // rows per light SpMM work item when k <= 64
+
+// Rows one SpMM epilogue batch holds (and so the most rows a light work item
+// may carry): 8 with one topic per lane, 4 with two topics per lane.
+inline int spmm_row_group(int k) { return k > 64 ? kRowGroup / 2 : kRowGroup; }
+constexpr int kBins = 256;       // radix digit width of the top-t select (8 bits)
+constexpr int kSmall = 2048;     // candidates finished by an in-LDS sort
+constexpr int kHistRing = 4096;  // iterations kept in the device history ring
+constexpr int kGramBlocks = 240; // Gram partial blocks (fixed: deterministic sums)
+constexpr int kMetricBlocks = 240;
+constexpr int kCntStride = 32;  // ints between per-column counters (one 128-byte line each)
+
+// History record fields (float64 each).
+enum { H_E = 0, H_R, H_NNZU, H_NNZV, H_DEADU, H_DEADV, H_FIELDS };
+
+// One unit of SpMM work for one wave.
+//  light (heavy < 0): output rows [r0, r1), every row at most kChunk long.
+//  heavy (heavy >= 0): nonzeros [p0, p1) of row r0, one chunk of a long row;
+//    its partial sum goes to partial slot `part`; the last chunk to finish
+//    (ticket) adds the row's partials in chunk order and runs the epilogue.
+struct WorkItem {
+  int32_t r0, r1;
+  int64_t p0, p1;
+  int32_t heavy;
+  int32_t part;
+};
+
+// SpMM plan for one orientation of A (CSR of A: U half; CSR of A^T: V half).
+struct Plan {
+  int64_t rows = 0;
+  int64_t* rowptr = nullptr;  // [rows + 1]
+  int32_t* col = nullptr;     // [nnz]
+  void* val = nullptr;        // [nnz] T
+  WorkItem* items = nullptr;  // [n_items]
+  int32_t n_items = 0;
+  int32_t n_heavy = 0;
+  int32_t n_parts = 0;
+  int32_t* heavy_ticket = nullptr;   // [n_heavy], zero between launches
+  int32_t* heavy_nchunks = nullptr;  // [n_heavy]
+  int32_t* heavy_part0 = nullptr;    // [n_heavy]
+  void* partials = nullptr;          // [n_parts][k] T
+};
+
+// A factor as stored (row-compressed sparse) plus the gather cache the SpMM
+// reads: every nonempty row expanded to a dense k-wide row.
+struct Factor {
+  int64_t rows = 0;
+  int32_t* row_ptr = nullptr;  // [rows + 1]
+  uint8_t* topic = nullptr;    // [rows * k]
+  void* val = nullptr;         // [rows * k] T
+  int32_t* slot = nullptr;     // [rows]: -1 empty, else compact row index
+  int32_t* rowid = nullptr;    // [rows]: compact row index -> row
+  void* dense = nullptr;       // [rows][k] T: compact dense rows 0..R-1
+  int32_t* counts = nullptr;   // device [0] = nnz, [1] = R (nonempty rows)
+};
+
+// Gram matrix of a factor and its inverse.
+struct Gram {
+  double* G = nullptr;  // [k][k] F^T F
+  double* W = nullptr;  // [k][k] inverse of G
+  int32_t* dead = nullptr;  // device: number of dead topics
+};
+
+// Per-column selection state of the top-t select.
+struct ColSel {
+  int32_t b1;    // first digit of the threshold
+  int32_t need;  // entries still to take from the b1 bin
+  int32_t all;   // 1: the column keeps every positive entry
+  int32_t npos;  // positive entries in the column
+};
+
+struct SelectWs {
+  uint32_t* hist = nullptr;     // [k][kBins], zero between uses
+  ColSel* sel = nullptr;        // [k]
+  int32_t* cand_cnt = nullptr;  // [k * kCntStride], zero between uses
+  void* candA = nullptr;        // [k][rows_max] candidates (row, key)
+  void* candB = nullptr;        // [k][rows_max] ping-pong buffer
+  int64_t cand_stride = 0;      // entries per column
+  uint32_t* mask = nullptr;     // [rows_max][mask_words], zero between uses
+  int32_t* ticket = nullptr;    // [4], zero between uses
+  int32_t* scan_part = nullptr; // [2][scan blocks + 1]
+};
+
+struct Metrics {
+  double* partials = nullptr;   // [kMetricBlocks][4]
+  int32_t* ticket = nullptr;    // [1]
+  double* ring = nullptr;       // [kHistRing][H_FIELDS]
+  int64_t* it = nullptr;        // device iteration counter
+  int64_t* max_nnz = nullptr;   // device storage high-water mark
+  double* nA2 = nullptr;        // ||A||_F^2
+  double* loss_parts = nullptr; // [kMetricBlocks]
+  double* out = nullptr;        // [4] scalar results of on-demand queries
+};
+
+}  // namespace nmfk
+
+struct nmf_handle {
+  nmf_config cfg{};
+  int64_t n = 0, m = 0, nnz = 0;
+  int k = 0;
+  size_t elt = 4;  // sizeof(T)
+  int mask_words = 1;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cus = 256;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+
+  nmfk::Plan planA;   // CSR of A: rows = terms (U half)
+  nmfk::Plan planAt;  // CSR of A^T: rows = docs (V half)
+  nmfk::Factor U[2];  // current and previous U
+  int cur_u = 0;
+  nmfk::Factor V;
+  nmfk::Gram gU, gV;
+  void* vpre = nullptr;  // [m][k] T clamped pre-selection V
+  void* upre = nullptr;  // [n][k] T clamped pre-selection U
+  void* cbuf = nullptr;  // [n][k] T raw A V of the last U half
+  void* lossB = nullptr; // [m][k] T scratch of the loss entry points
+  void* lossC = nullptr; // [n][k] T
+  double* lossG = nullptr; // [2][k][k]
+  nmfk::SelectWs sel;
+  void* gram_partials = nullptr;  // [kGramBlocks][k][k] T
+  int32_t* gram_ticket = nullptr;
+  nmfk::Metrics met;
+  int32_t* status = nullptr;      // sticky device status (nmf_status value)
+  int32_t* scratch_i = nullptr;   // small device scratch for host queries
+
+  // host-side state
+  int64_t iters_done = 0;
+  bool have_v = false;
+  bool have_pre_v = false, have_pre_u = false;
+  bool metrics_valid = false;  // the newest history record describes the current U, V
+  std::string last_error;
+};
+
+namespace nmfk {
+
+// Kernel launchers (one translation unit each), instantiated for float and
+// double.  All enqueue on h->stream and return hipSuccess or the launch error.
+template <typename T>
+hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
+                bool raw, const T* dense_in);
+template <typename T>
+hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int mode,
+                       const Factor& out_f);
+template <typename T>
+hipError_t mark_nonzero(nmf_handle* h, const T* X, int64_t rows);
+template <typename T>
+hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f);
+template <typename T>
+hipError_t gram(nmf_handle* h, const Factor& F, const Gram& g);
+template <typename T>
+hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const T* C,
+                   bool record);
+template <typename T>
+hipError_t densify(nmf_handle* h, const Factor& F, T* out);
+template <typename T>
+hipError_t check_input(nmf_handle* h, const T* x, int64_t count, int32_t* flag);
+template <typename T>
+hipError_t sum_squares(nmf_handle* h, const T* x, int64_t count, double* out);
+template <typename T>
+hipError_t loss_dot(nmf_handle* h, const T* U, const T* C, const double* GU, const double* GV,
+                    double* loss_out);
+template <typename T>
+hipError_t gram_dense(nmf_handle* h, const T* F, int64_t rows, double* G);
+template <typename T>
+hipError_t grad_combine(nmf_handle* h, const T* F, const T* B, const double* G,
+                        const double* g_scale, int64_t rows, T* out);
+hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t count);
+
+}  // namespace nmfk

@@ -1,0 +1,375 @@
+"""ctypes binding of the enforced-sparsity NMF C ABI (include/nmf.h).
+
+Argument marshalling only: every step of the factorization runs in the HIP
+kernels of ``libnmf.so``.  PyTorch provides device memory (the workspace,
+caller tensors) and the HIP stream; nothing here computes on the data.
+
+The low-level functions carry the C names (``nmf_create``, ``nmf_als_step``,
+...).  ``NMF`` wraps one handle together with the workspace tensor that
+backs it, and ``NMFLoss`` exposes the squared loss with its hand-written
+gradient to ``torch.autograd``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmf.so")
+
+# status codes
+NMF_OK = 0
+NMF_ERR_INVALID_ARG = -1
+NMF_ERR_INVALID_INPUT = -2
+NMF_ERR_UNSUPPORTED = -3
+NMF_ERR_NOT_SPD = -4
+NMF_ERR_NONFINITE = -5
+NMF_ERR_DEVICE = -6
+NMF_ERR_STATE = -7
+NMF_ERR_WORKSPACE = -8
+
+NMF_MODE_COLUMN = 0
+NMF_MODE_NONE = 1
+NMF_MODE_WHOLE = 2
+NMF_F32 = 0
+NMF_F64 = 1
+NMF_FLAG_NO_METRICS = 1
+
+_STATUS_NAMES = {
+    0: "NMF_OK", -1: "NMF_ERR_INVALID_ARG", -2: "NMF_ERR_INVALID_INPUT", -3: "NMF_ERR_UNSUPPORTED",
+    -4: "NMF_ERR_NOT_SPD", -5: "NMF_ERR_NONFINITE", -6: "NMF_ERR_DEVICE", -7: "NMF_ERR_STATE",
+    -8: "NMF_ERR_WORKSPACE",
+}
+
+
+class NMFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class nmf_config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("m", ctypes.c_int64),
+        ("k", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("t_u", ctypes.c_int64),
+        ("t_v", ctypes.c_int64),
+        ("dtype", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_PD = ctypes.POINTER(ctypes.c_double)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+
+# name -> (restype, argtypes); every function declared in include/nmf.h
+SIGNATURES = {
+    "nmf_workspace_size": (_I32, [ctypes.POINTER(nmf_config), _I64, ctypes.POINTER(ctypes.c_size_t)]),
+    "nmf_create": (_I32, [ctypes.POINTER(nmf_config), _P, _P, _P, _I64, _P, _P, _P, ctypes.c_size_t, _P,
+                          ctypes.POINTER(_P)]),
+    "nmf_als_step": (_I32, [_P, _I32]),
+    "nmf_half_step": (_I32, [_P, _I32]),
+    "nmf_error": (_I32, [_P, _PD]),
+    "nmf_residual": (_I32, [_P, _PD]),
+    "nmf_history": (_I32, [_P, _P, _P, _P, _P, _I32, _PI32]),
+    "nmf_max_nnz": (_I32, [_P, _PI64]),
+    "nmf_get_factors": (_I32, [_P, _P, _P]),
+    "nmf_get_sparse": (_I32, [_P, _I32, _P, _P, _P, _PI64]),
+    "nmf_set_factors": (_I32, [_P, _P, _P, _P]),
+    "nmf_get_pre": (_I32, [_P, _I32, _P]),
+    "nmf_loss_fwd": (_I32, [_P, _P, _P, _P]),
+    "nmf_loss_bwd": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "nmf_last_error": (ctypes.c_char_p, [_P]),
+    "nmf_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnmf.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1510_05237_amd/build.py "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int, handle=None):
+    if st != NMF_OK:
+        msg = load_library().nmf_last_error(handle)
+        raise NMFError(st, msg.decode() if msg else "")
+
+
+def _ptr(x) -> Optional[int]:
+    """Raw address of a torch tensor or numpy array (or None)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("arrays must be C-contiguous")
+        return x.ctypes.data
+    import torch
+
+    if isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"unsupported array type {type(x)}")
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- C names
+
+
+def nmf_workspace_size(cfg: nmf_config, nnz: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().nmf_workspace_size(ctypes.byref(cfg), nnz, ctypes.byref(out)))
+    return out.value
+
+
+def nmf_create(cfg, a_rowptr, a_col, a_val, nnz, u0, v0, workspace, ws_bytes, stream) -> int:
+    h = _P()
+    st = load_library().nmf_create(ctypes.byref(cfg), _ptr(a_rowptr), _ptr(a_col), _ptr(a_val), nnz,
+                                   _ptr(u0), _ptr(v0), _ptr(workspace), ws_bytes, stream, ctypes.byref(h))
+    _check(st, None)
+    return h.value
+
+
+def nmf_als_step(h: int, iters: int):
+    _check(load_library().nmf_als_step(h, iters), h)
+
+
+def nmf_half_step(h: int, which: int):
+    _check(load_library().nmf_half_step(h, which), h)
+
+
+def nmf_error(h: int) -> float:
+    e = ctypes.c_double(0)
+    _check(load_library().nmf_error(h, ctypes.byref(e)), h)
+    return e.value
+
+
+def nmf_residual(h: int) -> float:
+    r = ctypes.c_double(0)
+    _check(load_library().nmf_residual(h, ctypes.byref(r)), h)
+    return r.value
+
+
+def nmf_history(h: int, cap: int = 4096):
+    E = np.zeros(cap, np.float64)
+    R = np.zeros(cap, np.float64)
+    nu = np.zeros(cap, np.int64)
+    nv = np.zeros(cap, np.int64)
+    ln = ctypes.c_int32(0)
+    _check(load_library().nmf_history(h, _ptr(E), _ptr(R), _ptr(nu), _ptr(nv), cap, ctypes.byref(ln)), h)
+    n = ln.value
+    return E[:n], R[:n], nu[:n], nv[:n]
+
+
+def nmf_max_nnz(h: int) -> int:
+    v = ctypes.c_int64(0)
+    _check(load_library().nmf_max_nnz(h, ctypes.byref(v)), h)
+    return v.value
+
+
+def nmf_get_factors(h: int, u_dense, v_dense):
+    _check(load_library().nmf_get_factors(h, _ptr(u_dense), _ptr(v_dense)), h)
+
+
+def nmf_get_sparse(h: int, which: int, row_ptr=None, topic=None, val=None) -> int:
+    nnz = ctypes.c_int64(0)
+    _check(load_library().nmf_get_sparse(h, which, _ptr(row_ptr), _ptr(topic), _ptr(val), ctypes.byref(nnz)), h)
+    return nnz.value
+
+
+def nmf_set_factors(h: int, u, u_prev=None, v=None):
+    _check(load_library().nmf_set_factors(h, _ptr(u), _ptr(u_prev), _ptr(v)), h)
+
+
+def nmf_get_pre(h: int, which: int, dst):
+    _check(load_library().nmf_get_pre(h, which, _ptr(dst)), h)
+
+
+def nmf_loss_fwd(h: int, U, V, loss_dev):
+    _check(load_library().nmf_loss_fwd(h, _ptr(U), _ptr(V), _ptr(loss_dev)), h)
+
+
+def nmf_loss_bwd(h: int, U, V, g_scale, gU, gV):
+    _check(load_library().nmf_loss_bwd(h, _ptr(U), _ptr(V), _ptr(g_scale), _ptr(gU), _ptr(gV)), h)
+
+
+def nmf_last_error(h: Optional[int] = None) -> str:
+    return load_library().nmf_last_error(h).decode()
+
+
+def nmf_destroy(h: int):
+    load_library().nmf_destroy(h)
+
+
+# ---------------------------------------------------------------- handle object
+
+_MODES = {"column": NMF_MODE_COLUMN, "none": NMF_MODE_NONE, "whole": NMF_MODE_WHOLE}
+
+
+class NMF:
+    """One factorization problem on one GPU.
+
+    ``indptr``/``indices``/``data``: A in CSR over term rows (numpy arrays or
+    torch tensors, host or device).  ``u0``: initial U (n x k); ``v0``
+    optional.  ``dtype``: "f32" or "f64" (the type of data/u0/v0).
+    """
+
+    def __init__(self, n, m, indptr, indices, data, u0, *, t_u, t_v, v0=None, mode="column",
+                 dtype="f32", flags=0, device="cuda:0", stream=None):
+        import torch
+
+        load_library()
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.np_dtype = np.float32 if dtype == "f32" else np.float64
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        k = int(u0.shape[1])
+        self.n, self.m, self.k = int(n), int(m), k
+        self.cfg = nmf_config(n=int(n), m=int(m), k=k, mode=_MODES[mode], t_u=int(t_u), t_v=int(t_v),
+                              dtype=NMF_F32 if dtype == "f32" else NMF_F64, flags=int(flags))
+        nnz = int(indptr[-1])
+        self.nnz = nnz
+        with torch.cuda.device(self.device):
+            self.ws_bytes = nmf_workspace_size(self.cfg, nnz)
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.h = nmf_create(self.cfg, indptr, indices, data, nnz, u0, v0, self.workspace,
+                                self.ws_bytes, self.stream.cuda_stream)
+
+    # -- iteration
+    def step(self, iters: int = 1):
+        nmf_als_step(self.h, iters)
+
+    def half_step(self, which: int):
+        nmf_half_step(self.h, which)
+
+    # -- queries
+    def error(self) -> float:
+        return nmf_error(self.h)
+
+    def residual(self) -> float:
+        return nmf_residual(self.h)
+
+    def history(self, cap: int = 4096):
+        return nmf_history(self.h, cap)
+
+    def max_nnz(self) -> int:
+        return nmf_max_nnz(self.h)
+
+    def factors(self):
+        """Dense (U, V) as float arrays on the host."""
+        U = np.zeros((self.n, self.k), self.np_dtype)
+        V = np.zeros((self.m, self.k), self.np_dtype)
+        nmf_get_factors(self.h, U, V)
+        return U, V
+
+    def factors_device(self):
+        import torch
+
+        U = torch.empty((self.n, self.k), dtype=self.torch_dtype, device=self.device)
+        V = torch.empty((self.m, self.k), dtype=self.torch_dtype, device=self.device)
+        nmf_get_factors(self.h, U, V)
+        return U, V
+
+    def sparse(self, which: int):
+        rows = self.n if which == 0 else self.m
+        nnz = nmf_get_sparse(self.h, which)
+        rp = np.zeros(rows + 1, np.int32)
+        tp = np.zeros(max(nnz, 1), np.uint8)
+        vl = np.zeros(max(nnz, 1), self.np_dtype)
+        nmf_get_sparse(self.h, which, rp, tp, vl)
+        return rp, tp[:nnz], vl[:nnz]
+
+    def pre(self, which: int):
+        rows = self.m if which == 0 else self.n
+        out = np.zeros((rows, self.k), self.np_dtype)
+        nmf_get_pre(self.h, which, out)
+        return out
+
+    def set_factors(self, u, u_prev=None, v=None):
+        nmf_set_factors(self.h, u, u_prev, v)
+
+    def close(self):
+        if getattr(self, "h", None):
+            nmf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class NMFLoss:
+    """``NMFLoss.apply(problem, U, V)`` -> L = ||A - U V^T||_F^2 (float64 scalar
+    tensor) with the hand-written gradient (-2 A V + 2 U V^T V, and the
+    transpose), A being the matrix held by ``problem`` (an ``NMF``)."""
+
+    _fn = None
+
+    @classmethod
+    def _function(cls):
+        if cls._fn is None:
+            import torch
+
+            class _Loss(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, problem, U, V):
+                    U = U.contiguous()
+                    V = V.contiguous()
+                    if U.dtype != problem.torch_dtype or V.dtype != problem.torch_dtype:
+                        raise TypeError("U and V must have the problem's dtype")
+                    out = torch.empty((), dtype=torch.float64, device=U.device)
+                    nmf_loss_fwd(problem.h, U, V, out)
+                    ctx.problem = problem
+                    ctx.save_for_backward(U, V)
+                    return out
+
+                @staticmethod
+                def backward(ctx, g):
+                    U, V = ctx.saved_tensors
+                    problem = ctx.problem
+                    g = g.to(torch.float64).contiguous()
+                    gU = torch.empty_like(U) if ctx.needs_input_grad[1] else None
+                    gV = torch.empty_like(V) if ctx.needs_input_grad[2] else None
+                    nmf_loss_bwd(problem.h, U, V, g, gU, gV)
+                    return None, gU, gV
+
+            cls._fn = _Loss
+        return cls._fn
+
+    @classmethod
+    def apply(cls, problem, U, V):
+        return cls._function().apply(problem, U, V)

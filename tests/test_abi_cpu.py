@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/nmf.h declares, and validates configurations."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1510_05237_amd import nmf as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "nmf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load_library()
+    names = _declared()
+    assert "nmf_create" in names and "nmf_als_step" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding declares the same set
+    assert sorted(B.SIGNATURES) == names
+
+
+def _cfg(**kw):
+    c = dict(n=1000, m=2000, k=10, mode=B.NMF_MODE_COLUMN, t_u=50, t_v=60, dtype=B.NMF_F32, flags=0)
+    c.update(kw)
+    return B.nmf_config(**c)
+
+
+def test_workspace_size_grows_with_problem():
+    a = B.nmf_workspace_size(_cfg(), 20000)
+    b = B.nmf_workspace_size(_cfg(), 40000)
+    c = B.nmf_workspace_size(_cfg(dtype=B.NMF_F64), 20000)
+    assert 0 < a < b and a < c
+    assert a % 256 == 0
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(k=0), B.NMF_ERR_INVALID_ARG),
+    (dict(k=129), B.NMF_ERR_UNSUPPORTED),
+    (dict(k=1001), B.NMF_ERR_UNSUPPORTED),
+    (dict(n=5, m=3, k=4), B.NMF_ERR_INVALID_ARG),
+    (dict(t_u=0), B.NMF_ERR_INVALID_ARG),
+    (dict(t_v=-2), B.NMF_ERR_INVALID_ARG),
+    (dict(mode=7), B.NMF_ERR_UNSUPPORTED),
+    (dict(dtype=3), B.NMF_ERR_UNSUPPORTED),
+    (dict(n=0), B.NMF_ERR_INVALID_ARG),
+])
+def test_config_validation(kw, status):
+    with pytest.raises(B.NMFError) as ei:
+        B.nmf_workspace_size(_cfg(**kw), 100)
+    assert ei.value.status == status
+
+
+def test_create_rejects_null_arguments_without_a_device():
+    lib = B.load_library()
+    cfg = _cfg()
+    h = ctypes.c_void_p()
+    st = lib.nmf_create(ctypes.byref(cfg), None, None, None, 10, None, None, None, 0, None, ctypes.byref(h))
+    assert st == B.NMF_ERR_INVALID_ARG
+    assert h.value is None
+    assert "NULL" in B.nmf_last_error(None)

@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded
+inputs.  Every test prints the case it runs before touching the GPU.
+
+Tolerances: FP64 workloads agree to 1e-9 relative (only summation order
+differs); FP32 workloads to the stated 1e-4 relative (Frobenius) on U, V and
+the error curve, with support mismatches allowed only at near-ties (see
+tests/parity.py).
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from tests.parity import compare_factor, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def _nmf():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_05237_amd import NMF, NMFError
+
+    return NMF, NMFError
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _problem(c, u0, k, t_u, t_v, dtype, **kw):
+    NMF, _ = _nmf()
+    return NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=t_u, t_v=t_v, dtype=dtype, **kw)
+
+
+# ------------------------------------------------------------------ FP64
+
+
+def test_fp64_trajectory_2000x1000():
+    """Full 20-iteration run of the 2000 x 1000 FP64 workload: every iterate
+    and the E / R curves match the oracle."""
+    p = synth.WORKLOADS["plain_f64_2000x1000"]
+    c, u0, v0, p = synth.make_workload("plain_f64_2000x1000")
+    _say(f"fp64 2000x1000 nnz={c.nnz} k={p['k']} 20 iterations")
+    prob = _problem(c, u0, p["k"], p["t_u"], p["t_v"], "f64", v0=v0)
+    A = c.scipy()
+    e0 = prob.error()
+    assert e0 == pytest.approx(oracle.error_direct(A, u0, v0), rel=1e-10)
+    st = None
+    for it in range(p["iters"]):
+        prob.step(1)
+        st = oracle.als(A, u0, p["t_u"], p["t_v"], 1, state=st)
+        U, V = prob.factors()
+        assert rel_fro(U, st.U) < 1e-9, it
+        assert rel_fro(V, st.V) < 1e-9, it
+        np.testing.assert_array_equal(U != 0, st.U != 0)
+        np.testing.assert_array_equal(V != 0, st.V != 0)
+    E, R, nu, nv = prob.history()
+    np.testing.assert_allclose(E, st.E, rtol=1e-9)
+    np.testing.assert_allclose(R, st.R, rtol=1e-8)
+    np.testing.assert_array_equal(nu, st.nnz_u)
+    np.testing.assert_array_equal(nv, st.nnz_v)
+    assert prob.max_nnz() == max(st.max_nnz_uv, int(np.count_nonzero(u0)) + int(np.count_nonzero(v0)))
+    assert prob.error() == pytest.approx(st.E[-1], rel=1e-12)
+    assert prob.residual() == pytest.approx(st.R[-1], rel=1e-12)
+    # the stored sparse form agrees with the dense export
+    rp, tp, vl = prob.sparse(0)
+    S = sp.csr_matrix((vl, tp.astype(np.int64), rp.astype(np.int64)), shape=U.shape).toarray()
+    np.testing.assert_array_equal(S, U)
+    for r in range(U.shape[0]):
+        assert np.all(np.diff(tp[rp[r]:rp[r + 1]].astype(int)) > 0)
+
+
+# ------------------------------------------------------------------ FP32 teacher forced
+
+
+def _teacher_forced(c, u0, k, t_u, t_v, iters, tol=1e-4):
+    A = c.scipy()
+    st = oracle.als(A, u0, t_u, t_v, iters, keep_steps=True)
+    prob = _problem(c, u0, k, t_u, t_v, "f32")
+    report = []
+    for i, s in enumerate(st.steps):
+        prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32))
+        prob.half_step(0)
+        vpre = prob.pre(0)
+        assert rel_fro(vpre, oracle.clamp(s["V_pre"])) <= tol, ("V_pre", i)
+        _, V = prob.factors()
+        dv = compare_factor(V, s["V"], s["V_pre"], tol)
+        prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32), v=np.ascontiguousarray(s["V"], np.float32))
+        prob.half_step(1)
+        upre = prob.pre(1)
+        assert rel_fro(upre, oracle.clamp(s["U_pre"])) <= tol, ("U_pre", i)
+        U, _ = prob.factors()
+        du = compare_factor(U, s["U"], s["U_pre"], tol)
+        report.append((i, dv, du))
+        _say(f"  iter {i}: V rel {dv.rel:.2e} mism {dv.mismatches} (near-tie {dv.near_ties}) | "
+             f"U rel {du.rel:.2e} mism {du.mismatches} (near-tie {du.near_ties})")
+        assert dv.ok(tol) and du.ok(tol), (i, dv, du)
+    prob.close()
+    return report
+
+
+def test_fp32_teacher_forced_small():
+    c = synth.make_corpus(3000, 5000, seed=31, alpha=1.1, per_doc=40, dtype="f32")
+    u0, _ = synth.make_init(3000, 5000, 16, seed=31, dtype="f32")
+    _say(f"fp32 teacher-forced 3000x5000 nnz={c.nnz} k=16")
+    _teacher_forced(c, u0, 16, t_u=80, t_v=120, iters=4)
+
+
+def test_fp32_two_topics_per_lane_k80():
+    c = synth.make_corpus(1500, 2500, seed=32, alpha=1.1, per_doc=50, dtype="f32")
+    u0, _ = synth.make_init(1500, 2500, 80, seed=32, dtype="f32")
+    _say(f"fp32 teacher-forced 1500x2500 nnz={c.nnz} k=80 (two topics per lane)")
+    _teacher_forced(c, u0, 80, t_u=40, t_v=60, iters=2)
+
+
+def test_fp32_heavy_rows_split():
+    """Term rows longer than one work chunk (4096 nonzeros) are split and
+    recombined in chunk order."""
+    c = synth.make_corpus(2000, 12000, seed=33, alpha=1.1, per_doc=30, dtype="f32")
+    lens = np.diff(c.indptr)
+    assert lens.max() > 2 * 4096
+    u0, _ = synth.make_init(2000, 12000, 8, seed=33, dtype="f32")
+    _say(f"fp32 heavy rows 2000x12000 nnz={c.nnz} max row {lens.max()} k=8")
+    _teacher_forced(c, u0, 8, t_u=50, t_v=300, iters=2)
+
+
+def test_fp32_free_running_error_curve():
+    c = synth.make_corpus(3000, 5000, seed=34, alpha=1.1, per_doc=40, dtype="f32")
+    u0, _ = synth.make_init(3000, 5000, 12, seed=34, dtype="f32")
+    _say(f"fp32 free-running 3000x5000 nnz={c.nnz} k=12, 8 iterations")
+    prob = _problem(c, u0, 12, 100, 150, "f32")
+    prob.step(8)
+    E, R, nu, nv = prob.history()
+    st = oracle.als(c.scipy(), u0, 100, 150, 8)
+    _say(f"  E gpu {E[-1]:.6f} oracle {st.E[-1]:.6f}; nnz U {nu[-1]} V {nv[-1]}")
+    np.testing.assert_allclose(E, st.E, rtol=1e-4)
+    np.testing.assert_array_equal(nu, st.nnz_u)
+    np.testing.assert_array_equal(nv, st.nnz_v)
+
+
+# ------------------------------------------------------------------ special cases
+
+
+def test_forced_ties_lowest_row_wins_gpu():
+    """Duplicate documents produce identical rows of V_pre on both sides; the
+    kept supports must agree exactly (lowest document index wins)."""
+    rng = np.random.default_rng(7)
+    n, m_base, k = 300, 200, 4
+    base = sp.random(n, m_base, density=0.05, random_state=rng, format="csc",
+                     data_rvs=lambda s: rng.uniform(0.1, 2.0, s)).toarray()
+    cols = list(range(m_base)) + [5] * 40 + [17] * 40
+    perm = rng.permutation(len(cols))
+    Ad = base[:, [cols[p] for p in perm]]
+    A = sp.csr_matrix(Ad)
+    A.sort_indices()
+    u0 = rng.uniform(0.1, 1.0, (n, k))
+    _say("fp64 forced ties: 80 duplicated documents, t_v=30")
+    NMF, _ = _nmf()
+    prob = NMF(n, A.shape[1], A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64),
+               u0, t_u=40, t_v=30, dtype="f64")
+    prob.half_step(0)
+    _, V = prob.factors()
+    Vo, _ = oracle.half_step(sp.csr_matrix(A.T), u0, 30)
+    np.testing.assert_array_equal(V != 0, Vo != 0)
+    np.testing.assert_allclose(V, Vo, rtol=1e-10, atol=1e-14)
+
+
+def test_dead_topic_gpu():
+    c = synth.make_corpus(500, 400, seed=35, alpha=1.1, nnz=5000, dtype="f64")
+    u0, _ = synth.make_init(500, 400, 5, seed=35, dtype="f64")
+    u0[:, 3] = 0.0
+    _say("fp64 dead topic (zero column of U0)")
+    prob = _problem(c, u0, 5, 30, 20, "f64")
+    prob.step(3)
+    U, V = prob.factors()
+    st = oracle.als(c.scipy(), u0, 30, 20, 3)
+    assert not U[:, 3].any() and not V[:, 3].any()
+    assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9
+
+
+def test_not_spd_surfaces_gpu():
+    """Two equal columns of U0 with exact arithmetic (pivot 9 - 3*3 = 0): the
+    Gram factorisation fails on the device and the synchronizing create call
+    reports NMF_ERR_NOT_SPD."""
+    _, NMFError = _nmf()
+    u = np.array([[2.0, 2.0], [1.0, 1.0], [2.0, 2.0], [0.0, 0.0]])
+    A = sp.csr_matrix(np.ones((4, 3)))
+    _say("fp64 exactly singular Gram -> NMF_ERR_NOT_SPD")
+    c = synth.Corpus(4, 3, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, "f64")
+    with pytest.raises(NMFError) as ei:
+        _problem(c, u, 2, 2, 2, "f64")
+    assert ei.value.status == -4
+
+
+def test_invalid_inputs_gpu():
+    NMF, NMFError = _nmf()
+    c = synth.make_corpus(50, 40, seed=36, alpha=1.1, nnz=300, dtype="f64")
+    u0, _ = synth.make_init(50, 40, 3, seed=36, dtype="f64")
+    _say("input validation: negative value, NaN, unsorted columns, bad row pointer, negative U0")
+    bad = c.data.copy()
+    bad[7] = -1.0
+    with pytest.raises(NMFError) as ei:
+        NMF(50, 40, c.indptr, c.indices, bad, u0, t_u=5, t_v=5, dtype="f64")
+    assert ei.value.status == -2
+    bad[7] = np.nan
+    with pytest.raises(NMFError) as ei:
+        NMF(50, 40, c.indptr, c.indices, bad, u0, t_u=5, t_v=5, dtype="f64")
+    assert ei.value.status == -2
+    idx = c.indices.copy()
+    r = int(np.argmax(np.diff(c.indptr)))
+    idx[c.indptr[r]], idx[c.indptr[r] + 1] = idx[c.indptr[r] + 1], idx[c.indptr[r]]
+    with pytest.raises(NMFError) as ei:
+        NMF(50, 40, c.indptr, idx, c.data, u0, t_u=5, t_v=5, dtype="f64")
+    assert ei.value.status == -1
+    ip = c.indptr.copy()
+    ip[-1] += 1
+    with pytest.raises(NMFError) as ei:
+        NMF(50, 40, ip, c.indices, c.data, u0, t_u=5, t_v=5, dtype="f64")
+    assert ei.value.status == -1
+    un = u0.copy()
+    un[3, 1] = -0.5
+    with pytest.raises(NMFError) as ei:
+        NMF(50, 40, c.indptr, c.indices, c.data, un, t_u=5, t_v=5, dtype="f64")
+    assert ei.value.status == -2
+
+
+def test_determinism_and_resume():
+    c = synth.make_corpus(3000, 5000, seed=37, alpha=1.1, per_doc=40, dtype="f32")
+    u0, _ = synth.make_init(3000, 5000, 16, seed=37, dtype="f32")
+    _say("fp32 determinism (two runs bitwise equal) and resume (3 + 3 == 6)")
+    a = _problem(c, u0, 16, 80, 120, "f32")
+    a.step(6)
+    Ua, Va = a.factors()
+    Ea, Ra, _, _ = a.history()
+    b = _problem(c, u0, 16, 80, 120, "f32")
+    b.step(6)
+    Ub, Vb = b.factors()
+    Eb, Rb, _, _ = b.history()
+    np.testing.assert_array_equal(Ua, Ub)
+    np.testing.assert_array_equal(Va, Vb)
+    np.testing.assert_array_equal(Ea, Eb)
+    np.testing.assert_array_equal(Ra, Rb)
+    r = _problem(c, u0, 16, 80, 120, "f32")
+    r.step(3)
+    U3, V3 = r.factors()
+    s = _problem(c, u0, 16, 80, 120, "f32")
+    s.set_factors(U3, v=V3)
+    s.step(3)
+    Us, Vs = s.factors()
+    np.testing.assert_array_equal(Us, Ua)
+    np.testing.assert_array_equal(Vs, Va)
+
+
+def test_power_of_two_scaling_gpu():
+    """Scaling A by 2^p leaves U and every support bit-identical and scales V
+    by exactly 2^p on the GPU too (rounding commutes with the scaling)."""
+    c = synth.make_corpus(3000, 5000, seed=38, alpha=1.1, per_doc=40, dtype="f32")
+    u0, _ = synth.make_init(3000, 5000, 10, seed=38, dtype="f32")
+    _say("fp32 power-of-two scaling of A")
+    a = _problem(c, u0, 10, 60, 90, "f32")
+    a.step(3)
+    Ua, Va = a.factors()
+    Ea, Ra, _, _ = a.history()
+    c2 = synth.Corpus(c.n, c.m, c.indptr, c.indices, (c.data * np.float32(8.0)).astype(np.float32), "f32")
+    b = _problem(c2, u0, 10, 60, 90, "f32")
+    b.step(3)
+    Ub, Vb = b.factors()
+    Eb, Rb, _, _ = b.history()
+    np.testing.assert_array_equal(Ua, Ub)
+    np.testing.assert_array_equal(Va * np.float32(8.0), Vb)
+    np.testing.assert_allclose(Ea, Eb, rtol=1e-12)
+    np.testing.assert_array_equal(Ra, Rb)
+
+
+def test_mode_none_is_algorithm_1_gpu():
+    c = synth.make_corpus(400, 300, seed=39, alpha=1.1, nnz=5000, dtype="f64")
+    u0, _ = synth.make_init(400, 300, 6, seed=39, dtype="f64")
+    _say("fp64 mode none (Algorithm 1)")
+    prob = _problem(c, u0, 6, 1, 1, "f64", mode="none")
+    prob.step(4)
+    U, V = prob.factors()
+    st = oracle.als(c.scipy(), u0, 1, 1, 4, mode=oracle.MODE_NONE)
+    assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9
