@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the enforced-sparsity ALS hot path on one MI355X.
+
+One step = one ALS iteration of Algorithm 2 with per-column top-t (V half:
+A^T U, FP64 solve, clamp, top-t_v, sparse repack, Gram + Cholesky; U half
+mirrored; then R and E), on the 100k terms x 200k docs / 20M-nnz FP32
+workload with k = 50, t_u = 1000, t_v = 2000.  Inputs are synthetic (Zipf
+terms, lognormal TF-IDF values) and resident in HBM before timing starts.
+
+Prints one JSON line: iterations/s, plus the SpMM roofline (algorithmic
+bytes per launch / event-timed launch duration) and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py --copy-calibration      # plain copy kernel for counter scaling
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_traffic_100kx200k.json")
+SPMM_SRC = os.path.join(ROOT, "paper_1510_05237_amd", "csrc", "k_spmm.hip")
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmm_algorithmic_bytes(rows_out: int, rows_f: int, nnz_a: int, nnz_f: float, k: int, elt: int,
+                           keep_c: bool) -> float:
+    """Bytes one fused SpMM launch must move: the A orientation it streams
+    (value + int32 index per nonzero, int64 row offsets), the sparse fixed
+    factor once (value + 1-byte topic per entry, int32 row offsets), and the
+    dense k-wide output written once (twice in the U half, which also keeps
+    the raw product for the error)."""
+    a = nnz_a * (elt + 4) + (rows_out + 1) * 8
+    f = nnz_f * (elt + 1) + (rows_f + 1) * 4
+    out = rows_out * k * elt * (2 if keep_c else 1)
+    return float(a + f + out)
+
+
+def file_sha(path: str) -> str:
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic(stage: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
+    absent or taken on a different version of the SpMM kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != file_sha(SPMM_SRC):
+        return None
+    s = t.get("stages", {}).get(stage)
+    if not s:
+        return None
+    return float(s["fetch_bytes"] + s["write_bytes"])
+
+
+def cpu_baseline(corpus, u0, p, iters: int):
+    """The FP64 oracle as it stands, single-threaded, on a bounded sample:
+    one untimed iteration from U0, then `iters` timed steady-state iterations
+    of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    A = corpus.scipy()
+    with threadpool_limits(limits=1):
+        st = oracle.als(A, u0, p["t_u"], p["t_v"], 1)
+        times = []
+        for _ in range(iters):
+            t0 = time.perf_counter()
+            st = oracle.als(A, u0, p["t_u"], p["t_v"], 1, state=st)
+            times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    return {
+        "value": 1.0 / med,
+        "unit": "it/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{iters} steady-state ALS iterations (after 1 untimed from U0) of the full "
+                   f"{corpus.n}x{corpus.m} / {corpus.nnz}-nnz workload, FP64 numpy/scipy oracle, "
+                   f"1 thread, median {med:.2f} s/iteration"),
+        "E_after": float(st.E[-1]),
+    }
+
+
+def copy_calibration(gib: float = 1.0, reps: int = 5):
+    """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain_f32_100kx200k")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the ALS hot path on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1510_05237_amd import NMF
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log(f"generating {args.workload}")
+    t0 = time.perf_counter()
+    corpus, u0, _, p = synth.make_workload(args.workload)
+    log(f"generated n={corpus.n} m={corpus.m} nnz={corpus.nnz} in {time.perf_counter() - t0:.1f}s")
+    dtype = p["dtype"]
+    elt = 4 if dtype == "f32" else 8
+    # inputs resident in HBM before anything is timed
+    rp = torch.from_numpy(corpus.indptr).to(dev)
+    ci = torch.from_numpy(corpus.indices).to(dev)
+    cv = torch.from_numpy(corpus.data).to(dev)
+    u0d = torch.from_numpy(u0).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = NMF(corpus.n, corpus.m, rp, ci, cv, u0d, t_u=p["t_u"], t_v=p["t_v"], dtype=dtype, device=dev)
+    torch.cuda.synchronize()
+    log(f"created handle in {time.perf_counter() - t0:.1f}s (workspace {prob.ws_bytes / 2**30:.2f} GiB)")
+
+    # iteration 1 starts from the dense U0; it is timed on its own
+    t0 = time.perf_counter()
+    prob.step(1)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    if args.warmup > 1:
+        prob.step(args.warmup - 1)
+    torch.cuda.synchronize()
+    log(f"warm-up done (first iteration {first_ms:.2f} ms)")
+
+    prob.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = prob.profile_read()
+    prob.profile(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} iterations: {ms_per_step:.3f} ms/iteration")
+
+    E, R, nu, nv = prob.history(args.steps)
+    nnz_u = float(np.mean(nu))
+    nnz_v = float(np.mean(nv))
+    k = p["k"]
+    stage_ms = {name: (ms / cnt if cnt else None) for name, (ms, cnt) in prof.items()}
+    bytes_v = spmm_algorithmic_bytes(corpus.m, corpus.n, corpus.nnz, nnz_u, k, elt, keep_c=False)
+    bytes_u = spmm_algorithmic_bytes(corpus.n, corpus.m, corpus.nnz, nnz_v, k, elt, keep_c=True)
+    kern = {}
+    for stage, nbytes in (("spmm_v", bytes_v), ("spmm_u", bytes_u)):
+        ms = stage_ms[stage]
+        kern[stage] = dict(ms=ms, algorithmic_bytes=nbytes, gbs=nbytes / (ms * 1e-3) / 1e9)
+    dom = max(kern, key=lambda s: kern[s]["ms"])
+    achieved = kern[dom]["gbs"]
+    traffic = read_traffic(dom)
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": f"k_spmm ({'V half: A^T U' if dom == 'spmm_v' else 'U half: A V'})",
+        "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"],
+        "launch_ms": round(kern[dom]["ms"], 4),
+    }
+    out = {
+        "metric": "ALS iters/sec + SpMM HBM GB/s (20M nnz, k=50); batched vs per-problem loop",
+        "value": round(1e3 / ms_per_step, 2),
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": corpus.n, "m": corpus.m, "nnz": corpus.nnz, "k": k,
+                   "t_u": p["t_u"], "t_v": p["t_v"], "mode": "column", "solve": "f64"},
+        "roofline": roofline,
+        "spmm_gbs": {s: round(v["gbs"], 1) for s, v in kern.items()},
+        "stage_ms": {s: (round(v, 4) if v is not None else None) for s, v in stage_ms.items()},
+        "first_iteration_ms": round(first_ms, 3),
+        "E_last": float(E[-1]),
+        "nnz_u": nnz_u,
+        "nnz_v": nnz_v,
+    }
+    prob.close()
+    del rp, ci, cv, u0d
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the FP64 CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(corpus, u0, p, args.cpu_iters)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,45 @@ nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* los
 nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const double* g_scale,
                         void* gU, void* gV);
 
+/* Stages of one iteration, for nmf_profile_read. */
+enum {
+  NMF_STAGE_SPMM_V = 0,   /* A^T U, solve, clamp (Algorithm 2 step 1)      */
+  NMF_STAGE_SELECT_V = 1, /* per-column top-t_v (step 2)                   */
+  NMF_STAGE_REPACK_V = 2, /* sparse repack of V                            */
+  NMF_STAGE_GRAM_V = 3,   /* V^T V, Cholesky, inverse                      */
+  NMF_STAGE_SPMM_U = 4,   /* A V, solve, clamp (step 3)                    */
+  NMF_STAGE_SELECT_U = 5, /* per-column top-t_u (step 4)                   */
+  NMF_STAGE_REPACK_U = 6,
+  NMF_STAGE_GRAM_U = 7,
+  NMF_STAGE_METRICS = 8,  /* R and E of Section 3.1                        */
+  NMF_NUM_STAGES = 9
+};
+
+/* Measurement aid, not part of the method: while enabled (enable != 0),
+ * every stage that nmf_als_step enqueues is bracketed by HIP events on the
+ * handle's stream.  Enabling clears the totals.  Host-side events only; no
+ * device memory is allocated. */
+nmf_status nmf_profile(nmf_handle* h, int32_t enable);
+
+/* Summed event time (milliseconds) and number of launches per stage since
+ * profiling was enabled; arrays of n_stages entries (<= NMF_NUM_STAGES).
+ * Synchronizes. */
+nmf_status nmf_profile_read(nmf_handle* h, double* ms, int64_t* count, int32_t n_stages);
+
+/* Tuning parameters (performance only; results stay within the documented
+ * tolerance and are reproducible for a given setting). */
+enum {
+  NMF_PARAM_SPARSE_ROW_V = 0, /* V half: U rows with <= this many entries are
+                                 gathered entry by entry, denser rows whole
+                                 (0..128; default 3)                        */
+  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V             */
+  NMF_NUM_PARAMS = 2
+};
+
+/* Set a tuning parameter of a handle (applies to later launches).
+ * Errors: INVALID_ARG for an unknown parameter or a value out of range. */
+nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value);
+
 /* Message for the last error on this handle (or of the last failed
  * nmf_create when h is NULL).  Never NULL. */
 const char* nmf_last_error(const nmf_handle* h);

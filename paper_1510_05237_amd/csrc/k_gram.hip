@@ -1,18 +1,20 @@
 // Gram matrix of the fixed factor and its inverse: the (U^T U)^-1 and
 // (V^T V)^-1 of Algorithms 1-2.
 //
-// G = F^T F is summed over the rows of F in the working type T: each of a
-// fixed number of blocks owns a fixed slice of rows and keeps its partial
-// k x k sums in registers (one thread per upper-triangle entry group), so
-// the sums do not depend on scheduling.  The last block to finish (device
-// ticket) adds the block partials in block order in float64, then, still in
-// float64 and in LDS:
-//  * dead topics (zero diagonal: an all-zero column of F) get an identity
-//    row and column, which keeps that topic at exactly zero;
-//  * Cholesky G = L L^T (a non-positive pivot elsewhere sets the sticky
-//    status NMF_ERR_NOT_SPD);
-//  * L^-1 by forward substitution (one thread per column, written into the
-//    free upper triangle), then W = L^-T L^-1.
+//  1. k_gram_partial: G = F^T F is summed over the rows of F in the working
+//     type T.  Each of kGramBlocks blocks owns a fixed slice of rows and keeps
+//     its partial k x k sums (upper triangle) in registers.
+//  2. k_gram_reduce: every block owns 64 upper-triangle entries; its four
+//     waves add strided subsets of the block partials in float64 and the
+//     four sums are combined in a fixed order, so G does not depend on
+//     scheduling.
+//  3. k_gram_factor (one block) factorizes in float64, in LDS:
+//      * dead topics (zero diagonal: an all-zero column of F) get an identity
+//        row and column, which keeps that topic at exactly zero;
+//      * Cholesky G = L L^T, right-looking; a non-positive pivot elsewhere
+//        sets the sticky status NMF_ERR_NOT_SPD;
+//      * L^-1 overwrites L row by row (forward substitution on all columns
+//        of the identity at once), then W = L^-T L^-1.
 // G itself is stored without the dead-topic substitution (the error of
 // Section 3.1 needs the true Gram matrices).
 #include "nmf_device.h"
@@ -21,7 +23,8 @@ namespace nmfk {
 
 namespace {
 
-constexpr int kStageRows = 32;
+constexpr int kStageRows = 128;
+constexpr int kReduceEntries = 64;  // upper-triangle entries per reduce block
 
 struct GramArgs {
   const void* F;            // rows x k (compact rows of a factor, or a dense matrix)
@@ -29,7 +32,6 @@ struct GramArgs {
   int64_t rows_host;
   int32_t k;
   void* partials;           // [kGramBlocks][ne] T
-  int32_t* ticket;
   double* G;
   double* W;                // nullptr: no factorisation (plain Gram)
   int32_t* dead;
@@ -38,6 +40,7 @@ struct GramArgs {
   const int32_t* counts_a;
   const int32_t* counts_b;
   int64_t* max_nnz;
+  int32_t two_mats;  // LDS holds a second k x k matrix for L^-1
 };
 
 __device__ __forceinline__ void tri_index(int e, int k, int* pa, int* pb) {
@@ -54,10 +57,8 @@ __device__ __forceinline__ void tri_index(int e, int k, int* pa, int* pb) {
 }
 
 template <typename T, int JMAX>
-__global__ __launch_bounds__(256) void k_gram(GramArgs g) {
+__global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int last;
-  __shared__ int bad;
   if (*g.status != 0) return;
   const int k = g.k;
   const int kpad = (k + 3) & ~3;
@@ -83,9 +84,23 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g) {
   for (int64_t r0 = lo; r0 < hi; r0 += kStageRows) {
     const int nr = static_cast<int>(hi - r0 < kStageRows ? hi - r0 : kStageRows);
     __syncthreads();
-    for (int i = tid; i < nr * k; i += 256) {
-      const int rr = i / k, c = i - rr * k;
-      stage[rr * kpad + c] = F[(r0 + rr) * k + c];
+    // the batch is contiguous in F: eight independent loads per thread
+    const int nel = nr * k;
+    for (int i0 = tid; i0 < nel; i0 += 256 * 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + 256 * u;
+        v[u] = i < nel ? F[r0 * k + i] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + 256 * u;
+        if (i < nel) {
+          const int rr = i / k, c = i - rr * k;
+          stage[rr * kpad + c] = v[u];
+        }
+      }
     }
     __syncthreads();
     for (int rr = 0; rr < nr; ++rr) {
@@ -100,103 +115,154 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs g) {
     const int e = tid + 256 * j;
     if (e < ne) part[e] = acc[j];
   }
-  fence_release();
-  __syncthreads();
-  if (tid == 0) last = atomicAdd(g.ticket, 1) == P - 1;
-  __syncthreads();
-  if (!last) return;
-  fence_acquire();
+}
 
-  double* A = reinterpret_cast<double*>(smem);  // [k][k]
-  double* dinv = A + k * k;                     // [k]
-  const T* allp = static_cast<const T*>(g.partials);
-  for (int e = tid; e < ne; e += 256) {
-    double s = 0.0;
-    for (int b = 0; b < P; ++b) s += static_cast<double>(__builtin_nontemporal_load(&allp[static_cast<int64_t>(b) * ne + e]));
-    int a, bb;
-    tri_index(e, k, &a, &bb);
-    A[a * k + bb] = s;
-    A[bb * k + a] = s;
-    g.G[a * k + bb] = s;
-    g.G[bb * k + a] = s;
-  }
-  if (tid == 0) {
-    *g.ticket = 0;
-    bad = 0;
-    if (g.max_nnz) {
-      const int64_t cur = static_cast<int64_t>(*g.counts_a) + (g.counts_b ? *g.counts_b : 0);
-      if (cur > *g.max_nnz) *g.max_nnz = cur;
-    }
+// In-LDS float64 factorization of the k x k matrix A (full storage); writes
+// W = A^-1.  X (k x k, may alias nothing) holds L^-1 when it is not null;
+// otherwise L^-1 overwrites L row by row.  Returns false when a pivot is not
+// positive.
+__device__ bool factor_inverse(double* A, double* X, double* tmp, int* dead, int k, double* W,
+                               int32_t* ndead) {
+  const int tid = threadIdx.x;
+  __shared__ int nd;
+  if (tid == 0) nd = 0;
+  __syncthreads();
+  for (int c = tid; c < k; c += 256) {
+    dead[c] = A[c * k + c] == 0.0;
+    if (dead[c]) atomicAdd(&nd, 1);
   }
   __syncthreads();
-  if (g.W == nullptr) return;
-  // dead topics
-  if (tid == 0) {
-    int nd = 0;
-    for (int c = 0; c < k; ++c)
-      if (A[c * k + c] == 0.0) ++nd;
-    *g.dead = nd;
-  }
-  for (int c = 0; c < k; ++c) {
-    if (A[c * k + c] == 0.0) {
-      __syncthreads();
-      for (int i = tid; i < k; i += 256) {
-        A[c * k + i] = 0.0;
-        A[i * k + c] = 0.0;
-      }
-      __syncthreads();
-      if (tid == 0) A[c * k + c] = 1.0;
-    }
-  }
-  __syncthreads();
-  // right-looking Cholesky on the lower triangle
-  for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      const double d = A[j * k + j];
-      if (!(d > 0.0)) {
-        bad = 1;
-        A[j * k + j] = 1.0;
-      } else {
-        A[j * k + j] = sqrt(d);
-      }
+  if (tid == 0) *ndead = nd;
+  if (nd > 0) {
+    for (int e = tid; e < k * k; e += 256) {
+      const int i = e / k, j = e - (e / k) * k;
+      if (dead[i] || dead[j]) A[e] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
-    const double piv = A[j * k + j];
+  }
+  // right-looking Cholesky on the lower triangle, two barriers per column.
+  // The diagonal of L goes to tmp and replaces A's diagonal only at the end,
+  // so every thread can read the pivot A[j][j] itself without a race.
+  bool ok = true;
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();  // the previous trailing update is complete
+    const double d = A[j * k + j];
+    if (!(d > 0.0)) ok = false;
+    const double piv = d > 0.0 ? sqrt(d) : 1.0;
+    if (tid == 0) tmp[j] = piv;
     for (int i = j + 1 + tid; i < k; i += 256) A[i * k + j] /= piv;
     __syncthreads();
-    const int w = k - j - 1;
-    for (int idx = tid; idx < w * w; idx += 256) {
-      const int i = j + 1 + idx / w;
-      const int l = j + 1 + idx % w;
-      if (l <= i) A[i * k + l] -= A[i * k + j] * A[l * k + j];
-    }
-    __syncthreads();
-  }
-  if (bad) {
-    if (tid == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
-    for (int i = tid; i < k * k; i += 256) g.W[i] = 0.0;
-    return;
-  }
-  // column a of L^-1 by forward substitution; L^-1[r][a] (r > a) is kept at
-  // A[a][r] (upper triangle), its diagonal in dinv
-  for (int a = tid; a < k; a += 256) {
-    const double da = 1.0 / A[a * k + a];
-    dinv[a] = da;
-    for (int r = a + 1; r < k; ++r) {
-      double s = A[r * k + a] * da;
-      for (int q = a + 1; q < r; ++q) s = fma(A[r * k + q], A[a * k + q], s);
-      A[a * k + r] = -s / A[r * k + r];
+    // trailing update: thread -> row i = j+1+tid/4, every 4th column
+    for (int i = j + 1 + (tid >> 2); i < k; i += 64) {
+      const double lij = A[i * k + j];
+      for (int l = j + 1 + (tid & 3); l <= i; l += 4) A[i * k + l] = fma(-lij, A[l * k + j], A[i * k + l]);
     }
   }
   __syncthreads();
-  // W = L^-T L^-1: W[a][b] = sum_{r >= max(a,b)} L^-1[r][a] L^-1[r][b]
+  for (int j = tid; j < k; j += 256) A[j * k + j] = tmp[j];
+  __syncthreads();
+  if (!ok) return false;
+  if (X != nullptr) {
+    // L^-1 by forward substitution on every column of the identity at once:
+    // X = I; for j: X[j][:] /= L[j][j]; X[i][:] -= L[i][j] X[j][:] (i > j)
+    for (int e = tid; e < k * k; e += 256) X[e] = (e / k) == (e % k) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+      const double ljj = A[j * k + j];
+      for (int c = tid; c <= j; c += 256) X[j * k + c] /= ljj;
+      __syncthreads();
+      for (int i = j + 1 + (tid >> 2); i < k; i += 64) {
+        const double lij = A[i * k + j];
+        for (int c = (tid & 3); c <= j; c += 4) X[i * k + c] = fma(-lij, X[j * k + c], X[i * k + c]);
+      }
+      __syncthreads();
+    }
+  } else {
+    // X = L^-1 overwrites L row by row:
+    //   X[j][c] = (delta_jc - sum_{c <= i < j} L[j][i] X[i][c]) / L[j][j]
+    X = A;
+    for (int j = 0; j < k; ++j) {
+      for (int i = tid; i <= j; i += 256) tmp[i] = A[j * k + i];
+      __syncthreads();
+      for (int c = tid; c <= j; c += 256) {
+        double s = c == j ? 1.0 : 0.0;
+        for (int i = c; i < j; ++i) s = fma(-tmp[i], A[i * k + c], s);
+        A[j * k + c] = s / tmp[j];
+      }
+      __syncthreads();
+    }
+  }
+  // W = X^T X: W[a][b] = sum_{r >= max(a,b)} X[r][a] X[r][b]
+  const int ne = k * (k + 1) / 2;
   for (int e = tid; e < ne; e += 256) {
     int a, b;
     tri_index(e, k, &a, &b);  // a <= b
-    double s = dinv[b] * (a == b ? dinv[a] : A[a * k + b]);
-    for (int r = b + 1; r < k; ++r) s = fma(A[a * k + r], A[b * k + r], s);
-    g.W[a * k + b] = s;
-    g.W[b * k + a] = s;
+    double s0 = 0.0, s1 = 0.0;
+    int r = b;
+    for (; r + 1 < k; r += 2) {
+      s0 = fma(X[r * k + a], X[r * k + b], s0);
+      s1 = fma(X[(r + 1) * k + a], X[(r + 1) * k + b], s1);
+    }
+    if (r < k) s0 = fma(X[r * k + a], X[r * k + b], s0);
+    const double sum = s0 + s1;
+    W[a * k + b] = sum;
+    W[b * k + a] = sum;
+  }
+  return true;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
+  __shared__ double red[4][kReduceEntries];
+  if (*g.status != 0) return;
+  const int k = g.k;
+  const int ne = k * (k + 1) / 2;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * kReduceEntries + lane;
+  const T* __restrict__ part = static_cast<const T*>(g.partials);
+  double s = 0.0;
+  if (e < ne) {
+    // wave wv adds partials wv, wv + 4, ... in order, eight loads in flight
+    int b = wv;
+    for (; b + 28 < kGramBlocks; b += 32) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[static_cast<int64_t>(b + 4 * u) * ne + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += static_cast<double>(v[u]);
+    }
+    for (; b < kGramBlocks; b += 4) s += static_cast<double>(part[static_cast<int64_t>(b) * ne + e]);
+  }
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && e < ne) {
+    const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    int a, b;
+    tri_index(e, k, &a, &b);
+    g.G[a * k + b] = t;
+    g.G[b * k + a] = t;
+  }
+}
+
+// One block: the storage high-water mark, then W = G^-1 in float64.
+__global__ __launch_bounds__(256) void k_gram_factor(GramArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (*g.status != 0) return;
+  const int k = g.k;
+  if (threadIdx.x == 0 && g.max_nnz) {
+    const int64_t cur = static_cast<int64_t>(*g.counts_a) + (g.counts_b ? *g.counts_b : 0);
+    if (cur > *g.max_nnz) *g.max_nnz = cur;
+  }
+  double* A = reinterpret_cast<double*>(smem);  // [k][k]
+  double* tmp = A + k * k;                      // [k]
+  int* dead = reinterpret_cast<int*>(tmp + k);  // [k]
+  double* X = g.two_mats ? reinterpret_cast<double*>(dead + ((k + 1) & ~1)) : nullptr;  // [k][k]
+  for (int i = threadIdx.x; i < k * k; i += 256) A[i] = g.G[i];
+  __syncthreads();
+  if (!factor_inverse(A, X, tmp, dead, k, g.W, g.dead)) {
+    if (threadIdx.x == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
+    for (int i = threadIdx.x; i < k * k; i += 256) g.W[i] = 0.0;
   }
 }
 
@@ -204,13 +270,18 @@ template <typename T>
 hipError_t launch(nmf_handle* h, GramArgs& g) {
   const int k = h->k;
   const int kpad = (k + 3) & ~3;
-  size_t lds = static_cast<size_t>(kStageRows) * kpad * sizeof(T);
-  const size_t fac = (static_cast<size_t>(k) * k + k) * sizeof(double);
-  if (fac > lds) lds = fac;
+  const size_t stage = static_cast<size_t>(kStageRows) * kpad * sizeof(T);
+  size_t fac = (static_cast<size_t>(k) * k + k) * sizeof(double) + static_cast<size_t>((k + 1) & ~1) * sizeof(int);
+  g.two_mats = fac + static_cast<size_t>(k) * k * sizeof(double) <= 150 * 1024 ? 1 : 0;
+  if (g.two_mats) fac += static_cast<size_t>(k) * k * sizeof(double);
   if (k <= 64)
-    hipLaunchKernelGGL((k_gram<T, 9>), dim3(kGramBlocks), dim3(256), lds, h->stream, g);
+    hipLaunchKernelGGL((k_gram_partial<T, 9>), dim3(kGramBlocks), dim3(256), stage, h->stream, g);
   else
-    hipLaunchKernelGGL((k_gram<T, 33>), dim3(kGramBlocks), dim3(256), lds, h->stream, g);
+    hipLaunchKernelGGL((k_gram_partial<T, 33>), dim3(kGramBlocks), dim3(256), stage, h->stream, g);
+  const int ne = k * (k + 1) / 2;
+  const int rblocks = (ne + kReduceEntries - 1) / kReduceEntries;
+  hipLaunchKernelGGL((k_gram_reduce<T>), dim3(rblocks), dim3(256), 0, h->stream, g);
+  if (g.W) hipLaunchKernelGGL(k_gram_factor, dim3(1), dim3(256), fac, h->stream, g);
   return hipGetLastError();
 }
 
@@ -223,7 +294,6 @@ hipError_t gram(nmf_handle* h, const Factor& F, const Gram& out) {
   g.rows_dev = F.counts + 1;
   g.k = h->k;
   g.partials = h->gram_partials;
-  g.ticket = h->gram_ticket;
   g.G = out.G;
   g.W = out.W;
   g.dead = out.dead;
@@ -244,7 +314,6 @@ hipError_t gram_dense(nmf_handle* h, const T* F, int64_t rows, double* G) {
   g.rows_host = rows;
   g.k = h->k;
   g.partials = h->gram_partials;
-  g.ticket = h->gram_ticket;
   g.G = G;
   g.W = nullptr;
   g.status = h->status;

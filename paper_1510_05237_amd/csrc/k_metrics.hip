@@ -7,8 +7,8 @@
 //       ||A - U V^T||^2 = ||A||^2 - 2 <U, A V> + <U^T U, V^T V>,
 //       where A V is the raw product kept by the U half-step and the two
 //       Gram matrices come from the Gram kernels.
-// Every sum is float64 over fixed blocks, added in block order by the last
-// block to finish, so the history is reproducible bit for bit.
+// Every sum is float64 over fixed blocks, added in block order by a
+// one-block final kernel, so the history is reproducible bit for bit.
 #include <cmath>
 
 #include "nmf_device.h"
@@ -57,7 +57,6 @@ struct MetArgs {
   const void* dense_old;
   const void* C;  // raw A V (n x k), or nullptr
   double* partials;
-  int32_t* ticket;
   const double* GU;
   const double* GV;
   const double* nA2;
@@ -75,7 +74,6 @@ template <typename T, int KPL>
 __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
   __shared__ double sh[12];
   __shared__ double tot[3];
-  __shared__ int last;
   if (*a.status != 0) return;
   const int k = a.k;
   const int lane = lane_id();
@@ -97,23 +95,40 @@ __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
       }
       uint64_t todo = __ballot(sn >= 0 || so >= 0);
       while (todo) {
-        const int b = __ffsll(static_cast<long long>(todo)) - 1;
-        todo &= todo - 1;
-        const int64_t row = base + b;
-        const int s1 = __shfl(sn, b, 64);
-        const int s0 = __shfl(so, b, 64);
+        // four rows per step: their loads are in flight together
+        int bb[4];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-          const int c = lane + 64 * q;
-          if (c < k) {
-            const double un = s1 >= 0 ? static_cast<double>(Dn[static_cast<int64_t>(s1) * k + c]) : 0.0;
-            const double uo = s0 >= 0 ? static_cast<double>(Do[static_cast<int64_t>(s0) * k + c]) : 0.0;
-            const double dd = un - uo;
-            d2 = fma(dd, dd, d2);
-            n2 = fma(un, un, n2);
-            if (C != nullptr && s1 >= 0) x = fma(un, static_cast<double>(C[row * k + c]), x);
+        for (int u = 0; u < 4; ++u) {
+          bb[u] = -1;
+          if (todo) {
+            bb[u] = __ffsll(static_cast<long long>(todo)) - 1;
+            todo &= todo - 1;
           }
         }
+        double un[4][KPL], uo[4][KPL], cv[4][KPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int b = bb[u] < 0 ? 0 : bb[u];
+          const int s1 = bb[u] < 0 ? -1 : __shfl(sn, b, 64);
+          const int s0 = bb[u] < 0 ? -1 : __shfl(so, b, 64);
+#pragma unroll
+          for (int q = 0; q < KPL; ++q) {
+            const int c = lane + 64 * q;
+            const bool in = c < k;
+            un[u][q] = (in && s1 >= 0) ? static_cast<double>(Dn[static_cast<int64_t>(s1) * k + c]) : 0.0;
+            uo[u][q] = (in && s0 >= 0) ? static_cast<double>(Do[static_cast<int64_t>(s0) * k + c]) : 0.0;
+            cv[u][q] = (in && s1 >= 0 && C != nullptr) ? static_cast<double>(C[(base + b) * k + c]) : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < KPL; ++q) {
+            const double dd = un[u][q] - uo[u][q];
+            d2 = fma(dd, dd, d2);
+            n2 = fma(un[u][q], un[u][q], n2);
+            x = fma(un[u][q], cv[u][q], x);
+          }
       }
     }
   }
@@ -124,26 +139,28 @@ __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
     p[1] = tot[1];
     p[2] = tot[2];
   }
-  fence_release();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1) == static_cast<int>(gridDim.x) - 1;
-  __syncthreads();
-  if (!last) return;
-  fence_acquire();
-  // quadratic term <G_U, G_V>, summed by thread 0 in fixed order below
+}
+
+// One block: add the block partials in block order, the quadratic term
+// <G_U, G_V>, then E and R into the history ring.
+__global__ __launch_bounds__(256) void k_metrics_final(MetArgs a, int nparts) {
+  __shared__ double sh[12];
+  __shared__ double tot[3];
+  __shared__ double pv[kMetricBlocks * 3];
+  if (*a.status != 0) return;
+  const int k = a.k;
+  for (int i = threadIdx.x; i < nparts * 3; i += 256) pv[i] = a.partials[(i / 3) * 4 + (i % 3)];
   double q = 0.0;
   if (a.record && a.GU != nullptr)
     for (int i = threadIdx.x; i < k * k; i += 256) q = fma(a.GU[i], a.GV[i], q);
-  __syncthreads();
   block_sum3(q, 0.0, 0.0, sh, tot);
   __syncthreads();
   if (threadIdx.x != 0) return;
   double D = 0, N = 0, X = 0;
-  for (int b = 0; b < static_cast<int>(gridDim.x); ++b) {
-    const double* p = a.partials + b * 4;
-    D += __builtin_nontemporal_load(&p[0]);
-    N += __builtin_nontemporal_load(&p[1]);
-    X += __builtin_nontemporal_load(&p[2]);
+  for (int b = 0; b < nparts; ++b) {
+    D += pv[b * 3 + 0];
+    N += pv[b * 3 + 1];
+    X += pv[b * 3 + 2];
   }
   const int64_t it = *a.it;
   double* rec = a.ring + (it % kHistRing) * H_FIELDS;
@@ -162,18 +179,13 @@ __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
   rec[H_DEADU] = static_cast<double>(*a.dead_u);
   rec[H_DEADV] = static_cast<double>(*a.dead_v);
   *a.it = it + 1;
-  *a.ticket = 0;
 }
 
-// <U, C> for dense U, C (n x k) and L = ||A||^2 - 2 <U, C> + <G_U, G_V>
+// <U, C> for dense U, C (n x k): block partials ...
 template <typename T>
-__global__ __launch_bounds__(256) void k_loss(int64_t count, const T* U, const T* C,
-                                              const double* GU, const double* GV, int k,
-                                              const double* nA2, double* partials, int32_t* ticket,
-                                              double* out) {
+__global__ __launch_bounds__(256) void k_loss(int64_t count, const T* U, const T* C, double* partials) {
   __shared__ double sh[12];
   __shared__ double tot[3];
-  __shared__ int last;
   const int P = gridDim.x;
   const int64_t lo = count * blockIdx.x / P;
   const int64_t hi = count * (blockIdx.x + 1) / P;
@@ -182,21 +194,26 @@ __global__ __launch_bounds__(256) void k_loss(int64_t count, const T* U, const T
     x = fma(static_cast<double>(U[i]), static_cast<double>(C[i]), x);
   block_sum3(x, 0.0, 0.0, sh, tot);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot[0];
-  fence_release();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == P - 1;
-  __syncthreads();
-  if (!last) return;
-  fence_acquire();
+}
+
+// ... then L = ||A||^2 - 2 <U, C> + <G_U, G_V> (one block; GU may be null
+// for a plain sum of the partials into *out).
+__global__ __launch_bounds__(256) void k_loss_final(const double* partials, int nparts, const double* GU,
+                                                    const double* GV, int k, const double* nA2,
+                                                    double* out) {
+  __shared__ double sh[12];
+  __shared__ double tot[3];
+  __shared__ double pv[kMetricBlocks];
+  for (int i = threadIdx.x; i < nparts; i += 256) pv[i] = partials[i];
   double q = 0.0;
-  for (int i = threadIdx.x; i < k * k; i += 256) q = fma(GU[i], GV[i], q);
-  __syncthreads();
+  if (GU != nullptr)
+    for (int i = threadIdx.x; i < k * k; i += 256) q = fma(GU[i], GV[i], q);
   block_sum3(q, 0.0, 0.0, sh, tot);
+  __syncthreads();
   if (threadIdx.x != 0) return;
   double X = 0.0;
-  for (int b = 0; b < P; ++b) X += __builtin_nontemporal_load(&partials[b]);
-  *out = *nA2 - 2.0 * X + tot[0];
-  *ticket = 0;
+  for (int b = 0; b < nparts; ++b) X += pv[b];
+  *out = GU != nullptr ? *nA2 - 2.0 * X + tot[0] : X;
 }
 
 // out = g * (-2 B + 2 F G) for dense F, B (rows x k), G (k x k, float64)
@@ -263,11 +280,9 @@ __global__ void k_check(const T* x, int64_t count, int32_t* flag) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_sumsq(const T* x, int64_t count, double* partials,
-                                               int32_t* ticket, double* out) {
+__global__ __launch_bounds__(256) void k_sumsq(const T* x, int64_t count, double* partials) {
   __shared__ double sh[12];
   __shared__ double tot[3];
-  __shared__ int last;
   const int P = gridDim.x;
   const int64_t lo = count * blockIdx.x / P;
   const int64_t hi = count * (blockIdx.x + 1) / P;
@@ -278,16 +293,6 @@ __global__ __launch_bounds__(256) void k_sumsq(const T* x, int64_t count, double
   }
   block_sum3(s, 0.0, 0.0, sh, tot);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot[0];
-  fence_release();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1) == P - 1;
-  __syncthreads();
-  if (!last || threadIdx.x != 0) return;
-  fence_acquire();
-  double S = 0.0;
-  for (int b = 0; b < P; ++b) S += __builtin_nontemporal_load(&partials[b]);
-  *out = S;
-  *ticket = 0;
 }
 
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
@@ -316,7 +321,6 @@ hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const 
   a.dense_old = Uold.dense;
   a.C = C;
   a.partials = h->met.partials;
-  a.ticket = h->met.ticket;
   a.GU = h->gU.G;
   a.GV = h->gV.G;
   a.nA2 = h->met.nA2;
@@ -332,14 +336,17 @@ hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const 
     hipLaunchKernelGGL((k_metrics<T, 2>), dim3(kMetricBlocks), dim3(256), 0, h->stream, a);
   else
     hipLaunchKernelGGL((k_metrics<T, 1>), dim3(kMetricBlocks), dim3(256), 0, h->stream, a);
+  hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(256), 0, h->stream, a, kMetricBlocks);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t loss_dot(nmf_handle* h, const T* U, const T* C, const double* GU, const double* GV,
                     double* loss_out) {
-  hipLaunchKernelGGL((k_loss<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, h->n * h->k, U, C, GU,
-                     GV, h->k, h->met.nA2, h->met.loss_parts, h->met.ticket, loss_out);
+  hipLaunchKernelGGL((k_loss<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, h->n * h->k, U, C,
+                     h->met.loss_parts);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, h->stream, h->met.loss_parts, kMetricBlocks, GU, GV,
+                     h->k, h->met.nA2, loss_out);
   return hipGetLastError();
 }
 
@@ -379,8 +386,9 @@ hipError_t check_input(nmf_handle* h, const T* x, int64_t count, int32_t* flag) 
 
 template <typename T>
 hipError_t sum_squares(nmf_handle* h, const T* x, int64_t count, double* out) {
-  hipLaunchKernelGGL((k_sumsq<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, x, count,
-                     h->met.loss_parts, h->met.ticket, out);
+  hipLaunchKernelGGL((k_sumsq<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, x, count, h->met.loss_parts);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, h->stream, h->met.loss_parts, kMetricBlocks, nullptr,
+                     nullptr, 0, nullptr, out);
   return hipGetLastError();
 }
 

@@ -8,19 +8,22 @@
 // set in):
 //  * row-compressed sparse factor: row_ptr[rows+1], topic[], val[] with
 //    topics ascending within a row;
-//  * the SpMM gather cache: slot[r] (compact index of a nonempty row or -1),
-//    rowid[slot], and every nonempty row expanded to k dense values;
+//  * what the SpMM gathers: per row {compact dense row when the row has more
+//    than `sparse_row` entries, else its first entry; entry count}, per entry
+//    {value, topic}, and every nonempty row expanded to k dense values
+//    (slot[r] = its compact index or -1, rowid[slot] = r);
 //  * counts[0] = nnz, counts[1] = number of nonempty rows.
-// Two kernels: per-block counts + (last block) scan of the block totals;
-// then per-block local scan and write-out.  The masks are cleared as they
-// are consumed.
+// Two kernels: per-block totals, then per-block offsets (sum of the earlier
+// block totals), a local scan and the write-out.  The masks are cleared as
+// they are consumed.
 #include "nmf_device.h"
 
 namespace nmfk {
 
 namespace {
 
-constexpr int kScanRows = 256;  // rows per block, one per thread
+constexpr int kRowsPerThread = 2;
+constexpr int kScanRows = 256 * kRowsPerThread;  // rows per block
 
 struct RepackArgs {
   const void* X;
@@ -30,8 +33,8 @@ struct RepackArgs {
   uint32_t* mask;
   int32_t* part_cnt;  // [blocks]
   int32_t* part_ne;   // [blocks]
-  int32_t* ticket;
   Factor F;
+  int32_t sparse_row;
   const int32_t* status;
 };
 
@@ -41,54 +44,31 @@ __device__ __forceinline__ int row_count(const uint32_t* mask, int64_t r, int mw
   return c;
 }
 
+__device__ __forceinline__ int block_sum_256(int v, int* tmp) {
+  int t;
+  block_excl_scan_256(v, tmp, &t);
+  return t;
+}
+
 __global__ __launch_bounds__(256) void k_scan_count(RepackArgs a) {
   __shared__ int tmp[8];
-  __shared__ int last;
-  __shared__ int seg_tmp[8];
   if (*a.status != 0) return;
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * kScanRows + threadIdx.x;
-  int cnt = 0;
-  if (r < a.rows) cnt = row_count(a.mask, r, a.mw);
-  const int ne = cnt > 0;
-  int tot_c, tot_n;
-  block_excl_scan_256(cnt, tmp, &tot_c);
-  block_excl_scan_256(ne, tmp, &tot_n);
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kScanRows + threadIdx.x * kRowsPerThread;
+  int cnt = 0, ne = 0;
+#pragma unroll
+  for (int i = 0; i < kRowsPerThread; ++i) {
+    const int64_t r = r0 + i;
+    if (r < a.rows) {
+      const int c = row_count(a.mask, r, a.mw);
+      cnt += c;
+      ne += c > 0;
+    }
+  }
+  const int tc = block_sum_256(cnt, tmp);
+  const int tn = block_sum_256(ne, tmp);
   if (threadIdx.x == 0) {
-    a.part_cnt[blockIdx.x] = tot_c;
-    a.part_ne[blockIdx.x] = tot_n;
-  }
-  fence_release();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(a.ticket, 1) == static_cast<int>(gridDim.x) - 1;
-  __syncthreads();
-  if (!last) return;
-  fence_acquire();
-  // exclusive scan of the block totals: each thread scans one contiguous
-  // segment, the segment sums are scanned across the block
-  const int P = gridDim.x;
-  const int seg = (P + 255) / 256;
-  const int s0 = threadIdx.x * seg;
-  int sc = 0, sn = 0;
-  for (int i = s0; i < s0 + seg && i < P; ++i) {
-    sc += __hip_atomic_load(&a.part_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sn += __hip_atomic_load(&a.part_ne[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  int all_c, all_n;
-  int oc = block_excl_scan_256(sc, seg_tmp, &all_c);
-  int on = block_excl_scan_256(sn, seg_tmp, &all_n);
-  for (int i = s0; i < s0 + seg && i < P; ++i) {
-    const int vc = __hip_atomic_load(&a.part_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int vn = __hip_atomic_load(&a.part_ne[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.part_cnt[i] = oc;
-    a.part_ne[i] = on;
-    oc += vc;
-    on += vn;
-  }
-  if (threadIdx.x == 0) {
-    a.F.counts[0] = all_c;
-    a.F.counts[1] = all_n;
-    a.F.row_ptr[a.rows] = all_c;
-    *a.ticket = 0;
+    a.part_cnt[blockIdx.x] = tc;
+    a.part_ne[blockIdx.x] = tn;
   }
 }
 
@@ -101,71 +81,134 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
   if (*a.status != 0) return;
   const int mw = a.mw;
   const int k = a.k;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kScanRows;
-  const int64_t r = r0 + threadIdx.x;
-  int cnt = 0;
-  if (r < a.rows) {
-    for (int w = 0; w < mw; ++w) {
-      const uint32_t m = a.mask[r * mw + w];
-      smask[threadIdx.x * 4 + w] = m;
-      cnt += __popc(m);
+  const int tid = threadIdx.x;
+  // offsets of this block: the totals of all earlier blocks
+  int oc = 0, on = 0;
+  for (int b = tid; b < static_cast<int>(blockIdx.x); b += 256) {
+    oc += a.part_cnt[b];
+    on += a.part_ne[b];
+  }
+  const int off_c = block_sum_256(oc, tmp);
+  const int off_n = block_sum_256(on, tmp);
+  const int64_t rb0 = static_cast<int64_t>(blockIdx.x) * kScanRows;
+  const int64_t r0 = rb0 + tid * kRowsPerThread;
+  int cnt[kRowsPerThread];
+  int tc = 0, tn = 0;
+#pragma unroll
+  for (int i = 0; i < kRowsPerThread; ++i) {
+    const int64_t r = r0 + i;
+    const int li = tid * kRowsPerThread + i;
+    int c = 0;
+    if (r < a.rows) {
+      for (int w = 0; w < mw; ++w) {
+        const uint32_t m = a.mask[r * mw + w];
+        smask[li * 4 + w] = m;
+        c += __popc(m);
+      }
     }
+    cnt[i] = c;
+    tc += c;
+    tn += c > 0;
   }
-  const int ne = cnt > 0;
-  int tc, tn;
-  const int lc = block_excl_scan_256(cnt, tmp, &tc);
-  const int ln = block_excl_scan_256(ne, tmp, &tn);
-  const int rp = a.part_cnt[blockIdx.x] + lc;
-  const int sl = ne ? a.part_ne[blockIdx.x] + ln : -1;
-  if (r < a.rows) {
-    a.F.row_ptr[r] = rp;
-    a.F.slot[r] = sl;
-    if (ne) a.F.rowid[sl] = static_cast<int32_t>(r);
-    for (int w = 0; w < mw; ++w) a.mask[r * mw + w] = 0u;
+  int bc, bn;
+  int lc = block_excl_scan_256(tc, tmp, &bc);
+  int ln = block_excl_scan_256(tn, tmp, &bn);
+  lc += off_c;
+  ln += off_n;
+#pragma unroll
+  for (int i = 0; i < kRowsPerThread; ++i) {
+    const int64_t r = r0 + i;
+    const int li = tid * kRowsPerThread + i;
+    const bool ne = cnt[i] > 0;
+    const int sl = ne ? ln : -1;
+    s_rp[li] = lc;
+    s_slot[li] = sl;
+    if (r < a.rows) {
+      a.F.row_ptr[r] = lc;
+      a.F.slot[r] = sl;
+      a.F.meta[r] = make_int2(cnt[i] > a.sparse_row ? sl : lc, cnt[i]);
+      if (ne) a.F.rowid[sl] = static_cast<int32_t>(r);
+      for (int w = 0; w < mw; ++w) a.mask[r * mw + w] = 0u;
+    }
+    lc += cnt[i];
+    ln += ne ? 1 : 0;
   }
-  s_rp[threadIdx.x] = rp;
-  s_slot[threadIdx.x] = sl;
+  if (blockIdx.x == gridDim.x - 1 && tid == 255) {
+    // lc / ln now hold the totals over every block
+    a.F.counts[0] = lc;
+    a.F.counts[1] = ln;
+    a.F.row_ptr[a.rows] = lc;
+  }
   __syncthreads();
-  // write-out: each wave takes 64 rows; lanes = topics for every nonempty row
+  // write-out: each wave takes 64 rows at a time; lanes = topics for every
+  // nonempty row
   const int lane = lane_id();
-  const int wv = threadIdx.x >> 6;
+  const int wv = tid >> 6;
   const T* __restrict__ X = static_cast<const T*>(a.X);
   T* __restrict__ dense = static_cast<T*>(a.F.dense);
   T* __restrict__ fval = static_cast<T*>(a.F.val);
-  const int lr = wv * 64 + lane;
-  uint64_t todo = __ballot(s_slot[lr] >= 0);
-  while (todo) {
-    const int b = __ffsll(static_cast<long long>(todo)) - 1;
-    todo &= todo - 1;
-    const int i = wv * 64 + b;
-    const int64_t row = r0 + i;
-    const int s = s_slot[i];
-    const int base = s_rp[i];
-    uint32_t mwords[4];
+  FactorEnt<T>* __restrict__ ents = static_cast<FactorEnt<T>*>(a.F.packed);
+  for (int g = wv * 64; g < kScanRows; g += 256) {
+    uint64_t todo = __ballot(s_slot[g + lane] >= 0);
+    // four nonempty rows per step: their value loads are in flight together
+    while (todo) {
+      int ib[4];
+      int nb = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) mwords[w] = w < mw ? smask[i * 4 + w] : 0u;
-#pragma unroll
-    for (int q = 0; q < KPL; ++q) {
-      const int c = lane + 64 * q;
-      if (c < k) {
-        uint32_t word = 0;
-        int below = 0;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          if (w == (c >> 5))
-            word = mwords[w];
-          else if (w < (c >> 5))
-            below += __popc(mwords[w]);
-        }
-        const bool bit = (word >> (c & 31)) & 1u;
-        const T v = bit ? X[row * k + c] : T(0);
-        dense[static_cast<int64_t>(s) * k + c] = v;
-        if (bit) {
-          below += __popc(word & ((1u << (c & 31)) - 1u));
-          fval[base + below] = v;
-          a.F.topic[base + below] = static_cast<uint8_t>(c);
+      for (int u = 0; u < 4; ++u) {
+        ib[u] = -1;
+        if (todo) {
+          ib[u] = g + __ffsll(static_cast<long long>(todo)) - 1;
+          todo &= todo - 1;
+          ++nb;
         }
       }
+      T xv[4][KPL];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+          const int c = lane + 64 * q;
+          xv[u][q] = (ib[u] >= 0 && c < k) ? X[(rb0 + ib[u]) * k + c] : T(0);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (ib[u] < 0) continue;
+        const int i = ib[u];
+        const int s = s_slot[i];
+        const int base = s_rp[i];
+        uint32_t mwords[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) mwords[w] = w < mw ? smask[i * 4 + w] : 0u;
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+          const int c = lane + 64 * q;
+          if (c < k) {
+            uint32_t word = 0;
+            int below = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              if (w == (c >> 5))
+                word = mwords[w];
+              else if (w < (c >> 5))
+                below += __popc(mwords[w]);
+            }
+            const bool bit = (word >> (c & 31)) & 1u;
+            const T v = bit ? xv[u][q] : T(0);
+            dense[static_cast<int64_t>(s) * k + c] = v;
+            if (bit) {
+              below += __popc(word & ((1u << (c & 31)) - 1u));
+              fval[base + below] = v;
+              a.F.topic[base + below] = static_cast<uint8_t>(c);
+              FactorEnt<T> en;
+              en.v = v;
+              en.t = static_cast<uint32_t>(c);
+              ents[base + below] = en;
+            }
+          }
+        }
+      }
+      (void)nb;
     }
   }
 }
@@ -173,8 +216,9 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
 }  // namespace
 
 template <typename T>
-hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f) {
+hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f, int sparse_row) {
   RepackArgs a{};
+  a.sparse_row = sparse_row;
   a.X = X;
   a.rows = rows;
   a.k = h->k;
@@ -183,7 +227,6 @@ hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f) 
   const int blocks = static_cast<int>((rows + kScanRows - 1) / kScanRows);
   a.part_cnt = h->sel.scan_part;
   a.part_ne = h->sel.scan_part + blocks + 1;
-  a.ticket = h->sel.ticket + 1;
   a.F = out_f;
   a.status = h->status;
   if (blocks == 0) return hipSuccess;
@@ -195,7 +238,7 @@ hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f) 
   return hipGetLastError();
 }
 
-template hipError_t repack<float>(nmf_handle*, const float*, int64_t, const Factor&);
-template hipError_t repack<double>(nmf_handle*, const double*, int64_t, const Factor&);
+template hipError_t repack<float>(nmf_handle*, const float*, int64_t, const Factor&, int);
+template hipError_t repack<double>(nmf_handle*, const double*, int64_t, const Factor&, int);
 
 }  // namespace nmfk

@@ -10,8 +10,8 @@
 // unsigned integers):
 //  1. hist:    per-column histogram of the first digit (the 8 bits under
 //              the sign bit: the exponent for float32), block-private in LDS,
-//              flushed with integer atomics.  The last block to finish picks,
-//              per column, the digit b1 holding the t-th largest entry.
+//              flushed with integer atomics; then one block picks, per
+//              column, the digit b1 holding the t-th largest entry.
 //  2. collect: one pass over X: entries whose digit is above b1 are kept
 //              (bit set in the per-row keep mask); entries with digit b1 are
 //              appended to the column's candidate list.
@@ -22,6 +22,8 @@
 // Only integer atomics are used, so the kept set does not depend on
 // scheduling; the row-compressed factor is then built in row order from the
 // keep masks (k_repack.hip).
+#include <algorithm>
+
 #include "nmf_device.h"
 
 namespace nmfk {
@@ -38,6 +40,7 @@ struct SelArgs {
   int32_t mw;  // mask words per row
   int64_t t;
   int32_t mode;
+  int32_t hist_rows;  // rows of X per hist block
   uint32_t* hist;
   ColSel* sel;
   int32_t* cand_cnt;  // padded: column c at cand_cnt[c * kCntStride]
@@ -54,7 +57,6 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
   using KO = KeyOf<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins]
-  __shared__ int last;
   if (*a.status != 0) return;
   const int k = a.k;
   for (int i = threadIdx.x; i < k * kPadBins; i += 256) h[i] = 0;
@@ -62,16 +64,21 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   const T* __restrict__ X = static_cast<const T*>(a.X);
-  const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock;
-  int64_t r_end = r_begin + kRowsPerBlock;
+  const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * a.hist_rows;
+  int64_t r_end = r_begin + a.hist_rows;
   if (r_end > a.rows) r_end = a.rows;
-  for (int64_t r = r_begin + wv; r < r_end; r += 4) {
+  // four rows per wave per step keep four loads in flight
+  for (int64_t r = r_begin + wv; r < r_end; r += 16) {
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
       if (c < k) {
-        const auto key = KO::key(X[r * k + c]);
-        if (key != 0) atomicAdd(&h[c * kPadBins + top_digit<T>(key)], 1u);
+        typename KO::K key[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) key[u] = r + 4 * u < r_end ? KO::key(X[(r + 4 * u) * k + c]) : 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (key[u] != 0) atomicAdd(&h[c * kPadBins + top_digit<T>(key[u])], 1u);
       }
     }
   }
@@ -81,18 +88,34 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
     const uint32_t v = h[c * kPadBins + d];
     if (v) atomicAdd(&a.hist[i], v);
   }
-  fence_release();
+}
+
+// One block: the threshold digit of every column from the full histogram,
+// which is cleared for the next use.
+__global__ __launch_bounds__(256) void k_pick(SelArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins]
+  if (*a.status != 0) return;
+  const int k = a.k;
+  for (int i0 = threadIdx.x; i0 < k * kBins; i0 += 256 * 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i0 + 256 * u < k * kBins ? a.hist[i0 + 256 * u] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 256 * u;
+      if (i < k * kBins) {
+        const int c = i / kBins, d = i - c * kBins;
+        h[c * kPadBins + d] = v[u];
+        a.hist[i] = 0;
+      }
+    }
+  }
   __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&a.ticket[0], 1) == static_cast<int>(gridDim.x) - 1;
-  __syncthreads();
-  if (!last) return;
-  fence_acquire();
-  // last block: choose the threshold digit of every column and clear the
-  // global histogram for the next use
   for (int c = threadIdx.x; c < k; c += 256) {
-    uint32_t* hc = a.hist + static_cast<int64_t>(c) * kBins;
+    const uint32_t* hc = h + c * kPadBins;
     int64_t npos = 0;
-    for (int d = 0; d < kBins; ++d) npos += __hip_atomic_load(&hc[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int d = 0; d < kBins; ++d) npos += hc[d];
     ColSel s;
     s.npos = static_cast<int32_t>(npos);
     s.all = (a.mode == NMF_MODE_NONE || npos <= a.t) ? 1 : 0;
@@ -101,7 +124,7 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
     if (!s.all) {
       int64_t above = 0;
       for (int d = kBins - 1; d >= 0; --d) {
-        const int64_t hd = __hip_atomic_load(&hc[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t hd = hc[d];
         if (above + hd >= a.t) {
           s.b1 = d;
           s.need = static_cast<int32_t>(a.t - above);
@@ -111,9 +134,7 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
       }
     }
     a.sel[c] = s;
-    for (int d = 0; d < kBins; ++d) hc[d] = 0;
   }
-  if (threadIdx.x == 0) a.ticket[0] = 0;
 }
 
 template <typename T, int KPL>
@@ -140,14 +161,26 @@ __global__ __launch_bounds__(256) void k_collect(SelArgs a) {
   const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock;
   int64_t r_end = r_begin + kRowsPerBlock;
   if (r_end > a.rows) r_end = a.rows;
-  for (int64_t r = r_begin + wv; r < r_end; r += 4) {
+  for (int64_t r4 = r_begin + wv; r4 < r_end; r4 += 16) {
+   typename KO::K keys[4][KPL];
+#pragma unroll
+   for (int u = 0; u < 4; ++u)
+#pragma unroll
+     for (int q = 0; q < KPL; ++q) {
+       const int c = lane + 64 * q;
+       keys[u][q] = (c < k && r4 + 4 * u < r_end) ? KO::key(X[(r4 + 4 * u) * k + c]) : 0;
+     }
+#pragma unroll
+   for (int u = 0; u < 4; ++u) {
+    const int64_t r = r4 + 4 * u;
+    if (r >= r_end) break;
     uint64_t keep_bits[KPL];
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
       bool keep = false;
       if (c < k) {
-        const auto key = KO::key(X[r * k + c]);
+        const auto key = keys[u][q];
         if (key != 0) {
           const int d = top_digit<T>(key);
           keep = s[q].all || d > s[q].b1;
@@ -169,6 +202,7 @@ __global__ __launch_bounds__(256) void k_collect(SelArgs a) {
       const uint32_t word = (lane & 1) ? static_cast<uint32_t>(b >> 32) : static_cast<uint32_t>(b);
       if (word) atomicOr(&a.mask[r * a.mw + lane], word);
     }
+   }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < k; c += 256) {
@@ -204,7 +238,7 @@ __device__ __forceinline__ void mark(uint32_t* mask, int mw, uint32_t row, int c
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_refine(SelArgs a) {
+__global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
   using C = Cand<T>;
   __shared__ uint32_t h[kBins];
   __shared__ int s_bin, s_need, s_n, s_cnt;
@@ -226,10 +260,19 @@ __global__ __launch_bounds__(256) void k_refine(SelArgs a) {
   int kb = KeyOf<T>::bits - 9;
   int rb = 32;
   while (n > kSmall && (kb > 0 || rb > 0)) {
-    for (int i = tid; i < kBins; i += 256) h[i] = 0;
+    const int NT = blockDim.x;
+    for (int i = tid; i < kBins; i += NT) h[i] = 0;
     __syncthreads();
     int width;
-    for (int i = tid; i < n; i += 256) atomicAdd(&h[cand_digit<T>(src[i], kb, rb, &width)], 1u);
+    for (int i = tid; i < n; i += 4 * NT) {
+      C v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i + NT * u < n) v[u] = src[i + NT * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i + NT * u < n) atomicAdd(&h[cand_digit<T>(v[u], kb, rb, &width)], 1u);
+    }
     __syncthreads();
     if (tid == 0) {
       int above = 0;
@@ -249,14 +292,28 @@ __global__ __launch_bounds__(256) void k_refine(SelArgs a) {
     }
     __syncthreads();
     const int bin = s_bin;
-    for (int i = tid; i < n; i += 256) {
-      const C cd = src[i];
-      const int d = cand_digit<T>(cd, kb, rb, &width);
-      if (d > bin) {
-        mark(a.mask, a.mw, cd.row, c);
-      } else if (d == bin) {
-        const int pos = atomicAdd(&s_cnt, 1);
-        dst[pos] = cd;
+    // each wave takes 256 consecutive entries per step (four per lane)
+    for (int i0 = (tid >> 6) * 256; i0 < n; i0 += 4 * NT) {
+      C cd[4];
+      int d[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + 64 * u + __lane_id();
+        d[u] = -1;
+        if (i < n) {
+          cd[u] = src[i];
+          d[u] = cand_digit<T>(cd[u], kb, rb, &width);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (d[u] > bin) mark(a.mask, a.mw, cd[u].row, c);
+        // one LDS atomic per wave for the equal-digit entries
+        const uint64_t eq = __ballot(d[u] == bin);
+        int base = 0;
+        if (__lane_id() == 0 && eq) base = atomicAdd(&s_cnt, __popcll(eq));
+        base = __shfl(base, 0, 64);
+        if (d[u] == bin) dst[base + lane_rank(eq)] = cd[u];
       }
     }
     if (kb > 0)
@@ -280,7 +337,7 @@ __global__ __launch_bounds__(256) void k_refine(SelArgs a) {
   }
   int np = 1;
   while (np < n) np <<= 1;
-  for (int i = tid; i < np; i += 256) {
+  for (int i = tid; i < np; i += blockDim.x) {
     if (i < n) {
       srt[i] = src[i];
     } else {
@@ -293,7 +350,7 @@ __global__ __launch_bounds__(256) void k_refine(SelArgs a) {
   __syncthreads();
   for (int size = 2; size <= np; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < np; i += 256) {
+      for (int i = tid; i < np; i += blockDim.x) {
         const int j = i ^ stride;
         if (j > i) {
           const bool desc = (i & size) == 0;
@@ -309,7 +366,7 @@ __global__ __launch_bounds__(256) void k_refine(SelArgs a) {
       __syncthreads();
     }
   }
-  for (int i = tid; i < need && i < n; i += 256) mark(a.mask, a.mw, srt[i].row, c);
+  for (int i = tid; i < need && i < n; i += blockDim.x) mark(a.mask, a.mw, srt[i].row, c);
   if (tid == 0) *cnt_ptr = 0;
 }
 
@@ -317,11 +374,17 @@ template <typename T, int KPL>
 hipError_t run(nmf_handle* h, SelArgs& a) {
   const int blocks = static_cast<int>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
   if (blocks == 0) return hipSuccess;
+  // a few hundred histogram blocks: enough rows each that the flush of the
+  // block histograms stays small
+  const int64_t want = 2 * static_cast<int64_t>(h->num_cus);
+  a.hist_rows = static_cast<int32_t>(std::max<int64_t>(kRowsPerBlock, (a.rows + want - 1) / want));
+  const int hblocks = static_cast<int>((a.rows + a.hist_rows - 1) / a.hist_rows);
   const size_t hbytes = static_cast<size_t>(a.k) * kPadBins * sizeof(uint32_t);
   const size_t stage = static_cast<size_t>(a.k) * kRowsPerBlock * sizeof(Cand<T>);
-  hipLaunchKernelGGL((k_hist<T, KPL>), dim3(blocks), dim3(256), hbytes, h->stream, a);
+  hipLaunchKernelGGL((k_hist<T, KPL>), dim3(hblocks), dim3(256), hbytes, h->stream, a);
+  hipLaunchKernelGGL(k_pick, dim3(1), dim3(256), hbytes, h->stream, a);
   hipLaunchKernelGGL((k_collect<T, KPL>), dim3(blocks), dim3(256), stage, h->stream, a);
-  hipLaunchKernelGGL((k_refine<T>), dim3(a.k), dim3(256), kSmall * sizeof(Cand<T>), h->stream, a);
+  hipLaunchKernelGGL((k_refine<T>), dim3(a.k), dim3(1024), kSmall * sizeof(Cand<T>), h->stream, a);
   return hipGetLastError();
 }
 

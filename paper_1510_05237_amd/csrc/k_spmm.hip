@@ -8,35 +8,42 @@
 // accumulates in the working type T (float32 for the FP32 workloads); the
 // k x k solve of the epilogue is float64.
 //
-// Mapping (wave64):
-//  * each wave owns one work item: up to kRowGroup short rows, or one
-//    kChunk-long piece of a long (Zipf-heavy) row;
-//  * phase A, lanes = 64 consecutive nonzeros: coalesced loads of (col, a),
-//    gather of the factor row's compact slot, ballot of the hits (rows of F
-//    that are not empty), hits appended to a per-wave LDS queue;
-//  * phase B, lanes = topics: for every queued hit one coalesced k-wide load
-//    of the factor row and one FMA per lane;
-//  * the epilogue multiplies the raw sums of a group of rows by W (held in
-//    LDS as float64), clamps at zero, rounds to T and stores coalesced rows.
-// Long rows: every chunk writes a partial sum; the last chunk to arrive
-// (device-scope ticket) adds the partials in chunk order, so the result does
-// not depend on scheduling.
+// Work items (built once per orientation of A): up to RG consecutive short
+// rows with at most kChunk nonzeros in total, or one kChunk-long piece of a
+// long (Zipf-heavy) row.  Per item, per 64 nonzeros (lanes span the item's
+// rows):
+//  * lanes = nonzeros: coalesced loads of (col, a) and one 8-byte gather of
+//    the factor row's metadata {where, how many entries};
+//  * factor rows with at most `sparse_row` entries are gathered entry by entry
+//    (one {value, topic} load per entry, lanes still = nonzeros) and each
+//    product is added into the wave's LDS accumulator at (row, topic).  One
+//    wave owns the accumulator and LDS executes a wave's instructions in
+//    order, so the sums are reproducible;
+//  * denser factor rows are queued and then read as whole k-wide rows from
+//    the compact dense copy of the factor, lanes = topics: one coalesced load
+//    and one FMA per lane per row, eight rows in flight;
+//  * the epilogue multiplies the item's raw row sums by W (float64, in LDS),
+//    clamps at zero, rounds to T and stores whole rows.
+// Pieces of long rows store their raw sums; k_spmm_heavy adds them in piece
+// order and runs the same epilogue.
 #include "nmf_device.h"
 
 namespace nmfk {
 
 namespace {
 
+constexpr int kWaves = 8;  // waves per block
+
 template <typename T, int RG>
 __host__ __device__ inline size_t spmm_per_wave(int k) {
   const int kpad = (k + 3) & ~3;
-  return 64 * sizeof(int32_t) + 64 * sizeof(T) + static_cast<size_t>(RG) * kpad * sizeof(T);
+  return 64 * (2 * sizeof(int32_t) + sizeof(T)) + static_cast<size_t>(RG) * kpad * sizeof(T);
 }
 
 template <typename T, int RG>
 size_t spmm_lds_bytes(int k, bool raw) {
   const size_t w = raw ? 0 : static_cast<size_t>(k) * k * sizeof(double);
-  return w + 4 * spmm_per_wave<T, RG>(k);
+  return w + kWaves * spmm_per_wave<T, RG>(k);
 }
 
 struct SpmmArgs {
@@ -45,28 +52,58 @@ struct SpmmArgs {
   const void* val;
   const WorkItem* items;
   int32_t n_items;
-  int32_t* heavy_ticket;
+  const int32_t* heavy_row;
   const int32_t* heavy_nchunks;
   const int32_t* heavy_part0;
+  int32_t n_heavy;
   void* partials;
-  const int32_t* slot;  // gather slot per factor row (nullptr: dense input)
-  const void* F;        // compact dense factor rows (or the dense input)
+  const int2* meta;   // factor row metadata {dense row or first entry, entry count}
+  int32_t sparse_row;  // rows with at most this many entries are gathered entry by entry
+  const void* ents;   // stored factor entries {value, topic}
+  const void* F;      // compact dense factor rows (or the dense input)
   const double* W;
   void* X;
   void* C;
   int32_t k;
-  const int32_t* status;
-  int32_t* status_w;
+  int32_t* status;
 };
 
-template <typename T, int KPL>
-__device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_t p1, T* acc,
-                                           int32_t* q_off, T* q_a, bool dense_in) {
+struct WaveLds {
+  int32_t* q_off;
+  int32_t* q_row;
+  void* q_a;
+  void* tile;
+};
+
+template <typename T, int RG>
+__device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, int k, bool raw, int wv) {
+  unsigned char* base = smem + (raw ? 0 : static_cast<size_t>(k) * k * sizeof(double)) +
+                        wv * spmm_per_wave<T, RG>(k);
+  WaveLds w;
+  w.q_off = reinterpret_cast<int32_t*>(base);
+  w.q_row = reinterpret_cast<int32_t*>(base + 64 * sizeof(int32_t));
+  w.q_a = base + 128 * sizeof(int32_t);
+  w.tile = base + 128 * sizeof(int32_t) + 64 * sizeof(T);
+  return w;
+}
+
+// Adds the nonzeros [p0, p1) of an item (rows bounded by rb[0..nrows]) times
+// F into the LDS tile: tile[topic * RG + row].
+template <typename T, int KPL, int RG, bool DENSE_IN>
+__device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_t p1, const int64_t* rb,
+                                           int nrows, const WaveLds& w) {
   const int lane = lane_id();
+  const int k = a.k;
   const int32_t* __restrict__ col = a.col;
   const T* __restrict__ val = static_cast<const T*>(a.val);
   const T* __restrict__ F = static_cast<const T*>(a.F);
-  const int k = a.k;
+  const FactorEnt<T>* __restrict__ ents = static_cast<const FactorEnt<T>*>(a.ents);
+  T* tile = static_cast<T*>(w.tile);
+  T* q_a = static_cast<T*>(w.q_a);
+  T acc[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) acc[q] = T(0);
+  int cur_r = 0;
   for (int64_t base = p0; base < p1; base += 64) {
     const int64_t p = base + lane;
     const bool valid = p < p1;
@@ -76,43 +113,90 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
       j = col[p];
       av = val[p];
     }
-    int32_t s = -1;
-    if (valid) s = dense_in ? j : a.slot[j];
-    const bool hit = s >= 0;
+    int r = 0;
+#pragma unroll
+    for (int i = 1; i < RG; ++i) r += (i < nrows && p >= rb[i]) ? 1 : 0;
+    int32_t x = 0, cnt = 0;
+    if (valid) {
+      if (DENSE_IN) {
+        x = j;
+        cnt = k;
+      } else {
+        const int2 m = a.meta[j];
+        x = m.x;
+        cnt = m.y;
+      }
+    }
+    const bool sparse = !DENSE_IN && cnt > 0 && cnt <= a.sparse_row;
+    // sparse factor rows: entry e of every lane's row per round; lanes start
+    // at a rotated entry so that one round rarely adds twice to one topic
+    const int rot = sparse ? lane % cnt : 0;
+    for (int e = 0; __ballot(sparse && e < cnt) != 0; ++e) {
+      if (sparse && e < cnt) {
+        int idx = e + rot;
+        if (idx >= cnt) idx -= cnt;
+        const FactorEnt<T> en = ents[x + idx];
+        atomicAdd(&tile[en.t * RG + r], av * en.v);
+      }
+    }
+    // dense factor rows: queue, then one k-wide row per hit, lanes = topics
+    const bool hit = DENSE_IN ? valid : cnt > a.sparse_row;
     const uint64_t bal = __ballot(hit);
+    const int nh = __popcll(bal);
+    if (nh == 0) continue;
     if (hit) {
       const int pos = lane_rank(bal);
-      q_off[pos] = s * k;
+      w.q_off[pos] = x * k;
+      w.q_row[pos] = r;
       q_a[pos] = av;
     }
-    const int nh = __popcll(bal);
-    int h = 0;
-    // four hits per step keep four gathers in flight; the sums are still
-    // formed in hit order
-    for (; h + 4 <= nh; h += 4) {
-      int32_t o0 = q_off[h], o1 = q_off[h + 1], o2 = q_off[h + 2], o3 = q_off[h + 3];
-      T a0 = q_a[h], a1 = q_a[h + 1], a2 = q_a[h + 2], a3 = q_a[h + 3];
+    // pad the queue to a multiple of 8 with zero-weight copies of row 0 of F
+    // (same row index as the last hit), so the loop below needs no guards
+    const int last_lane = 63 - __builtin_clzll(bal);
+    const int r_last = __shfl(r, last_lane, 64);
+    const int nh8 = (nh + 7) & ~7;
+    if (lane < nh8 - nh) {
+      w.q_off[nh + lane] = 0;
+      w.q_row[nh + lane] = r_last;
+      q_a[nh + lane] = T(0);
+    }
+    for (int h = 0; h < nh8; h += 8) {
+      int32_t o[8], rr[8];
+      T aa[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        o[u] = w.q_off[h + u];
+        rr[u] = w.q_row[h + u];
+        aa[u] = q_a[h + u];
+      }
+      T f[8][KPL];
 #pragma unroll
       for (int q = 0; q < KPL; ++q) {
         const int c = lane + 64 * q;
-        if (c < k) {
-          T f0 = F[o0 + c], f1 = F[o1 + c], f2 = F[o2 + c], f3 = F[o3 + c];
-          acc[q] = fma(a0, f0, acc[q]);
-          acc[q] = fma(a1, f1, acc[q]);
-          acc[q] = fma(a2, f2, acc[q]);
-          acc[q] = fma(a3, f3, acc[q]);
+        const int cc = c < k ? c : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f[u][q] = F[o[u] + cc];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (rr[u] != cur_r) {  // rows are queued in order: flush on a change
+#pragma unroll
+          for (int q = 0; q < KPL; ++q) {
+            const int c = lane + 64 * q;
+            if (c < k) tile[c * RG + cur_r] += acc[q];
+            acc[q] = T(0);
+          }
+          cur_r = rr[u];
         }
-      }
-    }
-    for (; h < nh; ++h) {
-      const int32_t o = q_off[h];
-      const T av2 = q_a[h];
 #pragma unroll
-      for (int q = 0; q < KPL; ++q) {
-        const int c = lane + 64 * q;
-        if (c < k) acc[q] = fma(av2, F[o + c], acc[q]);
+        for (int q = 0; q < KPL; ++q) acc[q] = fma(aa[u], f[u][q], acc[q]);
       }
     }
+  }
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    if (c < k) tile[c * RG + cur_r] += acc[q];
   }
 }
 
@@ -139,129 +223,155 @@ __device__ __forceinline__ void epilogue(const SpmmArgs& a, const T* tile, const
 #pragma unroll
     for (int q = 0; q < KPL; ++q) out[r][q] = 0.0;
   for (int rr = 0; rr < k; ++rr) {
-    double w[KPL];
+    double wv[KPL];
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
-      w[q] = c < k ? sW[rr * k + c] : 0.0;
+      wv[q] = c < k ? sW[rr * k + c] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
       const double b = static_cast<double>(tile[rr * RG + r]);
 #pragma unroll
-      for (int q = 0; q < KPL; ++q) out[r][q] = fma(b, w[q], out[r][q]);
+      for (int q = 0; q < KPL; ++q) out[r][q] = fma(b, wv[q], out[r][q]);
     }
   }
-  for (int r = 0; r < nrows; ++r) {
 #pragma unroll
-    for (int q = 0; q < KPL; ++q) {
-      const int c = lane + 64 * q;
-      if (c < k) {
-        const double x = out[r][q];
-        const int64_t o = static_cast<int64_t>(r0 + r) * k + c;
-        X[o] = static_cast<T>(x > 0.0 ? x : 0.0);
-        if (STORE_C) static_cast<T*>(a.C)[o] = tile[c * RG + r];
+  for (int r = 0; r < RG; ++r) {
+    if (r < nrows) {
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) {
+        const int c = lane + 64 * q;
+        if (c < k) {
+          const double x = out[r][q];
+          const int64_t o = static_cast<int64_t>(r0 + r) * k + c;
+          X[o] = static_cast<T>(x > 0.0 ? x : 0.0);
+          if (STORE_C) static_cast<T*>(a.C)[o] = tile[c * RG + r];
+        }
       }
     }
   }
 }
 
+template <typename T, int KPL, int RG>
+__device__ __forceinline__ void clear_tile(T* tile, int k) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    if (c < k) {
+#pragma unroll
+      for (int r = 0; r < RG; ++r) tile[c * RG + r] = T(0);
+    }
+  }
+}
+
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN>
-__global__ __launch_bounds__(256) void k_spmm(SpmmArgs a) {
+__global__ __launch_bounds__(512) void k_spmm(SpmmArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
   const int k = a.k;
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   double* sW = reinterpret_cast<double*>(smem);
-  unsigned char* wbase = smem + (RAW ? 0 : static_cast<size_t>(k) * k * sizeof(double));
-  unsigned char* mine = wbase + wv * spmm_per_wave<T, RG>(k);
-  int32_t* q_off = reinterpret_cast<int32_t*>(mine);
-  T* q_a = reinterpret_cast<T*>(mine + 64 * sizeof(int32_t));
-  T* tile = reinterpret_cast<T*>(mine + 64 * sizeof(int32_t) + 64 * sizeof(T));
+  const WaveLds w = wave_lds<T, RG>(smem, k, RAW, wv);
+  T* tile = static_cast<T*>(w.tile);
   if (!RAW) {
     for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
   }
   __syncthreads();
 
-  const int nw = gridDim.x * 4;
-  for (int it = blockIdx.x * 4 + wv; it < a.n_items; it += nw) {
+  const int nw = gridDim.x * kWaves;
+  for (int it = blockIdx.x * kWaves + wv; it < a.n_items; it += nw) {
     const WorkItem wi = a.items[it];
+    clear_tile<T, KPL, RG>(tile, k);
     if (wi.heavy < 0) {
       const int nrows = wi.r1 - wi.r0;
       if (nrows > RG) {  // a plan built for another row group: refuse, never overrun the tile
-        if (lane == 0) atomicCAS(a.status_w, 0, static_cast<int32_t>(NMF_ERR_DEVICE));
+        if (lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_DEVICE));
         continue;
       }
-      for (int r = 0; r < nrows; ++r) {
-        T acc[KPL];
+      int64_t rb[RG + 1];
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) acc[q] = T(0);
-        accumulate<T, KPL>(a, a.rowptr[wi.r0 + r], a.rowptr[wi.r0 + r + 1], acc, q_off, q_a,
-                           DENSE_IN);
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-          const int c = lane + 64 * q;
-          if (c < k) tile[c * RG + r] = acc[q];
-        }
-      }
+      for (int i = 0; i <= RG; ++i) rb[i] = a.rowptr[wi.r0 + (i < nrows ? i : nrows)];
+      accumulate<T, KPL, RG, DENSE_IN>(a, rb[0], rb[nrows], rb, nrows, w);
       epilogue<T, KPL, RG, RAW, STORE_C>(a, tile, sW, nrows, wi.r0);
     } else {
-      T acc[KPL];
+      int64_t rb[RG + 1];
 #pragma unroll
-      for (int q = 0; q < KPL; ++q) acc[q] = T(0);
-      accumulate<T, KPL>(a, wi.p0, wi.p1, acc, q_off, q_a, DENSE_IN);
+      for (int i = 0; i <= RG; ++i) rb[i] = i == 0 ? wi.p0 : wi.p1;
+      accumulate<T, KPL, RG, DENSE_IN>(a, wi.p0, wi.p1, rb, 1, w);
       T* part = static_cast<T*>(a.partials);
 #pragma unroll
       for (int q = 0; q < KPL; ++q) {
         const int c = lane + 64 * q;
-        if (c < k) part[static_cast<int64_t>(wi.part) * k + c] = acc[q];
-      }
-      fence_release();
-      int tk = 0;
-      if (lane == 0) tk = atomicAdd(&a.heavy_ticket[wi.heavy], 1);
-      tk = bcast_i32(tk, 0);
-      const int nch = a.heavy_nchunks[wi.heavy];
-      if (tk == nch - 1) {
-        fence_acquire();
-        const int32_t p0 = a.heavy_part0[wi.heavy];
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) acc[q] = T(0);
-        for (int j = 0; j < nch; ++j) {
-#pragma unroll
-          for (int q = 0; q < KPL; ++q) {
-            const int c = lane + 64 * q;
-            if (c < k) {
-              const T v = __builtin_nontemporal_load(&part[static_cast<int64_t>(p0 + j) * k + c]);
-              acc[q] += v;
-            }
-          }
-        }
-        if (lane == 0) a.heavy_ticket[wi.heavy] = 0;
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-          const int c = lane + 64 * q;
-          if (c < k) tile[c * RG + 0] = acc[q];
-        }
-        epilogue<T, KPL, RG, RAW, STORE_C>(a, tile, sW, 1, wi.r0);
+        if (c < k) part[static_cast<int64_t>(wi.part) * k + c] = tile[c * RG];
       }
     }
+  }
+}
+
+// Long rows: add the pieces' raw sums in piece order, then the epilogue.
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C>
+__global__ __launch_bounds__(512) void k_spmm_heavy(SpmmArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (*a.status != 0) return;
+  const int k = a.k;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  double* sW = reinterpret_cast<double*>(smem);
+  const WaveLds w = wave_lds<T, RG>(smem, k, RAW, wv);
+  T* tile = static_cast<T*>(w.tile);
+  if (!RAW) {
+    for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
+  }
+  __syncthreads();
+  const T* part = static_cast<const T*>(a.partials);
+  const int nw = gridDim.x * kWaves;
+  for (int hh = blockIdx.x * kWaves + wv; hh < a.n_heavy; hh += nw) {
+    const int nch = a.heavy_nchunks[hh];
+    const int p0 = a.heavy_part0[hh];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      if (c < k) {
+        T s = T(0);
+        int j = 0;
+        for (; j + 8 <= nch; j += 8) {  // eight loads in flight, added in order
+          T v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = part[static_cast<int64_t>(p0 + j + u) * k + c];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; j < nch; ++j) s += part[static_cast<int64_t>(p0 + j) * k + c];
+        tile[c * RG] = s;
+      }
+    }
+    epilogue<T, KPL, RG, RAW, STORE_C>(a, tile, sW, 1, a.heavy_row[hh]);
   }
 }
 
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN>
 hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
   const size_t lds = spmm_lds_bytes<T, RG>(a.k, RAW);
-  auto kern = k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN>;
-  if (a.n_items == 0) return hipSuccess;
-  // several resident blocks per CU; the LDS footprint decides how many fit
-  int per_cu = static_cast<int>((160 * 1024) / (lds + 1024));
+  int per_cu = static_cast<int>((160 * 1024) / (lds + 512));
   if (per_cu < 1) per_cu = 1;
-  if (per_cu > 8) per_cu = 8;
-  int blocks = (a.n_items + 3) / 4;
-  const int cap = h->num_cus * per_cu;
-  if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, h->stream, a);
+  if (per_cu > 4) per_cu = 4;
+  if (a.n_items > 0) {
+    int blocks = (a.n_items + kWaves - 1) / kWaves;
+    const int cap = h->num_cus * per_cu;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL((k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN>), dim3(blocks), dim3(64 * kWaves), lds,
+                       h->stream, a);
+  }
+  if (a.n_heavy > 0) {
+    int blocks = (a.n_heavy + kWaves - 1) / kWaves;
+    const int cap = h->num_cus * per_cu;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL((k_spmm_heavy<T, KPL, RG, RAW, STORE_C>), dim3(blocks), dim3(64 * kWaves), lds,
+                       h->stream, a);
+  }
   return hipGetLastError();
 }
 
@@ -269,25 +379,27 @@ hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
 
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                bool raw, const T* dense_in) {
+                bool raw, const T* dense_in, int sparse_row) {
   SpmmArgs a{};
   a.rowptr = p.rowptr;
   a.col = p.col;
   a.val = p.val;
   a.items = p.items;
   a.n_items = p.n_items;
-  a.heavy_ticket = p.heavy_ticket;
+  a.heavy_row = p.heavy_row;
   a.heavy_nchunks = p.heavy_nchunks;
   a.heavy_part0 = p.heavy_part0;
+  a.n_heavy = p.n_heavy;
   a.partials = p.partials;
-  a.slot = dense_in ? nullptr : F.slot;
+  a.meta = dense_in ? nullptr : F.meta;
+  a.sparse_row = sparse_row;
+  a.ents = F.packed;
   a.F = dense_in ? static_cast<const void*>(dense_in) : static_cast<const void*>(F.dense);
   a.W = W;
   a.X = X;
   a.C = C;
   a.k = h->k;
   a.status = h->status;
-  a.status_w = h->status;
   const bool two = h->k > 64;
   const bool dense = dense_in != nullptr;
   if (raw) {
@@ -301,8 +413,8 @@ hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, 
 }
 
 template hipError_t spmm<float>(nmf_handle*, const Plan&, const Factor&, const double*, float*,
-                                float*, bool, const float*);
+                                float*, bool, const float*, int);
 template hipError_t spmm<double>(nmf_handle*, const Plan&, const Factor&, const double*, double*,
-                                 double*, bool, const double*);
+                                 double*, bool, const double*, int);
 
 }  // namespace nmfk

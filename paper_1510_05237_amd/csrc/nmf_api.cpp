@@ -74,7 +74,7 @@ PlanSizes plan_bounds(int64_t rows, int64_t nnz) {
 
 struct HostPlan {
   std::vector<WorkItem> items;
-  std::vector<int32_t> nchunks, part0;
+  std::vector<int32_t> rows, nchunks, part0;
   int32_t parts = 0;
 };
 
@@ -89,6 +89,7 @@ HostPlan build_plan(const int64_t* rp, int64_t rows, int max_rows) {
     if (len > kChunk) {
       const int32_t nch = static_cast<int32_t>((len + kChunk - 1) / kChunk);
       const int32_t hidx = static_cast<int32_t>(p.nchunks.size());
+      p.rows.push_back(static_cast<int32_t>(r));
       p.nchunks.push_back(nch);
       p.part0.push_back(p.parts);
       for (int32_t j = 0; j < nch; ++j) {
@@ -151,7 +152,7 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
     Plan& p = o == 0 ? h->planA : h->planAt;
     const PlanSizes& s = o == 0 ? pa : pt;
     p.items = cv.take<WorkItem>(s.items);
-    p.heavy_ticket = cv.take<int32_t>(s.heavy);
+    p.heavy_row = cv.take<int32_t>(s.heavy);
     p.heavy_nchunks = cv.take<int32_t>(s.heavy);
     p.heavy_part0 = cv.take<int32_t>(s.heavy);
     p.partials = cv.take<char>(s.parts * k * elt);
@@ -165,6 +166,8 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
     f.rowid = cv.take<int32_t>(rows);
     f.dense = cv.take<char>(rows * k * elt);
     f.counts = cv.take<int32_t>(4);
+    f.meta = cv.take<int2>(rows);
+    f.packed = cv.take<char>(rows * k * 2 * elt);
   };
   factor(h->U[0], n);
   factor(h->U[1], n);
@@ -253,6 +256,44 @@ nmf_status sync_status(nmf_handle* h) {
   return NMF_OK;
 }
 
+// ---- stage timing: events in a pool; interval i = (event i-1, event i)
+constexpr size_t kProfPool = 1024;
+
+nmf_status prof_fold(nmf_handle* h) {
+  if (h->prof_used == 0) return NMF_OK;
+  HIPCHK(h, hipEventSynchronize(h->prof_ev[h->prof_used - 1]));
+  for (size_t i = 1; i < h->prof_used; ++i) {
+    const int st = h->prof_stage[i];
+    if (st < 0) continue;
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->prof_ev[i - 1], h->prof_ev[i]));
+    h->prof_ms[st] += ms;
+    h->prof_cnt[st] += 1;
+  }
+  h->prof_used = 0;
+  return NMF_OK;
+}
+
+// Record an event closing `stage` (-1: an opening mark).
+nmf_status prof_mark(nmf_handle* h, int stage) {
+  if (!h->prof_on) return NMF_OK;
+  if (h->prof_used == kProfPool) {
+    nmf_status s = prof_fold(h);
+    if (s != NMF_OK) return s;
+  }
+  if (h->prof_used == 0) stage = -1;
+  HIPCHK(h, hipEventRecord(h->prof_ev[h->prof_used], h->stream));
+  h->prof_stage[h->prof_used] = stage;
+  ++h->prof_used;
+  return NMF_OK;
+}
+
+#define PROF(h, st)                          \
+  do {                                       \
+    nmf_status ps_ = prof_mark((h), (st));   \
+    if (ps_ != NMF_OK) return ps_;           \
+  } while (0)
+
 // Load a dense rows x k factor (host or device) into a stored factor.
 template <typename T>
 nmf_status load_factor(nmf_handle* h, const void* src, Factor& f) {
@@ -273,7 +314,7 @@ nmf_status load_factor(nmf_handle* h, const void* src, Factor& f) {
     if (flag) return fail(h, NMF_ERR_INVALID_INPUT, "factor has a negative or non-finite value");
   }
   HIPCHK(h, mark_nonzero<T>(h, stage, f.rows));
-  HIPCHK(h, repack<T>(h, stage, f.rows, f));
+  HIPCHK(h, repack<T>(h, stage, f.rows, f, (&f == &h->V) ? h->sparse_row[1] : h->sparse_row[0]));
   return NMF_OK;
 }
 
@@ -294,10 +335,15 @@ template <typename T>
 nmf_status v_half(nmf_handle* h) {
   Factor& U = h->U[h->cur_u];
   T* vpre = static_cast<T*>(h->vpre);
-  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr));
+  PROF(h, -1);
+  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr, h->sparse_row[0]));
+  PROF(h, NMF_STAGE_SPMM_V);
   HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
-  HIPCHK(h, repack<T>(h, vpre, h->m, h->V));
+  PROF(h, NMF_STAGE_SELECT_V);
+  HIPCHK(h, repack<T>(h, vpre, h->m, h->V, h->sparse_row[1]));
+  PROF(h, NMF_STAGE_REPACK_V);
   HIPCHK(h, gram<T>(h, h->V, h->gV));
+  PROF(h, NMF_STAGE_GRAM_V);
   h->have_v = true;
   h->have_pre_v = true;
   return NMF_OK;
@@ -309,10 +355,14 @@ nmf_status u_half(nmf_handle* h, bool keep_c) {
   Factor& Un = h->U[nxt];
   T* upre = static_cast<T*>(h->upre);
   HIPCHK(h, spmm<T>(h, h->planA, h->V, h->gV.W, upre, keep_c ? static_cast<T*>(h->cbuf) : nullptr,
-                    false, nullptr));
+                    false, nullptr, h->sparse_row[1]));
+  PROF(h, NMF_STAGE_SPMM_U);
   HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
-  HIPCHK(h, repack<T>(h, upre, h->n, Un));
+  PROF(h, NMF_STAGE_SELECT_U);
+  HIPCHK(h, repack<T>(h, upre, h->n, Un, h->sparse_row[0]));
+  PROF(h, NMF_STAGE_REPACK_U);
   HIPCHK(h, gram<T>(h, Un, h->gU));
+  PROF(h, NMF_STAGE_GRAM_U);
   h->have_pre_u = true;
   return NMF_OK;
 }
@@ -327,6 +377,7 @@ nmf_status do_steps(nmf_handle* h, int32_t iters) {
     if (s != NMF_OK) return s;
     const int nxt = 1 - h->cur_u;
     HIPCHK(h, metrics<T>(h, h->U[nxt], h->U[h->cur_u], rec ? static_cast<T*>(h->cbuf) : nullptr, rec));
+    PROF(h, NMF_STAGE_METRICS);
     h->cur_u = nxt;
     ++h->iters_done;
     h->metrics_valid = rec;
@@ -404,7 +455,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
     if (!hp.nchunks.empty()) {
       HIPCHK(h, hipMemcpy(p.heavy_nchunks, hp.nchunks.data(), hp.nchunks.size() * 4, hipMemcpyHostToDevice));
       HIPCHK(h, hipMemcpy(p.heavy_part0, hp.part0.data(), hp.part0.size() * 4, hipMemcpyHostToDevice));
-      HIPCHK(h, hipMemset(p.heavy_ticket, 0, hp.nchunks.size() * 4));
+      HIPCHK(h, hipMemcpy(p.heavy_row, hp.rows.data(), hp.rows.size() * 4, hipMemcpyHostToDevice));
     }
     return NMF_OK;
   };
@@ -464,7 +515,7 @@ nmf_status do_error(nmf_handle* h, double* E) {
   }
   // on demand: C = A V (raw), then ||A||^2 - 2 <U, C> + <G_U, G_V>
   T* C = static_cast<T*>(h->cbuf);
-  HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr));
+  HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr, h->sparse_row[1]));
   HIPCHK(h, densify<T>(h, h->U[h->cur_u], static_cast<T*>(h->lossC)));
   HIPCHK(h, loss_dot<T>(h, static_cast<const T*>(h->lossC), C, h->gU.G, h->gV.G, h->met.out));
   s = sync_status(h);
@@ -690,12 +741,12 @@ nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* los
   double* GU = h->lossG;
   double* GV = h->lossG + static_cast<size_t>(h->k) * h->k;
   if (h->elt == 8) {
-    HIPCHK(h, spmm<double>(h, h->planA, h->V, nullptr, static_cast<double*>(h->lossC), nullptr, true, static_cast<const double*>(V)));
+    HIPCHK(h, spmm<double>(h, h->planA, h->V, nullptr, static_cast<double*>(h->lossC), nullptr, true, static_cast<const double*>(V), 0));
     HIPCHK(h, gram_dense<double>(h, static_cast<const double*>(U), h->n, GU));
     HIPCHK(h, gram_dense<double>(h, static_cast<const double*>(V), h->m, GV));
     HIPCHK(h, loss_dot<double>(h, static_cast<const double*>(U), static_cast<const double*>(h->lossC), GU, GV, loss_dev));
   } else {
-    HIPCHK(h, spmm<float>(h, h->planA, h->V, nullptr, static_cast<float*>(h->lossC), nullptr, true, static_cast<const float*>(V)));
+    HIPCHK(h, spmm<float>(h, h->planA, h->V, nullptr, static_cast<float*>(h->lossC), nullptr, true, static_cast<const float*>(V), 0));
     HIPCHK(h, gram_dense<float>(h, static_cast<const float*>(U), h->n, GU));
     HIPCHK(h, gram_dense<float>(h, static_cast<const float*>(V), h->m, GV));
     HIPCHK(h, loss_dot<float>(h, static_cast<const float*>(U), static_cast<const float*>(h->lossC), GU, GV, loss_dev));
@@ -711,27 +762,92 @@ nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const doubl
   if (h->elt == 8) {
     using T = double;
     if (gU) {
-      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, static_cast<T*>(h->lossC), nullptr, true, static_cast<const T*>(V)));
+      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, static_cast<T*>(h->lossC), nullptr, true, static_cast<const T*>(V), 0));
       HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(V), h->m, GV));
       HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(U), static_cast<const T*>(h->lossC), GV, g_scale, h->n, static_cast<T*>(gU)));
     }
     if (gV) {
-      HIPCHK(h, spmm<T>(h, h->planAt, h->U[0], nullptr, static_cast<T*>(h->lossB), nullptr, true, static_cast<const T*>(U)));
+      HIPCHK(h, spmm<T>(h, h->planAt, h->U[0], nullptr, static_cast<T*>(h->lossB), nullptr, true, static_cast<const T*>(U), 0));
       HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(U), h->n, GU));
       HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(V), static_cast<const T*>(h->lossB), GU, g_scale, h->m, static_cast<T*>(gV)));
     }
   } else {
     using T = float;
     if (gU) {
-      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, static_cast<T*>(h->lossC), nullptr, true, static_cast<const T*>(V)));
+      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, static_cast<T*>(h->lossC), nullptr, true, static_cast<const T*>(V), 0));
       HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(V), h->m, GV));
       HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(U), static_cast<const T*>(h->lossC), GV, g_scale, h->n, static_cast<T*>(gU)));
     }
     if (gV) {
-      HIPCHK(h, spmm<T>(h, h->planAt, h->U[0], nullptr, static_cast<T*>(h->lossB), nullptr, true, static_cast<const T*>(U)));
+      HIPCHK(h, spmm<T>(h, h->planAt, h->U[0], nullptr, static_cast<T*>(h->lossB), nullptr, true, static_cast<const T*>(U), 0));
       HIPCHK(h, gram_dense<T>(h, static_cast<const T*>(U), h->n, GU));
       HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(V), static_cast<const T*>(h->lossB), GU, g_scale, h->m, static_cast<T*>(gV)));
     }
+  }
+  return NMF_OK;
+}
+
+// Rebuild a stored factor (0: U, 1: V) from its dense form so that its
+// gather metadata matches the current thresholds.
+nmf_status reload_meta(nmf_handle* h, int which) {
+  if (which == 1 && !h->have_v) return NMF_OK;
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  Factor& F = which == 0 ? h->U[h->cur_u] : h->V;
+  void* stage = h->sel.candA;  // rows x k scratch, free between selections
+  if (h->elt == 8) {
+    HIPCHK(h, densify<double>(h, F, static_cast<double*>(stage)));
+    HIPCHK(h, mark_nonzero<double>(h, static_cast<double*>(stage), F.rows));
+    HIPCHK(h, repack<double>(h, static_cast<double*>(stage), F.rows, F, h->sparse_row[which == 0 ? 0 : 1]));
+  } else {
+    HIPCHK(h, densify<float>(h, F, static_cast<float*>(stage)));
+    HIPCHK(h, mark_nonzero<float>(h, static_cast<float*>(stage), F.rows));
+    HIPCHK(h, repack<float>(h, static_cast<float*>(stage), F.rows, F, h->sparse_row[which == 0 ? 0 : 1]));
+  }
+  return sync_status(h);
+}
+
+nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  switch (param) {
+    case NMF_PARAM_SPARSE_ROW_V:
+    case NMF_PARAM_SPARSE_ROW_U:
+      if (value < 0 || value > kMaxK) return fail(h, NMF_ERR_INVALID_ARG, "sparse-row threshold out of range");
+      h->sparse_row[param] = static_cast<int>(value);
+      // the stored factor's gather metadata depends on the threshold:
+      // rebuild it for the factor this half-step gathers
+      return param == NMF_PARAM_SPARSE_ROW_V ? reload_meta(h, 0) : reload_meta(h, 1);
+    default:
+      return fail(h, NMF_ERR_INVALID_ARG, "unknown parameter");
+  }
+}
+
+nmf_status nmf_profile(nmf_handle* h, int32_t enable) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  if (h->prof_ev.empty()) {
+    h->prof_ev.resize(kProfPool);
+    h->prof_stage.resize(kProfPool, -1);
+    for (auto& e : h->prof_ev) HIPCHK(h, hipEventCreate(&e));
+  }
+  nmf_status s = prof_fold(h);
+  if (s != NMF_OK) return s;
+  h->prof_on = enable != 0;
+  if (h->prof_on)
+    for (int i = 0; i < NMF_NUM_STAGES; ++i) {
+      h->prof_ms[i] = 0;
+      h->prof_cnt[i] = 0;
+    }
+  return NMF_OK;
+}
+
+nmf_status nmf_profile_read(nmf_handle* h, double* ms, int64_t* count, int32_t n_stages) {
+  if (h == nullptr || n_stages < 0 || n_stages > NMF_NUM_STAGES) return fail(h, NMF_ERR_INVALID_ARG, "bad argument");
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  nmf_status s = prof_fold(h);
+  if (s != NMF_OK) return s;
+  for (int i = 0; i < n_stages; ++i) {
+    if (ms) ms[i] = h->prof_ms[i];
+    if (count) count[i] = h->prof_cnt[i];
   }
   return NMF_OK;
 }
@@ -743,6 +859,7 @@ const char* nmf_last_error(const nmf_handle* h) {
 void nmf_destroy(nmf_handle* h) {
   if (h == nullptr) return;
   (void)hipStreamSynchronize(h->stream);
+  for (auto& e : h->prof_ev) (void)hipEventDestroy(e);
   delete h;
 }
 

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/nmf.h"
 
@@ -14,7 +15,7 @@ namespace nmfk {
 
 constexpr int kMaxK = 128;       // topics supported (2 per lane at most)
 constexpr int kWave = 64;        // CDNA wavefront width
-constexpr int kChunk = 4096;     // nonzeros per SpMM work item; longer rows are split
+constexpr int kChunk = 2048;     // nonzeros per SpMM work item; longer rows are split
 constexpr int kRowGroup = 8;     // rows per light SpMM work item when k <= 64
 
 // Rows one SpMM epilogue batch holds (and so the most rows a light work item
@@ -33,8 +34,8 @@ enum { H_E = 0, H_R, H_NNZU, H_NNZV, H_DEADU, H_DEADV, H_FIELDS };
 // One unit of SpMM work for one wave.
 //  light (heavy < 0): output rows [r0, r1), every row at most kChunk long.
 //  heavy (heavy >= 0): nonzeros [p0, p1) of row r0, one chunk of a long row;
-//    its partial sum goes to partial slot `part`; the last chunk to finish
-//    (ticket) adds the row's partials in chunk order and runs the epilogue.
+//    its raw sum goes to partial slot `part`; a second kernel adds the row's
+//    partials in chunk order and runs the epilogue.
 struct WorkItem {
   int32_t r0, r1;
   int64_t p0, p1;
@@ -52,7 +53,7 @@ struct Plan {
   int32_t n_items = 0;
   int32_t n_heavy = 0;
   int32_t n_parts = 0;
-  int32_t* heavy_ticket = nullptr;   // [n_heavy], zero between launches
+  int32_t* heavy_row = nullptr;      // [n_heavy] row of each long row
   int32_t* heavy_nchunks = nullptr;  // [n_heavy]
   int32_t* heavy_part0 = nullptr;    // [n_heavy]
   void* partials = nullptr;          // [n_parts][k] T
@@ -69,7 +70,21 @@ struct Factor {
   int32_t* rowid = nullptr;    // [rows]: compact row index -> row
   void* dense = nullptr;       // [rows][k] T: compact dense rows 0..R-1
   int32_t* counts = nullptr;   // device [0] = nnz, [1] = R (nonempty rows)
+  // SpMM gather metadata: per row {compact dense row (rows with more entries
+  // than the gathering SpMM's threshold) or first stored entry, entry count};
+  // per entry {value, topic}
+  int2* meta = nullptr;        // [rows]
+  void* packed = nullptr;      // [rows * k] FactorEnt<T>
 };
+
+// One stored factor entry as the SpMM gathers it (8 bytes for float).
+template <typename T>
+struct FactorEnt {
+  T v;
+  uint32_t t;
+};
+
+constexpr int kSparseRow = 3;  // default: factor rows with at most this many entries are gathered entry by entry
 
 // Gram matrix of a factor and its inverse.
 struct Gram {
@@ -87,7 +102,7 @@ struct ColSel {
 };
 
 struct SelectWs {
-  uint32_t* hist = nullptr;     // [k][kBins], zero between uses
+  uint32_t* hist = nullptr;     // [k][kBins], zero between uses (cleared by refine)
   ColSel* sel = nullptr;        // [k]
   int32_t* cand_cnt = nullptr;  // [k * kCntStride], zero between uses
   void* candA = nullptr;        // [k][rows_max] candidates (row, key)
@@ -147,6 +162,14 @@ struct nmf_handle {
   bool have_v = false;
   bool have_pre_v = false, have_pre_u = false;
   bool metrics_valid = false;  // the newest history record describes the current U, V
+  int sparse_row[2] = {nmfk::kSparseRow, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
+  // stage timing (nmf_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;      // pool
+  std::vector<int> prof_stage;          // stage of the interval ending at event i
+  size_t prof_used = 0;
+  double prof_ms[NMF_NUM_STAGES] = {0};
+  int64_t prof_cnt[NMF_NUM_STAGES] = {0};
   std::string last_error;
 };
 
@@ -156,14 +179,16 @@ namespace nmfk {
 // double.  All enqueue on h->stream and return hipSuccess or the launch error.
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                bool raw, const T* dense_in);
+                bool raw, const T* dense_in, int sparse_row);
 template <typename T>
 hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int mode,
                        const Factor& out_f);
 template <typename T>
 hipError_t mark_nonzero(nmf_handle* h, const T* X, int64_t rows);
+// sparse_row: the threshold of the SpMM that will gather this factor (it
+// decides what the per-row metadata points to).
 template <typename T>
-hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f);
+hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f, int sparse_row);
 template <typename T>
 hipError_t gram(nmf_handle* h, const Factor& F, const Gram& g);
 template <typename T>

@@ -89,6 +89,9 @@ SIGNATURES = {
     "nmf_get_pre": (_I32, [_P, _I32, _P]),
     "nmf_loss_fwd": (_I32, [_P, _P, _P, _P]),
     "nmf_loss_bwd": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "nmf_set_param": (_I32, [_P, _I32, _I64]),
+    "nmf_profile": (_I32, [_P, _I32]),
+    "nmf_profile_read": (_I32, [_P, _P, _P, _I32]),
     "nmf_last_error": (ctypes.c_char_p, [_P]),
     "nmf_destroy": (None, [_P]),
 }
@@ -224,6 +227,30 @@ def nmf_loss_bwd(h: int, U, V, g_scale, gU, gV):
     _check(load_library().nmf_loss_bwd(h, _ptr(U), _ptr(V), _ptr(g_scale), _ptr(gU), _ptr(gV)), h)
 
 
+NMF_PARAM_SPARSE_ROW_V = 0
+NMF_PARAM_SPARSE_ROW_U = 1
+
+
+def nmf_set_param(h: int, param: int, value: int):
+    _check(load_library().nmf_set_param(h, param, value), h)
+
+
+NMF_NUM_STAGES = 9
+STAGE_NAMES = ["spmm_v", "select_v", "repack_v", "gram_v", "spmm_u", "select_u", "repack_u", "gram_u",
+               "metrics"]
+
+
+def nmf_profile(h: int, enable: bool):
+    _check(load_library().nmf_profile(h, 1 if enable else 0), h)
+
+
+def nmf_profile_read(h: int):
+    ms = np.zeros(NMF_NUM_STAGES, np.float64)
+    cnt = np.zeros(NMF_NUM_STAGES, np.int64)
+    _check(load_library().nmf_profile_read(h, _ptr(ms), _ptr(cnt), NMF_NUM_STAGES), h)
+    return {STAGE_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(NMF_NUM_STAGES)}
+
+
 def nmf_last_error(h: Optional[int] = None) -> str:
     return load_library().nmf_last_error(h).decode()
 
@@ -319,6 +346,15 @@ class NMF:
 
     def set_factors(self, u, u_prev=None, v=None):
         nmf_set_factors(self.h, u, u_prev, v)
+
+    def set_param(self, param: int, value: int):
+        nmf_set_param(self.h, param, value)
+
+    def profile(self, enable: bool):
+        nmf_profile(self.h, enable)
+
+    def profile_read(self):
+        return nmf_profile_read(self.h)
 
     def close(self):
         if getattr(self, "h", None):
