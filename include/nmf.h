@@ -200,7 +200,14 @@ enum {
                                  gathered entry by entry, denser rows whole
                                  (0..128; default 3)                        */
   NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V             */
-  NMF_NUM_PARAMS = 2
+  NMF_PARAM_WIDE_V = 2,       /* V half SpMM step form: 0 = 64 nonzeros per
+                                 step with loads only on the lanes that need
+                                 them (default; suits factors whose gathered
+                                 rows are mostly dense), 1 = 128 nonzeros per
+                                 step with every load issued on all lanes
+                                 (suits very sparse gathered rows)          */
+  NMF_PARAM_WIDE_U = 3,       /* U half: the same (default 1)               */
+  NMF_NUM_PARAMS = 4
 };
 
 /* Set a tuning parameter of a handle (applies to later launches).

@@ -28,6 +28,7 @@ constexpr int kReduceEntries = 64;  // upper-triangle entries per reduce block
 
 struct GramArgs {
   const void* F;            // rows x k (compact rows of a factor, or a dense matrix)
+  int32_t ld;               // row pitch of F (>= k)
   const int32_t* rows_dev;  // number of rows (device), or nullptr
   int64_t rows_host;
   int32_t k;
@@ -85,21 +86,20 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) {
     const int nr = static_cast<int>(hi - r0 < kStageRows ? hi - r0 : kStageRows);
     __syncthreads();
     // the batch is contiguous in F: eight independent loads per thread
-    const int nel = nr * k;
+    const int ld = g.ld;
+    const int nel = nr * ld;
     for (int i0 = tid; i0 < nel; i0 += 256 * 8) {
       T v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i = i0 + 256 * u;
-        v[u] = i < nel ? F[r0 * k + i] : T(0);
+        v[u] = i < nel ? F[r0 * ld + i] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i = i0 + 256 * u;
-        if (i < nel) {
-          const int rr = i / k, c = i - rr * k;
-          stage[rr * kpad + c] = v[u];
-        }
+        const int rr = i / ld, c = i - rr * ld;
+        if (i < nel && c < k) stage[rr * kpad + c] = v[u];
       }
     }
     __syncthreads();
@@ -291,6 +291,7 @@ template <typename T>
 hipError_t gram(nmf_handle* h, const Factor& F, const Gram& out) {
   GramArgs g{};
   g.F = F.dense;
+  g.ld = F.ld;
   g.rows_dev = F.counts + 1;
   g.k = h->k;
   g.partials = h->gram_partials;
@@ -310,6 +311,7 @@ template <typename T>
 hipError_t gram_dense(nmf_handle* h, const T* F, int64_t rows, double* G) {
   GramArgs g{};
   g.F = F;
+  g.ld = h->k;
   g.rows_dev = nullptr;
   g.rows_host = rows;
   g.k = h->k;

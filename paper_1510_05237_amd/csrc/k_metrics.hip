@@ -55,6 +55,7 @@ struct MetArgs {
   const int32_t* slot_old;
   const void* dense_new;
   const void* dense_old;
+  int32_t ld;     // row pitch of dense_new / dense_old
   const void* C;  // raw A V (n x k), or nullptr
   double* partials;
   const double* GU;
@@ -115,8 +116,8 @@ __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
           for (int q = 0; q < KPL; ++q) {
             const int c = lane + 64 * q;
             const bool in = c < k;
-            un[u][q] = (in && s1 >= 0) ? static_cast<double>(Dn[static_cast<int64_t>(s1) * k + c]) : 0.0;
-            uo[u][q] = (in && s0 >= 0) ? static_cast<double>(Do[static_cast<int64_t>(s0) * k + c]) : 0.0;
+            un[u][q] = (in && s1 >= 0) ? static_cast<double>(Dn[static_cast<int64_t>(s1) * a.ld + c]) : 0.0;
+            uo[u][q] = (in && s0 >= 0) ? static_cast<double>(Do[static_cast<int64_t>(s0) * a.ld + c]) : 0.0;
             cv[u][q] = (in && s1 >= 0 && C != nullptr) ? static_cast<double>(C[(base + b) * k + c]) : 0.0;
           }
         }
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(256) void k_grad(const T* F, const T* B, const doub
 }
 
 template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_densify(const int32_t* slot, const T* dense, int64_t rows,
+__global__ __launch_bounds__(256) void k_densify(const int32_t* slot, const T* dense, int ld, int64_t rows,
                                                  int k, T* out) {
   const int lane = lane_id();
   const int64_t wg = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(256) void k_densify(const int32_t* slot, const T* d
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
-      if (c < k) out[r * k + c] = s >= 0 ? dense[static_cast<int64_t>(s) * k + c] : T(0);
+      if (c < k) out[r * k + c] = s >= 0 ? dense[static_cast<int64_t>(s) * ld + c] : T(0);
     }
   }
 }
@@ -318,6 +319,7 @@ hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const 
   a.slot_new = Unew.slot;
   a.slot_old = Uold.slot;
   a.dense_new = Unew.dense;
+  a.ld = Unew.ld;
   a.dense_old = Uold.dense;
   a.C = C;
   a.partials = h->met.partials;
@@ -369,10 +371,10 @@ hipError_t densify(nmf_handle* h, const Factor& F, T* out) {
   const int blocks = grid_for(F.rows, 4, h->num_cus * 8);
   if (h->k > 64)
     hipLaunchKernelGGL((k_densify<T, 2>), dim3(blocks), dim3(256), 0, h->stream, F.slot,
-                       static_cast<const T*>(F.dense), F.rows, h->k, out);
+                       static_cast<const T*>(F.dense), F.ld, F.rows, h->k, out);
   else
     hipLaunchKernelGGL((k_densify<T, 1>), dim3(blocks), dim3(256), 0, h->stream, F.slot,
-                       static_cast<const T*>(F.dense), F.rows, h->k, out);
+                       static_cast<const T*>(F.dense), F.ld, F.rows, h->k, out);
   return hipGetLastError();
 }
 

@@ -144,6 +144,7 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
   // nonempty row
   const int lane = lane_id();
   const int wv = tid >> 6;
+  const int ld = a.F.ld;
   const T* __restrict__ X = static_cast<const T*>(a.X);
   T* __restrict__ dense = static_cast<T*>(a.F.dense);
   T* __restrict__ fval = static_cast<T*>(a.F.val);
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
 #pragma unroll
         for (int q = 0; q < KPL; ++q) {
           const int c = lane + 64 * q;
-          if (c < k) {
+          if (c < ld) {  // columns k..ld-1 of the dense copy are padding: no bit is set there
             uint32_t word = 0;
             int below = 0;
 #pragma unroll
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
             }
             const bool bit = (word >> (c & 31)) & 1u;
             const T v = bit ? xv[u][q] : T(0);
-            dense[static_cast<int64_t>(s) * k + c] = v;
+            dense[static_cast<int64_t>(s) * ld + c] = v;
             if (bit) {
               below += __popc(word & ((1u << (c & 31)) - 1u));
               fval[base + below] = v;

@@ -10,40 +10,51 @@
 //
 // Work items (built once per orientation of A): up to RG consecutive short
 // rows with at most kChunk nonzeros in total, or one kChunk-long piece of a
-// long (Zipf-heavy) row.  Per item, per 64 nonzeros (lanes span the item's
-// rows):
+// long (Zipf-heavy) row.  One wave owns an item and its accumulator (in LDS).
+// Per step of 64 nonzeros (lanes span the item's rows; the wide form takes
+// two per lane):
 //  * lanes = nonzeros: coalesced loads of (col, a) and one 8-byte gather of
 //    the factor row's metadata {where, how many entries};
 //  * factor rows with at most `sparse_row` entries are gathered entry by entry
 //    (one {value, topic} load per entry, lanes still = nonzeros) and each
-//    product is added into the wave's LDS accumulator at (row, topic).  One
-//    wave owns the accumulator and LDS executes a wave's instructions in
-//    order, so the sums are reproducible;
-//  * denser factor rows are queued and then read as whole k-wide rows from
-//    the compact dense copy of the factor, lanes = topics: one coalesced load
-//    and one FMA per lane per row, eight rows in flight;
+//    product is added into the accumulator at (row, topic) with an LDS atomic;
+//  * denser factor rows are queued in row order and then read whole from the
+//    compact dense copy of the factor, lanes = topics, eight rows in flight;
+//    the running sums for the current row stay in registers and go to the
+//    accumulator when the row changes;
 //  * the epilogue multiplies the item's raw row sums by W (float64, in LDS),
 //    clamps at zero, rounds to T and stores whole rows.
 // Pieces of long rows store their raw sums; k_spmm_heavy adds them in piece
-// order and runs the same epilogue.
+// order and runs the same epilogue.  One wave owns each accumulator and LDS
+// executes a wave's instructions in order, so the sums are reproducible.
 #include "nmf_device.h"
 
 namespace nmfk {
 
 namespace {
 
-constexpr int kWaves = 8;  // waves per block
-
-template <typename T, int RG>
-__host__ __device__ inline size_t spmm_per_wave(int k) {
-  const int kpad = (k + 3) & ~3;
-  return 64 * (2 * sizeof(int32_t) + sizeof(T)) + static_cast<size_t>(RG) * kpad * sizeof(T);
+constexpr int kWaves = 8;  // waves per block (fewer when W and the wave buffers exceed the LDS)
+constexpr size_t kLdsBytes = 160 * 1024;
+// Dense-row queue: one step's hits (64, or 128 in the wide form) padded to
+// whole batches of 8.
+template <bool WIDE>
+constexpr int queue_len() {
+  return WIDE ? 136 : 64;
 }
 
-template <typename T, int RG>
-size_t spmm_lds_bytes(int k, bool raw) {
+__host__ __device__ inline int tile_pitch(int k) { return (k + 3) & ~3; }
+
+template <typename T, int RG, bool WIDE>
+__host__ __device__ inline size_t spmm_per_wave(int k) {
+  return queue_len<WIDE>() * (2 * sizeof(int32_t) + sizeof(T)) +
+         static_cast<size_t>(RG) * tile_pitch(k) * sizeof(T);
+}
+
+// LDS of one block: W (unless raw), then each wave's buffers.
+template <typename T, int RG, bool WIDE>
+size_t spmm_lds_bytes(int k, bool raw, int waves) {
   const size_t w = raw ? 0 : static_cast<size_t>(k) * k * sizeof(double);
-  return w + kWaves * spmm_per_wave<T, RG>(k);
+  return w + waves * spmm_per_wave<T, RG, WIDE>(k);
 }
 
 struct SpmmArgs {
@@ -57,10 +68,11 @@ struct SpmmArgs {
   const int32_t* heavy_part0;
   int32_t n_heavy;
   void* partials;
-  const int2* meta;   // factor row metadata {dense row or first entry, entry count}
+  const int2* meta;    // factor row metadata {dense row or first entry, entry count}
   int32_t sparse_row;  // rows with at most this many entries are gathered entry by entry
-  const void* ents;   // stored factor entries {value, topic}
-  const void* F;      // compact dense factor rows (or the dense input)
+  const void* ents;    // stored factor entries {value, topic}
+  const void* F;       // compact dense factor rows (or the dense input)
+  int32_t ld;          // row pitch of F
   const double* W;
   void* X;
   void* C;
@@ -69,29 +81,141 @@ struct SpmmArgs {
 };
 
 struct WaveLds {
-  int32_t* q_off;
-  int32_t* q_row;
-  void* q_a;
-  void* tile;
+  int32_t* q_off;  // dense-row queue: offset of the factor row in F
+  int32_t* q_row;  //                  row within the item
+  void* q_a;       //                  the nonzero's value
+  void* tile;      // accumulator: tile[topic * RG + row]
 };
 
-template <typename T, int RG>
-__device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, int k, bool raw, int wv) {
-  unsigned char* base = smem + (raw ? 0 : static_cast<size_t>(k) * k * sizeof(double)) +
-                        wv * spmm_per_wave<T, RG>(k);
+template <typename T, int RG, bool WIDE>
+__device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, size_t wave0, int k, int wv) {
+  constexpr int Q = queue_len<WIDE>();
+  unsigned char* base = smem + wave0 + wv * spmm_per_wave<T, RG, WIDE>(k);
   WaveLds w;
   w.q_off = reinterpret_cast<int32_t*>(base);
-  w.q_row = reinterpret_cast<int32_t*>(base + 64 * sizeof(int32_t));
-  w.q_a = base + 128 * sizeof(int32_t);
-  w.tile = base + 128 * sizeof(int32_t) + 64 * sizeof(T);
+  w.q_row = reinterpret_cast<int32_t*>(base + Q * sizeof(int32_t));
+  w.q_a = base + 2 * Q * sizeof(int32_t);
+  w.tile = base + Q * (2 * sizeof(int32_t) + sizeof(T));
   return w;
 }
 
+// Block prologue: W into LDS (unless raw); returns the LDS offset of the
+// waves' buffers.
+template <bool RAW>
+__device__ __forceinline__ size_t load_block(const SpmmArgs& a, unsigned char* smem) {
+  const int k = a.k;
+  if (!RAW) {
+    double* sW = reinterpret_cast<double*>(smem);
+    for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
+  }
+  __syncthreads();
+  return RAW ? 0 : static_cast<size_t>(k) * k * sizeof(double);
+}
+
+// Adds one part of the queue (entries [q0, q0 + n8), n8 a multiple of 8, in
+// row order) into the accumulator: eight factor rows in flight, from Fsrc at
+// the queued offsets; sums for the current row kept in acc.
+template <typename T, int KPL, int RG>
+__device__ __forceinline__ void run_queue(const WaveLds& w, const T* Fsrc, int q0, int n8, int k, T* acc,
+                                          int& cur_r) {
+  const int lane = lane_id();
+  T* tile = static_cast<T*>(w.tile);
+  const T* q_a = static_cast<const T*>(w.q_a);
+  for (int h = q0; h < q0 + n8; h += 8) {
+    int32_t o[8], rr[8];
+    T aa[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      o[u] = w.q_off[h + u];
+      rr[u] = w.q_row[h + u];
+      aa[u] = q_a[h + u];
+    }
+    T f[8][KPL];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      const int cc = c < k ? c : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f[u][q] = Fsrc[o[u] + cc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (rr[u] != cur_r) {  // rows are queued in order: flush on a change
+#pragma unroll
+        for (int q = 0; q < KPL; ++q) {
+          const int c = lane + 64 * q;
+          if (c < k) tile[c * RG + cur_r] += acc[q];
+          acc[q] = T(0);
+        }
+        cur_r = rr[u];
+      }
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) acc[q] = fma(aa[u], f[u][q], acc[q]);
+    }
+  }
+}
+
+// Queues a step's dense hits (one per lane, or two in the wide form: lane
+// positions base + 64 * s) in step order = row order, padded to whole
+// batches of 8 with zero-weight reads of the first factor row at the last
+// hit's row; returns the padded length.
+template <typename T, int NS>
+__device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, const int32_t* off, const int* r,
+                                          const T* av) {
+  const int lane = lane_id();
+  T* q_a = static_cast<T*>(w.q_a);
+  uint64_t bal[NS];
+  int before[NS];
+  int nh = 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    bal[s] = __ballot(hit[s]);
+    before[s] = nh;
+    nh += __popcll(bal[s]);
+  }
+  if (nh == 0) return 0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (hit[s]) {
+      const int pos = before[s] + lane_rank(bal[s]);
+      w.q_off[pos] = off[s];
+      w.q_row[pos] = r[s];
+      q_a[pos] = av[s];
+    }
+  }
+  int last_s = 0;
+#pragma unroll
+  for (int s = 1; s < NS; ++s)
+    if (bal[s]) last_s = s;
+  int r_src = r[0];
+#pragma unroll
+  for (int s = 1; s < NS; ++s)
+    if (s == last_s) r_src = r[s];
+  const int r_last = __shfl(r_src, 63 - __builtin_clzll(bal[last_s]), 64);
+  const int nh8 = (nh + 7) & ~7;
+  if (lane < nh8 - nh) {
+    w.q_off[nh + lane] = 0;
+    w.q_row[nh + lane] = r_last;
+    q_a[nh + lane] = T(0);
+  }
+  return nh8;
+}
+
 // Adds the nonzeros [p0, p1) of an item (rows bounded by rb[0..nrows]) times
-// F into the LDS tile: tile[topic * RG + row].
-template <typename T, int KPL, int RG, bool DENSE_IN>
+// F into the accumulator.
+//  * Narrow form (64 nonzeros per step): loads are predicated on the lanes
+//    that need them, so a gather costs only its active lanes.  Suits factors
+//    whose rows are mostly dense (few lanes take the entry-by-entry path).
+//  * Wide form (128 nonzeros per step, two per lane): every global load of a
+//    step is issued unconditionally at an in-bounds address (lanes past the
+//    end re-read the last nonzero, inactive gathers read entry 0) and masked
+//    afterwards, so twice as many loads are in flight per step and none waits
+//    at the end of a divergent branch.  Suits very sparse factors, where the
+//    wave mostly waits on the metadata and entry gathers.
+template <typename T, int KPL, int RG, bool DENSE_IN, bool WIDE>
 __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_t p1, const int64_t* rb,
                                            int nrows, const WaveLds& w) {
+  constexpr int NS = WIDE ? 2 : 1;
   const int lane = lane_id();
   const int k = a.k;
   const int32_t* __restrict__ col = a.col;
@@ -99,99 +223,110 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
   const T* __restrict__ F = static_cast<const T*>(a.F);
   const FactorEnt<T>* __restrict__ ents = static_cast<const FactorEnt<T>*>(a.ents);
   T* tile = static_cast<T*>(w.tile);
-  T* q_a = static_cast<T*>(w.q_a);
   T acc[KPL];
 #pragma unroll
   for (int q = 0; q < KPL; ++q) acc[q] = T(0);
   int cur_r = 0;
-  for (int64_t base = p0; base < p1; base += 64) {
-    const int64_t p = base + lane;
-    const bool valid = p < p1;
-    int32_t j = 0;
-    T av = T(0);
-    if (valid) {
-      j = col[p];
-      av = val[p];
-    }
-    int r = 0;
+  for (int64_t base = p0; base < p1; base += 64 * NS) {
+    int64_t p[NS];
+    bool valid[NS];
+    int32_t j[NS], x[NS], cnt[NS];
+    T av[NS];
+    int r[NS];
 #pragma unroll
-    for (int i = 1; i < RG; ++i) r += (i < nrows && p >= rb[i]) ? 1 : 0;
-    int32_t x = 0, cnt = 0;
-    if (valid) {
-      if (DENSE_IN) {
-        x = j;
-        cnt = k;
+    for (int s = 0; s < NS; ++s) {
+      p[s] = base + 64 * s + lane;
+      valid[s] = p[s] < p1;
+      if (WIDE) {
+        const int64_t pc = valid[s] ? p[s] : p1 - 1;
+        j[s] = __builtin_nontemporal_load(&col[pc]);
+        av[s] = __builtin_nontemporal_load(&val[pc]);
       } else {
-        const int2 m = a.meta[j];
-        x = m.x;
-        cnt = m.y;
-      }
-    }
-    const bool sparse = !DENSE_IN && cnt > 0 && cnt <= a.sparse_row;
-    // sparse factor rows: entry e of every lane's row per round; lanes start
-    // at a rotated entry so that one round rarely adds twice to one topic
-    const int rot = sparse ? lane % cnt : 0;
-    for (int e = 0; __ballot(sparse && e < cnt) != 0; ++e) {
-      if (sparse && e < cnt) {
-        int idx = e + rot;
-        if (idx >= cnt) idx -= cnt;
-        const FactorEnt<T> en = ents[x + idx];
-        atomicAdd(&tile[en.t * RG + r], av * en.v);
-      }
-    }
-    // dense factor rows: queue, then one k-wide row per hit, lanes = topics
-    const bool hit = DENSE_IN ? valid : cnt > a.sparse_row;
-    const uint64_t bal = __ballot(hit);
-    const int nh = __popcll(bal);
-    if (nh == 0) continue;
-    if (hit) {
-      const int pos = lane_rank(bal);
-      w.q_off[pos] = x * k;
-      w.q_row[pos] = r;
-      q_a[pos] = av;
-    }
-    // pad the queue to a multiple of 8 with zero-weight copies of row 0 of F
-    // (same row index as the last hit), so the loop below needs no guards
-    const int last_lane = 63 - __builtin_clzll(bal);
-    const int r_last = __shfl(r, last_lane, 64);
-    const int nh8 = (nh + 7) & ~7;
-    if (lane < nh8 - nh) {
-      w.q_off[nh + lane] = 0;
-      w.q_row[nh + lane] = r_last;
-      q_a[nh + lane] = T(0);
-    }
-    for (int h = 0; h < nh8; h += 8) {
-      int32_t o[8], rr[8];
-      T aa[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        o[u] = w.q_off[h + u];
-        rr[u] = w.q_row[h + u];
-        aa[u] = q_a[h + u];
-      }
-      T f[8][KPL];
-#pragma unroll
-      for (int q = 0; q < KPL; ++q) {
-        const int c = lane + 64 * q;
-        const int cc = c < k ? c : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) f[u][q] = F[o[u] + cc];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (rr[u] != cur_r) {  // rows are queued in order: flush on a change
-#pragma unroll
-          for (int q = 0; q < KPL; ++q) {
-            const int c = lane + 64 * q;
-            if (c < k) tile[c * RG + cur_r] += acc[q];
-            acc[q] = T(0);
-          }
-          cur_r = rr[u];
+        j[s] = 0;
+        av[s] = T(0);
+        if (valid[s]) {
+          j[s] = col[p[s]];
+          av[s] = val[p[s]];
         }
+      }
+      r[s] = 0;
 #pragma unroll
-        for (int q = 0; q < KPL; ++q) acc[q] = fma(aa[u], f[u][q], acc[q]);
+      for (int i = 1; i < RG; ++i) r[s] += (i < nrows && p[s] >= rb[i]) ? 1 : 0;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      if (DENSE_IN) {
+        x[s] = j[s];
+        cnt[s] = valid[s] ? k : 0;
+      } else if (WIDE) {
+        const int2 m = a.meta[j[s]];
+        x[s] = m.x;
+        cnt[s] = valid[s] ? m.y : 0;
+        av[s] = valid[s] ? av[s] : T(0);
+      } else {
+        x[s] = 0;
+        cnt[s] = 0;
+        if (valid[s]) {
+          const int2 m = a.meta[j[s]];
+          x[s] = m.x;
+          cnt[s] = m.y;
+        }
       }
     }
+    if (!DENSE_IN) {
+      // sparse factor rows, entry by entry; lanes start at a rotated entry so
+      // that one round rarely adds twice to one topic
+      bool sparse[NS];
+      int rot[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        sparse[s] = cnt[s] > 0 && cnt[s] <= a.sparse_row;
+        rot[s] = sparse[s] ? lane % cnt[s] : 0;
+      }
+      if (WIDE) {
+        // entries e and e + 1 of every row per round; a round only runs when
+        // some lane has an entry left, so entry 0 exists and serves as the
+        // inactive lanes' address
+        for (int e = 0; __ballot((sparse[0] && e < cnt[0]) || (sparse[NS - 1] && e < cnt[NS - 1])) != 0;
+             e += 2) {
+          FactorEnt<T> en[NS][2];
+          bool act[NS][2];
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+              act[s][d] = sparse[s] && e + d < cnt[s];
+              int idx = e + d + rot[s];
+              if (idx >= cnt[s]) idx -= cnt[s];
+              en[s][d] = ents[act[s][d] ? x[s] + idx : 0];
+            }
+#pragma unroll
+          for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+              if (act[s][d]) atomicAdd(&tile[en[s][d].t * RG + r[s]], av[s] * en[s][d].v);
+        }
+      } else {
+        for (int e = 0; __ballot(sparse[0] && e < cnt[0]) != 0; ++e) {
+          if (sparse[0] && e < cnt[0]) {
+            int idx = e + rot[0];
+            if (idx >= cnt[0]) idx -= cnt[0];
+            const FactorEnt<T> en = ents[x[0] + idx];
+            atomicAdd(&tile[en.t * RG + r[0]], av[0] * en.v);
+          }
+        }
+      }
+    }
+    // dense factor rows: queued, then one k-wide row per hit, lanes = topics
+    bool hit[NS];
+    int32_t off[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      hit[s] = DENSE_IN ? valid[s] : cnt[s] > a.sparse_row;
+      off[s] = x[s] * a.ld;
+    }
+    const int nq = queue_hits<T, NS>(w, hit, off, r, av);
+    run_queue<T, KPL, RG>(w, F, 0, nq, k, acc, cur_r);
   }
 #pragma unroll
   for (int q = 0; q < KPL; ++q) {
@@ -266,23 +401,21 @@ __device__ __forceinline__ void clear_tile(T* tile, int k) {
   }
 }
 
-template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN>
-__global__ __launch_bounds__(512) void k_spmm(SpmmArgs a) {
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
+__global__ __launch_bounds__(64 * kWaves) void k_spmm(SpmmArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
   const int k = a.k;
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
-  double* sW = reinterpret_cast<double*>(smem);
-  const WaveLds w = wave_lds<T, RG>(smem, k, RAW, wv);
+  const size_t wave0 = load_block<RAW>(a, smem);
+  const double* sW = reinterpret_cast<const double*>(smem);
+  const WaveLds w = wave_lds<T, RG, WIDE>(smem, wave0, k, wv);
   T* tile = static_cast<T*>(w.tile);
-  if (!RAW) {
-    for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
-  }
-  __syncthreads();
 
-  const int nw = gridDim.x * kWaves;
-  for (int it = blockIdx.x * kWaves + wv; it < a.n_items; it += nw) {
+  const int bw = blockDim.x >> 6;
+  const int nw = gridDim.x * bw;
+  for (int it = blockIdx.x * bw + wv; it < a.n_items; it += nw) {
     const WorkItem wi = a.items[it];
     clear_tile<T, KPL, RG>(tile, k);
     if (wi.heavy < 0) {
@@ -294,13 +427,13 @@ __global__ __launch_bounds__(512) void k_spmm(SpmmArgs a) {
       int64_t rb[RG + 1];
 #pragma unroll
       for (int i = 0; i <= RG; ++i) rb[i] = a.rowptr[wi.r0 + (i < nrows ? i : nrows)];
-      accumulate<T, KPL, RG, DENSE_IN>(a, rb[0], rb[nrows], rb, nrows, w);
+      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, rb[0], rb[nrows], rb, nrows, w);
       epilogue<T, KPL, RG, RAW, STORE_C>(a, tile, sW, nrows, wi.r0);
     } else {
       int64_t rb[RG + 1];
 #pragma unroll
       for (int i = 0; i <= RG; ++i) rb[i] = i == 0 ? wi.p0 : wi.p1;
-      accumulate<T, KPL, RG, DENSE_IN>(a, wi.p0, wi.p1, rb, 1, w);
+      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, wi.p0, wi.p1, rb, 1, w);
       T* part = static_cast<T*>(a.partials);
 #pragma unroll
       for (int q = 0; q < KPL; ++q) {
@@ -313,22 +446,23 @@ __global__ __launch_bounds__(512) void k_spmm(SpmmArgs a) {
 
 // Long rows: add the pieces' raw sums in piece order, then the epilogue.
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C>
-__global__ __launch_bounds__(512) void k_spmm_heavy(SpmmArgs a) {
+__global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy(SpmmArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
   const int k = a.k;
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   double* sW = reinterpret_cast<double*>(smem);
-  const WaveLds w = wave_lds<T, RG>(smem, k, RAW, wv);
-  T* tile = static_cast<T*>(w.tile);
   if (!RAW) {
     for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
   }
   __syncthreads();
+  const size_t wave0 = RAW ? 0 : static_cast<size_t>(k) * k * sizeof(double);
+  T* tile = reinterpret_cast<T*>(smem + wave0) + static_cast<size_t>(wv) * RG * tile_pitch(k);
   const T* part = static_cast<const T*>(a.partials);
-  const int nw = gridDim.x * kWaves;
-  for (int hh = blockIdx.x * kWaves + wv; hh < a.n_heavy; hh += nw) {
+  const int bw = blockDim.x >> 6;
+  const int nw = gridDim.x * bw;
+  for (int hh = blockIdx.x * bw + wv; hh < a.n_heavy; hh += nw) {
     const int nch = a.heavy_nchunks[hh];
     const int p0 = a.heavy_part0[hh];
 #pragma unroll
@@ -352,24 +486,32 @@ __global__ __launch_bounds__(512) void k_spmm_heavy(SpmmArgs a) {
   }
 }
 
-template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN>
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
 hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
-  const size_t lds = spmm_lds_bytes<T, RG>(a.k, RAW);
-  int per_cu = static_cast<int>((160 * 1024) / (lds + 512));
+  // W (float64, k x k) is shared by the block; with large k fewer waves fit
+  int waves = kWaves;
+  while (waves > 1 && spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves) > kLdsBytes) waves /= 2;
+  const size_t lds = spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves);
+  if (lds > kLdsBytes) return hipErrorInvalidValue;
+  // one wave of blocks: as many as are resident at once (registers and LDS),
+  // so no block starts late and the strided item loop stays balanced
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>,
+                                                   64 * waves, lds) != hipSuccess)
+    return hipErrorInvalidValue;
   if (per_cu < 1) per_cu = 1;
-  if (per_cu > 4) per_cu = 4;
   if (a.n_items > 0) {
-    int blocks = (a.n_items + kWaves - 1) / kWaves;
+    int blocks = (a.n_items + waves - 1) / waves;
     const int cap = h->num_cus * per_cu;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN>), dim3(blocks), dim3(64 * kWaves), lds,
+    hipLaunchKernelGGL((k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>), dim3(blocks), dim3(64 * waves), lds,
                        h->stream, a);
   }
   if (a.n_heavy > 0) {
-    int blocks = (a.n_heavy + kWaves - 1) / kWaves;
+    int blocks = (a.n_heavy + waves - 1) / waves;
     const int cap = h->num_cus * per_cu;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((k_spmm_heavy<T, KPL, RG, RAW, STORE_C>), dim3(blocks), dim3(64 * kWaves), lds,
+    hipLaunchKernelGGL((k_spmm_heavy<T, KPL, RG, RAW, STORE_C>), dim3(blocks), dim3(64 * waves), lds,
                        h->stream, a);
   }
   return hipGetLastError();
@@ -379,7 +521,7 @@ hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
 
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                bool raw, const T* dense_in, int sparse_row) {
+                bool raw, const T* dense_in, int sparse_row, bool wide) {
   SpmmArgs a{};
   a.rowptr = p.rowptr;
   a.col = p.col;
@@ -395,6 +537,7 @@ hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, 
   a.sparse_row = sparse_row;
   a.ents = F.packed;
   a.F = dense_in ? static_cast<const void*>(dense_in) : static_cast<const void*>(F.dense);
+  a.ld = dense_in ? h->k : F.ld;
   a.W = W;
   a.X = X;
   a.C = C;
@@ -404,17 +547,22 @@ hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, 
   const bool dense = dense_in != nullptr;
   if (raw) {
     if (dense)
-      return two ? launch<T, 2, 4, true, false, true>(h, a) : launch<T, 1, 8, true, false, true>(h, a);
-    return two ? launch<T, 2, 4, true, false, false>(h, a) : launch<T, 1, 8, true, false, false>(h, a);
+      return two ? launch<T, 2, 4, true, false, true, false>(h, a) : launch<T, 1, 8, true, false, true, false>(h, a);
+    return two ? launch<T, 2, 4, true, false, false, false>(h, a) : launch<T, 1, 8, true, false, false, false>(h, a);
   }
-  if (C != nullptr)
-    return two ? launch<T, 2, 4, false, true, false>(h, a) : launch<T, 1, 8, false, true, false>(h, a);
-  return two ? launch<T, 2, 4, false, false, false>(h, a) : launch<T, 1, 8, false, false, false>(h, a);
+  if (C != nullptr) {
+    if (wide)
+      return two ? launch<T, 2, 4, false, true, false, true>(h, a) : launch<T, 1, 8, false, true, false, true>(h, a);
+    return two ? launch<T, 2, 4, false, true, false, false>(h, a) : launch<T, 1, 8, false, true, false, false>(h, a);
+  }
+  if (wide)
+    return two ? launch<T, 2, 4, false, false, false, true>(h, a) : launch<T, 1, 8, false, false, false, true>(h, a);
+  return two ? launch<T, 2, 4, false, false, false, false>(h, a) : launch<T, 1, 8, false, false, false, false>(h, a);
 }
 
 template hipError_t spmm<float>(nmf_handle*, const Plan&, const Factor&, const double*, float*,
-                                float*, bool, const float*, int);
+                                float*, bool, const float*, int, bool);
 template hipError_t spmm<double>(nmf_handle*, const Plan&, const Factor&, const double*, double*,
-                                 double*, bool, const double*, int);
+                                 double*, bool, const double*, int, bool);
 
 }  // namespace nmfk

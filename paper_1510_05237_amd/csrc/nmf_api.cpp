@@ -78,7 +78,7 @@ struct HostPlan {
   int32_t parts = 0;
 };
 
-// Work items for one orientation: groups of up to kRowGroup consecutive
+// Work items for one orientation: groups of up to max_rows consecutive
 // short rows (total at most kChunk nonzeros), and kChunk-long pieces of
 // every longer row.
 HostPlan build_plan(const int64_t* rp, int64_t rows, int max_rows) {
@@ -117,7 +117,8 @@ HostPlan build_plan(const int64_t* rp, int64_t rows, int max_rows) {
     WorkItem w;
     w.r0 = static_cast<int32_t>(start);
     w.r1 = static_cast<int32_t>(r);
-    w.p0 = w.p1 = 0;
+    w.p0 = rp[start];
+    w.p1 = rp[r];
     w.heavy = -1;
     w.part = -1;
     p.items.push_back(w);
@@ -164,7 +165,8 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
     f.val = cv.take<char>(rows * k * elt);
     f.slot = cv.take<int32_t>(rows);
     f.rowid = cv.take<int32_t>(rows);
-    f.dense = cv.take<char>(rows * k * elt);
+    f.ld = dense_ld(k, elt);
+    f.dense = cv.take<char>(rows * f.ld * elt);
     f.counts = cv.take<int32_t>(4);
     f.meta = cv.take<int2>(rows);
     f.packed = cv.take<char>(rows * k * 2 * elt);
@@ -220,8 +222,9 @@ nmf_status check_config(const nmf_config* c) {
   if (c->mode != NMF_MODE_COLUMN && c->mode != NMF_MODE_NONE)
     return fail(nullptr, NMF_ERR_UNSUPPORTED, "mode not supported");
   if (c->dtype != NMF_F32 && c->dtype != NMF_F64) return fail(nullptr, NMF_ERR_UNSUPPORTED, "dtype");
-  if (c->n * static_cast<int64_t>(c->k) >= (int64_t(1) << 31) ||
-      c->m * static_cast<int64_t>(c->k) >= (int64_t(1) << 31))
+  // int32 offsets into the k-wide matrices and the compact dense copies
+  const int64_t ld = dense_ld(c->k, c->dtype == NMF_F32 ? 4 : 8);
+  if (c->n * ld >= (int64_t(1) << 31) || c->m * ld >= (int64_t(1) << 31))
     return fail(nullptr, NMF_ERR_UNSUPPORTED, "rows * k must be below 2^31");
   return NMF_OK;
 }
@@ -295,6 +298,12 @@ nmf_status prof_mark(nmf_handle* h, int stage) {
   } while (0)
 
 // Load a dense rows x k factor (host or device) into a stored factor.
+// A factor's gather metadata follows the SpMM that gathers it: U is gathered
+// by the V half (threshold sparse_row[0]), V by the U half (sparse_row[1]).
+int sparse_row_of(const nmf_handle* h, const Factor& f) {
+  return &f == &h->V ? h->sparse_row[1] : h->sparse_row[0];
+}
+
 template <typename T>
 nmf_status load_factor(nmf_handle* h, const void* src, Factor& f) {
   const size_t bytes = static_cast<size_t>(f.rows) * h->k * sizeof(T);
@@ -314,7 +323,7 @@ nmf_status load_factor(nmf_handle* h, const void* src, Factor& f) {
     if (flag) return fail(h, NMF_ERR_INVALID_INPUT, "factor has a negative or non-finite value");
   }
   HIPCHK(h, mark_nonzero<T>(h, stage, f.rows));
-  HIPCHK(h, repack<T>(h, stage, f.rows, f, (&f == &h->V) ? h->sparse_row[1] : h->sparse_row[0]));
+  HIPCHK(h, repack<T>(h, stage, f.rows, f, sparse_row_of(h, f)));
   return NMF_OK;
 }
 
@@ -336,11 +345,11 @@ nmf_status v_half(nmf_handle* h) {
   Factor& U = h->U[h->cur_u];
   T* vpre = static_cast<T*>(h->vpre);
   PROF(h, -1);
-  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr, h->sparse_row[0]));
+  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr, h->sparse_row[0], h->wide[0]));
   PROF(h, NMF_STAGE_SPMM_V);
   HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
   PROF(h, NMF_STAGE_SELECT_V);
-  HIPCHK(h, repack<T>(h, vpre, h->m, h->V, h->sparse_row[1]));
+  HIPCHK(h, repack<T>(h, vpre, h->m, h->V, sparse_row_of(h, h->V)));
   PROF(h, NMF_STAGE_REPACK_V);
   HIPCHK(h, gram<T>(h, h->V, h->gV));
   PROF(h, NMF_STAGE_GRAM_V);
@@ -355,11 +364,11 @@ nmf_status u_half(nmf_handle* h, bool keep_c) {
   Factor& Un = h->U[nxt];
   T* upre = static_cast<T*>(h->upre);
   HIPCHK(h, spmm<T>(h, h->planA, h->V, h->gV.W, upre, keep_c ? static_cast<T*>(h->cbuf) : nullptr,
-                    false, nullptr, h->sparse_row[1]));
+                    false, nullptr, h->sparse_row[1], h->wide[1]));
   PROF(h, NMF_STAGE_SPMM_U);
   HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
   PROF(h, NMF_STAGE_SELECT_U);
-  HIPCHK(h, repack<T>(h, upre, h->n, Un, h->sparse_row[0]));
+  HIPCHK(h, repack<T>(h, upre, h->n, Un, sparse_row_of(h, Un)));
   PROF(h, NMF_STAGE_REPACK_U);
   HIPCHK(h, gram<T>(h, Un, h->gU));
   PROF(h, NMF_STAGE_GRAM_U);
@@ -463,9 +472,9 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   if ((s = upload_plan(h->planA, pa)) != NMF_OK) return s;
   if ((s = upload_plan(h->planAt, pt)) != NMF_OK) return s;
   HIPCHK(h, hipMemcpy(h->planA.rowptr, rp, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.rowptr, cp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.val, val, nnz * sizeof(T), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->planAt.rowptr, cp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz * sizeof(T), hipMemcpyHostToDevice));
   // state that must start at zero
@@ -798,11 +807,11 @@ nmf_status reload_meta(nmf_handle* h, int which) {
   if (h->elt == 8) {
     HIPCHK(h, densify<double>(h, F, static_cast<double*>(stage)));
     HIPCHK(h, mark_nonzero<double>(h, static_cast<double*>(stage), F.rows));
-    HIPCHK(h, repack<double>(h, static_cast<double*>(stage), F.rows, F, h->sparse_row[which == 0 ? 0 : 1]));
+    HIPCHK(h, repack<double>(h, static_cast<double*>(stage), F.rows, F, sparse_row_of(h, F)));
   } else {
     HIPCHK(h, densify<float>(h, F, static_cast<float*>(stage)));
     HIPCHK(h, mark_nonzero<float>(h, static_cast<float*>(stage), F.rows));
-    HIPCHK(h, repack<float>(h, static_cast<float*>(stage), F.rows, F, h->sparse_row[which == 0 ? 0 : 1]));
+    HIPCHK(h, repack<float>(h, static_cast<float*>(stage), F.rows, F, sparse_row_of(h, F)));
   }
   return sync_status(h);
 }
@@ -817,6 +826,11 @@ nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value) {
       // the stored factor's gather metadata depends on the threshold:
       // rebuild it for the factor this half-step gathers
       return param == NMF_PARAM_SPARSE_ROW_V ? reload_meta(h, 0) : reload_meta(h, 1);
+    case NMF_PARAM_WIDE_V:
+    case NMF_PARAM_WIDE_U:
+      if (value != 0 && value != 1) return fail(h, NMF_ERR_INVALID_ARG, "step form must be 0 or 1");
+      h->wide[param - NMF_PARAM_WIDE_V] = value != 0;
+      return NMF_OK;
     default:
       return fail(h, NMF_ERR_INVALID_ARG, "unknown parameter");
   }

@@ -16,11 +16,10 @@ namespace nmfk {
 constexpr int kMaxK = 128;       // topics supported (2 per lane at most)
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kChunk = 2048;     // nonzeros per SpMM work item; longer rows are split
-constexpr int kRowGroup = 8;     // rows per light SpMM work item when k <= 64
 
-// Rows one SpMM epilogue batch holds (and so the most rows a light work item
-// may carry): 8 with one topic per lane, 4 with two topics per lane.
-inline int spmm_row_group(int k) { return k > 64 ? kRowGroup / 2 : kRowGroup; }
+// Most output rows a light SpMM work item carries (the rows of one epilogue
+// batch): 8 with one topic per lane, 4 with two.
+inline int spmm_row_group(int k) { return k > 64 ? 4 : 8; }
 constexpr int kBins = 256;       // radix digit width of the top-t select (8 bits)
 constexpr int kSmall = 2048;     // candidates finished by an in-LDS sort
 constexpr int kHistRing = 4096;  // iterations kept in the device history ring
@@ -31,11 +30,12 @@ constexpr int kCntStride = 32;  // ints between per-column counters (one 128-byt
 // History record fields (float64 each).
 enum { H_E = 0, H_R, H_NNZU, H_NNZV, H_DEADU, H_DEADV, H_FIELDS };
 
-// One unit of SpMM work for one wave.
+// One unit of SpMM work for one wave, over the nonzeros [p0, p1) of the
+// plan's arrays (row-compressed, rows ascending, columns ascending in a row).
 //  light (heavy < 0): output rows [r0, r1), every row at most kChunk long.
-//  heavy (heavy >= 0): nonzeros [p0, p1) of row r0, one chunk of a long row;
-//    its raw sum goes to partial slot `part`; a second kernel adds the row's
-//    partials in chunk order and runs the epilogue.
+//  heavy (heavy >= 0): one kChunk piece of the long row r0; its raw sum goes
+//    to partial slot `part`; a second kernel adds the row's partials in chunk
+//    order and runs the epilogue.
 struct WorkItem {
   int32_t r0, r1;
   int64_t p0, p1;
@@ -60,7 +60,8 @@ struct Plan {
 };
 
 // A factor as stored (row-compressed sparse) plus the gather cache the SpMM
-// reads: every nonempty row expanded to a dense k-wide row.
+// reads: every nonempty row expanded to a dense row (16-byte aligned rows, so
+// one lane can load four floats or two doubles of a row at once).
 struct Factor {
   int64_t rows = 0;
   int32_t* row_ptr = nullptr;  // [rows + 1]
@@ -68,7 +69,8 @@ struct Factor {
   void* val = nullptr;         // [rows * k] T
   int32_t* slot = nullptr;     // [rows]: -1 empty, else compact row index
   int32_t* rowid = nullptr;    // [rows]: compact row index -> row
-  void* dense = nullptr;       // [rows][k] T: compact dense rows 0..R-1
+  void* dense = nullptr;       // [rows][ld] T: compact dense rows 0..R-1, zero past k
+  int32_t ld = 0;              // row pitch of `dense`: k rounded up to 16 bytes
   int32_t* counts = nullptr;   // device [0] = nnz, [1] = R (nonempty rows)
   // SpMM gather metadata: per row {compact dense row (rows with more entries
   // than the gathering SpMM's threshold) or first stored entry, entry count};
@@ -83,6 +85,13 @@ struct FactorEnt {
   T v;
   uint32_t t;
 };
+
+// Row pitch of a factor's compact dense copy: k rounded up to whole 16-byte
+// vectors (four floats or two doubles).
+inline int32_t dense_ld(int32_t k, size_t elt) {
+  const int32_t v = static_cast<int32_t>(16 / elt);
+  return (k + v - 1) / v * v;
+}
 
 constexpr int kSparseRow = 3;  // default: factor rows with at most this many entries are gathered entry by entry
 
@@ -163,6 +172,7 @@ struct nmf_handle {
   bool have_pre_v = false, have_pre_u = false;
   bool metrics_valid = false;  // the newest history record describes the current U, V
   int sparse_row[2] = {nmfk::kSparseRow, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
+  bool wide[2] = {false, true};                               // NMF_PARAM_WIDE_V / _U
   // stage timing (nmf_profile)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;      // pool
@@ -179,7 +189,7 @@ namespace nmfk {
 // double.  All enqueue on h->stream and return hipSuccess or the launch error.
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                bool raw, const T* dense_in, int sparse_row);
+                bool raw, const T* dense_in, int sparse_row, bool wide = false);
 template <typename T>
 hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int mode,
                        const Factor& out_f);

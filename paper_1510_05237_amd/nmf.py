@@ -229,6 +229,8 @@ def nmf_loss_bwd(h: int, U, V, g_scale, gU, gV):
 
 NMF_PARAM_SPARSE_ROW_V = 0
 NMF_PARAM_SPARSE_ROW_U = 1
+NMF_PARAM_WIDE_V = 2
+NMF_PARAM_WIDE_U = 3
 
 
 def nmf_set_param(h: int, param: int, value: int):

@@ -256,6 +256,64 @@ def test_determinism_and_resume():
     np.testing.assert_array_equal(Vs, Va)
 
 
+def test_tuning_parameters_fp64():
+    """Every SpMM configuration (entry-by-entry threshold 0, 1, 3, 128 and
+    both step forms, on both halves, changed between iterations) reproduces
+    the oracle's FP64 trajectory; out-of-range settings are refused."""
+    from paper_1510_05237_amd import (NMF_PARAM_SPARSE_ROW_U, NMF_PARAM_SPARSE_ROW_V, NMF_PARAM_WIDE_U,
+                                      NMF_PARAM_WIDE_V)
+
+    _, NMFError = _nmf()
+    c, u0, v0, p = synth.make_workload("plain_f64_2000x1000")
+    A = c.scipy()
+    settings = [(0, 0, 0, 0), (0, 1, 0, 1), (3, 1, 3, 0), (128, 0, 128, 1), (1, 0, 1, 1), (3, 0, 3, 1)]
+    _say(f"fp64 2000x1000 k={p['k']}: {len(settings)} tuning settings, one per iteration")
+    prob = _problem(c, u0, p["k"], p["t_u"], p["t_v"], "f64")
+    st = None
+    for it, (srv, wv, sru, wu) in enumerate(settings):
+        prob.set_param(NMF_PARAM_SPARSE_ROW_V, srv)
+        prob.set_param(NMF_PARAM_WIDE_V, wv)
+        prob.set_param(NMF_PARAM_SPARSE_ROW_U, sru)
+        prob.set_param(NMF_PARAM_WIDE_U, wu)
+        prob.step(1)
+        st = oracle.als(A, u0, p["t_u"], p["t_v"], 1, state=st)
+        U, V = prob.factors()
+        assert rel_fro(U, st.U) < 1e-9, (it, srv, wv, sru, wu)
+        assert rel_fro(V, st.V) < 1e-9, (it, srv, wv, sru, wu)
+        np.testing.assert_array_equal(U != 0, st.U != 0)
+        np.testing.assert_array_equal(V != 0, st.V != 0)
+    E, R, _, _ = prob.history()
+    np.testing.assert_allclose(E, st.E, rtol=1e-9)
+    for param, bad in ((NMF_PARAM_SPARSE_ROW_V, -1), (NMF_PARAM_SPARSE_ROW_U, 129), (NMF_PARAM_WIDE_V, 2),
+                       (NMF_PARAM_WIDE_U, -1), (99, 0)):
+        with pytest.raises(NMFError):
+            prob.set_param(param, bad)
+    prob.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_k128_fits_lds(dtype):
+    """k = 128, the largest supported: the float64 W of the SpMM epilogue
+    (128 KiB) leaves room for fewer waves per block, which the launch picks;
+    three iterations match the oracle."""
+    c = synth.make_corpus(700, 500, seed=41, alpha=1.1, nnz=30000, dtype=dtype)
+    u0, _ = synth.make_init(700, 500, 128, seed=41, dtype=dtype)
+    _say(f"{dtype} 700x500 nnz={c.nnz} k=128, 3 iterations")
+    A = c.scipy()
+    prob = _problem(c, u0, 128, 40, 30, dtype)
+    prob.step(3)
+    st = oracle.als(A, u0.astype(np.float64), 40, 30, 3)
+    U, V = prob.factors()
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    if dtype == "f64":
+        assert rel_fro(U, st.U) < tol and rel_fro(V, st.V) < tol
+        np.testing.assert_array_equal(U != 0, st.U != 0)
+    else:
+        E, _, _, _ = prob.history()
+        np.testing.assert_allclose(E, st.E, rtol=1e-4)
+    prob.close()
+
+
 def test_power_of_two_scaling_gpu():
     """Scaling A by 2^p leaves U and every support bit-identical and scales V
     by exactly 2^p on the GPU too (rounding commutes with the scaling)."""
