@@ -1,20 +1,21 @@
 // Gram matrix of the fixed factor and its inverse: the (U^T U)^-1 and
 // (V^T V)^-1 of Algorithms 1-2.
 //
-//  1. k_gram_partial: G = F^T F is summed over the rows of F in the working
-//     type T.  Each of kGramBlocks blocks owns a fixed slice of rows and keeps
-//     its partial k x k sums (upper triangle) in registers.
+//  1. G = F^T F is summed over the rows of F in the working type T.  Each of
+//     kGramBlocks blocks owns a fixed slice of rows.  float32: k_gram_mfma,
+//     a dense contraction on the matrix cores (v_mfma_f32_16x16x4f32, four
+//     rows per instruction, the upper-triangle 16 x 16 tiles of G in
+//     accumulator registers); float64: k_gram_partial, the upper-triangle
+//     sums in registers, one FMA per entry and row.
 //  2. k_gram_reduce: every block owns 64 upper-triangle entries; its four
 //     waves add strided subsets of the block partials in float64 and the
 //     four sums are combined in a fixed order, so G does not depend on
 //     scheduling.
-//  3. k_gram_factor (one block) factorizes in float64, in LDS:
+//  3. k_gram_factor (one block) inverts in float64 (see there):
 //      * dead topics (zero diagonal: an all-zero column of F) get an identity
 //        row and column, which keeps that topic at exactly zero;
-//      * Cholesky G = L L^T, right-looking; a non-positive pivot elsewhere
-//        sets the sticky status NMF_ERR_NOT_SPD;
-//      * L^-1 overwrites L row by row (forward substitution on all columns
-//        of the identity at once), then W = L^-T L^-1.
+//      * a pivot that is not positive elsewhere (G not positive definite)
+//        sets the sticky status NMF_ERR_NOT_SPD.
 // G itself is stored without the dead-topic substitution (the error of
 // Section 3.1 needs the true Gram matrices).
 #include "nmf_device.h"
@@ -41,7 +42,6 @@ struct GramArgs {
   const int32_t* counts_a;
   const int32_t* counts_b;
   int64_t* max_nnz;
-  int32_t two_mats;  // LDS holds a second k x k matrix for L^-1
 };
 
 __device__ __forceinline__ void tri_index(int e, int k, int* pa, int* pb) {
@@ -117,100 +117,6 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) {
   }
 }
 
-// In-LDS float64 factorization of the k x k matrix A (full storage); writes
-// W = A^-1.  X (k x k, may alias nothing) holds L^-1 when it is not null;
-// otherwise L^-1 overwrites L row by row.  Returns false when a pivot is not
-// positive.
-__device__ bool factor_inverse(double* A, double* X, double* tmp, int* dead, int k, double* W,
-                               int32_t* ndead) {
-  const int tid = threadIdx.x;
-  __shared__ int nd;
-  if (tid == 0) nd = 0;
-  __syncthreads();
-  for (int c = tid; c < k; c += 256) {
-    dead[c] = A[c * k + c] == 0.0;
-    if (dead[c]) atomicAdd(&nd, 1);
-  }
-  __syncthreads();
-  if (tid == 0) *ndead = nd;
-  if (nd > 0) {
-    for (int e = tid; e < k * k; e += 256) {
-      const int i = e / k, j = e - (e / k) * k;
-      if (dead[i] || dead[j]) A[e] = i == j ? 1.0 : 0.0;
-    }
-    __syncthreads();
-  }
-  // right-looking Cholesky on the lower triangle, two barriers per column.
-  // The diagonal of L goes to tmp and replaces A's diagonal only at the end,
-  // so every thread can read the pivot A[j][j] itself without a race.
-  bool ok = true;
-  for (int j = 0; j < k; ++j) {
-    __syncthreads();  // the previous trailing update is complete
-    const double d = A[j * k + j];
-    if (!(d > 0.0)) ok = false;
-    const double piv = d > 0.0 ? sqrt(d) : 1.0;
-    if (tid == 0) tmp[j] = piv;
-    for (int i = j + 1 + tid; i < k; i += 256) A[i * k + j] /= piv;
-    __syncthreads();
-    // trailing update: thread -> row i = j+1+tid/4, every 4th column
-    for (int i = j + 1 + (tid >> 2); i < k; i += 64) {
-      const double lij = A[i * k + j];
-      for (int l = j + 1 + (tid & 3); l <= i; l += 4) A[i * k + l] = fma(-lij, A[l * k + j], A[i * k + l]);
-    }
-  }
-  __syncthreads();
-  for (int j = tid; j < k; j += 256) A[j * k + j] = tmp[j];
-  __syncthreads();
-  if (!ok) return false;
-  if (X != nullptr) {
-    // L^-1 by forward substitution on every column of the identity at once:
-    // X = I; for j: X[j][:] /= L[j][j]; X[i][:] -= L[i][j] X[j][:] (i > j)
-    for (int e = tid; e < k * k; e += 256) X[e] = (e / k) == (e % k) ? 1.0 : 0.0;
-    __syncthreads();
-    for (int j = 0; j < k; ++j) {
-      const double ljj = A[j * k + j];
-      for (int c = tid; c <= j; c += 256) X[j * k + c] /= ljj;
-      __syncthreads();
-      for (int i = j + 1 + (tid >> 2); i < k; i += 64) {
-        const double lij = A[i * k + j];
-        for (int c = (tid & 3); c <= j; c += 4) X[i * k + c] = fma(-lij, X[j * k + c], X[i * k + c]);
-      }
-      __syncthreads();
-    }
-  } else {
-    // X = L^-1 overwrites L row by row:
-    //   X[j][c] = (delta_jc - sum_{c <= i < j} L[j][i] X[i][c]) / L[j][j]
-    X = A;
-    for (int j = 0; j < k; ++j) {
-      for (int i = tid; i <= j; i += 256) tmp[i] = A[j * k + i];
-      __syncthreads();
-      for (int c = tid; c <= j; c += 256) {
-        double s = c == j ? 1.0 : 0.0;
-        for (int i = c; i < j; ++i) s = fma(-tmp[i], A[i * k + c], s);
-        A[j * k + c] = s / tmp[j];
-      }
-      __syncthreads();
-    }
-  }
-  // W = X^T X: W[a][b] = sum_{r >= max(a,b)} X[r][a] X[r][b]
-  const int ne = k * (k + 1) / 2;
-  for (int e = tid; e < ne; e += 256) {
-    int a, b;
-    tri_index(e, k, &a, &b);  // a <= b
-    double s0 = 0.0, s1 = 0.0;
-    int r = b;
-    for (; r + 1 < k; r += 2) {
-      s0 = fma(X[r * k + a], X[r * k + b], s0);
-      s1 = fma(X[(r + 1) * k + a], X[(r + 1) * k + b], s1);
-    }
-    if (r < k) s0 = fma(X[r * k + a], X[r * k + b], s0);
-    const double sum = s0 + s1;
-    W[a * k + b] = sum;
-    W[b * k + a] = sum;
-  }
-  return true;
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
   __shared__ double red[4][kReduceEntries];
@@ -245,24 +151,186 @@ __global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
   }
 }
 
-// One block: the storage high-water mark, then W = G^-1 in float64.
-__global__ __launch_bounds__(256) void k_gram_factor(GramArgs g) {
-  extern __shared__ __align__(16) unsigned char smem[];
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// G partials on the matrix cores (float32, k <= 16 * NB).  A 16 x 4 by
+// 4 x 16 product with the four rows r0..r0+3 of F as the inner dimension:
+// lane l supplies F[r0 + l / 16][16 t + l % 16] for topic block t, which is
+// both the A operand (F^T, topics x rows) of block t and the B operand (F,
+// rows x topics) of block t; the accumulator of tile (ta, tb) then holds
+// G[16 ta + 4 (l / 16) + i][16 tb + l % 16] in its element i.  Each wave sums
+// a contiguous slice of the block's rows; the block adds its waves' tiles in
+// wave order and stores the upper triangle like k_gram_partial.
+template <int NB>
+__global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) {
+  constexpr int NP = NB * (NB + 1) / 2;  // tiles (ta <= tb)
+  __shared__ float red[4][NP][64][4];
   if (*g.status != 0) return;
   const int k = g.k;
-  if (threadIdx.x == 0 && g.max_nnz) {
-    const int64_t cur = static_cast<int64_t>(*g.counts_a) + (g.counts_b ? *g.counts_b : 0);
-    if (cur > *g.max_nnz) *g.max_nnz = cur;
+  const int ld = g.ld;
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int64_t R = g.rows_dev ? static_cast<int64_t>(*g.rows_dev) : g.rows_host;
+  const int P = gridDim.x;
+  const int64_t blo = R * blockIdx.x / P, bhi = R * (blockIdx.x + 1) / P;
+  const int64_t lo = blo + (bhi - blo) * wv / 4, hi = blo + (bhi - blo) * (wv + 1) / 4;
+  const float* __restrict__ F = static_cast<const float*>(g.F);
+  mfma_f4 acc[NP];
+#pragma unroll
+  for (int t = 0; t < NP; ++t) acc[t] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+  const int kr = lane >> 4;  // row within a group of four
+  const int cl = lane & 15;  // topic within a block of 16
+  for (int64_t r0 = lo; r0 < hi; r0 += 8) {
+    // two groups of four rows, all loads in flight together
+    float f[2][NB];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int64_t r = r0 + 4 * s2 + kr;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const int c = 16 * t + cl;
+        f[s2][t] = (r < hi && c < k) ? F[r * ld + c] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      int pi = 0;
+#pragma unroll
+      for (int ta = 0; ta < NB; ++ta)
+#pragma unroll
+        for (int tb = ta; tb < NB; ++tb) {
+          acc[pi] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[s2][ta], f[s2][tb], acc[pi], 0, 0, 0);
+          ++pi;
+        }
+    }
   }
-  double* A = reinterpret_cast<double*>(smem);  // [k][k]
-  double* tmp = A + k * k;                      // [k]
-  int* dead = reinterpret_cast<int*>(tmp + k);  // [k]
-  double* X = g.two_mats ? reinterpret_cast<double*>(dead + ((k + 1) & ~1)) : nullptr;  // [k][k]
-  for (int i = threadIdx.x; i < k * k; i += 256) A[i] = g.G[i];
+#pragma unroll
+  for (int t = 0; t < NP; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wv][t][lane][i] = acc[t][i];
   __syncthreads();
-  if (!factor_inverse(A, X, tmp, dead, k, g.W, g.dead)) {
-    if (threadIdx.x == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
-    for (int i = threadIdx.x; i < k * k; i += 256) g.W[i] = 0.0;
+  const int ne = k * (k + 1) / 2;
+  float* part = static_cast<float*>(g.partials) + static_cast<int64_t>(blockIdx.x) * ne;
+  for (int x = threadIdx.x; x < NP * 256; x += 256) {
+    const int t = x >> 8, l = (x >> 2) & 63, i = x & 3;
+    const float v = ((red[0][t][l][i] + red[1][t][l][i]) + red[2][t][l][i]) + red[3][t][l][i];
+    // tile t -> (ta, tb)
+    int ta = 0, rem = t;
+    while (rem >= NB - ta) {
+      rem -= NB - ta;
+      ++ta;
+    }
+    const int tb = ta + rem;
+    const int a = 16 * ta + 4 * (l >> 4) + i, b = 16 * tb + (l & 15);
+    if (a <= b && b < k) part[a * k - a * (a - 1) / 2 + (b - a)] = v;
+  }
+}
+
+// One block: the storage high-water mark, then W = G^-1 in float64 by
+// Gauss-Jordan elimination on the symmetric positive definite G.  Without
+// pivoting its j-th pivot is the j-th Schur complement diagonal, i.e. the
+// square of the Cholesky diagonal L_jj, so a pivot that is not positive
+// (NOT_SPD) occurs exactly where the Cholesky factorization of G fails.
+// Dead topics (G_cc = 0) get identity rows and columns first, which the
+// elimination leaves unchanged.
+//
+// The KM x KM matrix lives in registers: thread t of 1024 owns row
+// i = t / TPR and the columns l = t % TPR + TPR * q.  Step j needs the pivot,
+// column j and row j as they were after step j - 1; their owners publish
+// them in a double-buffered LDS copy, so each step costs one barrier.
+constexpr int kFactorThreads = 1024;
+
+template <int KM>
+__global__ __launch_bounds__(kFactorThreads) void k_gram_factor(GramArgs g) {
+  constexpr int TPR = kFactorThreads / KM;  // threads per row
+  constexpr int NQ = KM / TPR;              // entries per thread
+  __shared__ double rowb[2][KM], colb[2][KM];
+  __shared__ int s_dead[KM];
+  __shared__ int s_nd;
+  if (*g.status != 0) return;
+  const int k = g.k;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_nd = 0;
+    if (g.max_nnz) {
+      const int64_t cur = static_cast<int64_t>(*g.counts_a) + (g.counts_b ? *g.counts_b : 0);
+      if (cur > *g.max_nnz) *g.max_nnz = cur;
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < KM; c += kFactorThreads) {
+    const int d = c < k && g.G[c * k + c] == 0.0;
+    s_dead[c] = d;
+    if (d) atomicAdd(&s_nd, 1);
+  }
+  __syncthreads();
+  if (tid == 0) *g.dead = s_nd;
+  const int i = tid / TPR;
+  const int ph = tid % TPR;
+  double e[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int l = ph + TPR * q;
+    double v = 0.0;
+    if (i < k && l < k) v = (s_dead[i] || s_dead[l]) ? (i == l ? 1.0 : 0.0) : g.G[i * k + l];
+    e[q] = v;
+  }
+  // publish row 0 and column 0
+  if (i == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rowb[0][ph + TPR * q] = e[q];
+  }
+  if (ph == 0) colb[0][i] = e[0];
+  __syncthreads();
+  bool ok = true;
+  for (int j = 0; j < k; ++j) {
+    const int b = j & 1;
+    const double p = rowb[b][j];
+    ok = ok && p > 0.0;
+    const double ip = 1.0 / p;
+    // row j: a_jl * ip; other rows: a_il - a_ij * (a_jl * ip); column j:
+    // ip on the pivot, -a_ij * ip elsewhere
+    const bool prow = i == j;
+    const double aij = prow ? 0.0 : colb[b][i];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double gl = rowb[b][ph + TPR * q] * ip;
+      e[q] = prow ? gl : fma(-aij, gl, e[q]);
+    }
+    if (ph == j % TPR) {
+      const double v = prow ? ip : -aij * ip;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (q == j / TPR) e[q] = v;
+    }
+    // publish row j + 1 and column j + 1 for the next step
+    const int jn = j + 1;
+    if (jn < k) {
+      if (i == jn) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) rowb[b ^ 1][ph + TPR * q] = e[q];
+      }
+      if (ph == jn % TPR) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          if (q == jn / TPR) v = e[q];
+        colb[b ^ 1][i] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (!ok) {
+    if (tid == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
+    for (int x = tid; x < k * k; x += kFactorThreads) g.W[x] = 0.0;
+    return;
+  }
+  if (i < k) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int l = ph + TPR * q;
+      if (l < k) g.W[i * k + l] = e[q];
+    }
   }
 }
 
@@ -271,17 +339,29 @@ hipError_t launch(nmf_handle* h, GramArgs& g) {
   const int k = h->k;
   const int kpad = (k + 3) & ~3;
   const size_t stage = static_cast<size_t>(kStageRows) * kpad * sizeof(T);
-  size_t fac = (static_cast<size_t>(k) * k + k) * sizeof(double) + static_cast<size_t>((k + 1) & ~1) * sizeof(int);
-  g.two_mats = fac + static_cast<size_t>(k) * k * sizeof(double) <= 150 * 1024 ? 1 : 0;
-  if (g.two_mats) fac += static_cast<size_t>(k) * k * sizeof(double);
-  if (k <= 64)
+  if (sizeof(T) == 4) {
+    if (k <= 32)
+      hipLaunchKernelGGL(k_gram_mfma<2>, dim3(kGramBlocks), dim3(256), 0, h->stream, g);
+    else if (k <= 64)
+      hipLaunchKernelGGL(k_gram_mfma<4>, dim3(kGramBlocks), dim3(256), 0, h->stream, g);
+    else
+      hipLaunchKernelGGL(k_gram_mfma<8>, dim3(kGramBlocks), dim3(256), 0, h->stream, g);
+  } else if (k <= 64) {
     hipLaunchKernelGGL((k_gram_partial<T, 9>), dim3(kGramBlocks), dim3(256), stage, h->stream, g);
-  else
+  } else {
     hipLaunchKernelGGL((k_gram_partial<T, 33>), dim3(kGramBlocks), dim3(256), stage, h->stream, g);
+  }
   const int ne = k * (k + 1) / 2;
   const int rblocks = (ne + kReduceEntries - 1) / kReduceEntries;
   hipLaunchKernelGGL((k_gram_reduce<T>), dim3(rblocks), dim3(256), 0, h->stream, g);
-  if (g.W) hipLaunchKernelGGL(k_gram_factor, dim3(1), dim3(256), fac, h->stream, g);
+  if (g.W) {
+    if (k <= 32)
+      hipLaunchKernelGGL(k_gram_factor<32>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+    else if (k <= 64)
+      hipLaunchKernelGGL(k_gram_factor<64>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+    else
+      hipLaunchKernelGGL(k_gram_factor<128>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+  }
   return hipGetLastError();
 }
 
