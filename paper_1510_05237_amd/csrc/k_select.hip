@@ -17,8 +17,8 @@
 //              appended to the column's candidate list.
 //  3. refine:  one block per column narrows the candidates digit by digit
 //              (remaining value bits, then the row bits for the tie-break),
-//              keeping whole digits above the threshold, until few enough
-//              remain to sort in LDS.
+//              keeping whole digits above the threshold, until at most 64
+//              remain; one wave then ranks those by comparing all pairs.
 // Only integer atomics are used, so the kept set does not depend on
 // scheduling; the row-compressed factor is then built in row order from the
 // keep masks (k_repack.hip).
@@ -32,6 +32,7 @@ namespace {
 
 constexpr int kRowsPerBlock = 64;  // rows of X per hist/collect block
 constexpr int kPadBins = kBins + 1;
+constexpr int kFinish = 64;  // candidates ranked directly by one wave
 
 struct SelArgs {
   const void* X;
@@ -90,32 +91,21 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
   }
 }
 
-// One block: the threshold digit of every column from the full histogram,
-// which is cleared for the next use.
+// The threshold digit of every column from the full histogram, one wave per
+// column; the histogram is cleared for the next use.
 __global__ __launch_bounds__(256) void k_pick(SelArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins]
   if (*a.status != 0) return;
   const int k = a.k;
-  for (int i0 = threadIdx.x; i0 < k * kBins; i0 += 256 * 8) {
-    uint32_t v[8];
+  const int lane = lane_id();
+  const int nw = gridDim.x * (blockDim.x >> 6);
+  for (int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < k; c += nw) {
+    uint4* hc = reinterpret_cast<uint4*>(a.hist + static_cast<size_t>(c) * kBins);
+    const uint4 q = hc[lane];
+    hc[lane] = make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t v[4] = {q.x, q.y, q.z, q.w};
+    int64_t npos = static_cast<int64_t>(q.x) + q.y + q.z + q.w;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = i0 + 256 * u < k * kBins ? a.hist[i0 + 256 * u] : 0u;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = i0 + 256 * u;
-      if (i < k * kBins) {
-        const int c = i / kBins, d = i - c * kBins;
-        h[c * kPadBins + d] = v[u];
-        a.hist[i] = 0;
-      }
-    }
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < k; c += 256) {
-    const uint32_t* hc = h + c * kPadBins;
-    int64_t npos = 0;
-    for (int d = 0; d < kBins; ++d) npos += hc[d];
+    for (int d = 32; d > 0; d >>= 1) npos += __shfl_xor(npos, d, 64);
     ColSel s;
     s.npos = static_cast<int32_t>(npos);
     s.all = (a.mode == NMF_MODE_NONE || npos <= a.t) ? 1 : 0;
@@ -123,17 +113,10 @@ __global__ __launch_bounds__(256) void k_pick(SelArgs a) {
     s.need = 0;
     if (!s.all) {
       int64_t above = 0;
-      for (int d = kBins - 1; d >= 0; --d) {
-        const int64_t hd = hc[d];
-        if (above + hd >= a.t) {
-          s.b1 = d;
-          s.need = static_cast<int32_t>(a.t - above);
-          break;
-        }
-        above += hd;
-      }
+      s.b1 = wave_pick_bin(v, a.t, &above);
+      s.need = static_cast<int32_t>(a.t - above);
     }
-    a.sel[c] = s;
+    if (lane == 0) a.sel[c] = s;
   }
 }
 
@@ -242,8 +225,6 @@ __global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
   using C = Cand<T>;
   __shared__ uint32_t h[kBins];
   __shared__ int s_bin, s_need, s_n, s_cnt;
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* srt = reinterpret_cast<C*>(smem);  // [kSmall]
   if (*a.status != 0) return;
   const int c = blockIdx.x;
   const int tid = threadIdx.x;
@@ -259,7 +240,7 @@ __global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
   C* dst = static_cast<C*>(a.candB) + static_cast<int64_t>(c) * a.stride;
   int kb = KeyOf<T>::bits - 9;
   int rb = 32;
-  while (n > kSmall && (kb > 0 || rb > 0)) {
+  while (n > kFinish && (kb > 0 || rb > 0)) {
     const int NT = blockDim.x;
     for (int i = tid; i < kBins; i += NT) h[i] = 0;
     __syncthreads();
@@ -274,21 +255,16 @@ __global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
         if (i + NT * u < n) atomicAdd(&h[cand_digit<T>(v[u], kb, rb, &width)], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-      int above = 0;
-      int bin = 0;
-      for (int d = kBins - 1; d >= 0; --d) {
-        const int hd = static_cast<int>(h[d]);
-        if (above + hd >= need) {
-          bin = d;
-          break;
-        }
-        above += hd;
+    if (tid < 64) {
+      const uint32_t v[4] = {h[4 * tid], h[4 * tid + 1], h[4 * tid + 2], h[4 * tid + 3]};
+      int64_t above = 0;
+      const int bin = wave_pick_bin(v, need, &above);
+      if (tid == 0) {
+        s_bin = bin;
+        s_need = need - static_cast<int>(above);
+        s_n = static_cast<int>(h[bin]);
+        s_cnt = 0;
       }
-      s_bin = bin;
-      s_need = need - above;
-      s_n = static_cast<int>(h[bin]);
-      s_cnt = 0;
     }
     __syncthreads();
     const int bin = s_bin;
@@ -327,47 +303,31 @@ __global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
     dst = tmp;
     __syncthreads();
   }
-  // finish: sort the remaining candidates by the compound order (bitonic in
-  // LDS) and keep the first `need`.  Distinct rows make every compound key
-  // distinct, so at most one candidate can survive all digits; more means a
-  // corrupted list, reported instead of overrunning the LDS buffer.
-  if (n > kSmall) {
+  // finish: rank the remaining candidates under the compound order (value
+  // descending, row ascending) on one wave, lane = candidate, and keep the
+  // first `need`.  Distinct rows make every compound key distinct, so the
+  // ranks are distinct; once every digit is fixed at most one candidate is
+  // left, so more than kFinish means a corrupted list, which is reported
+  // instead of read past.
+  if (n > kFinish) {
     if (tid == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_DEVICE));
     return;
   }
-  int np = 1;
-  while (np < n) np <<= 1;
-  for (int i = tid; i < np; i += blockDim.x) {
-    if (i < n) {
-      srt[i] = src[i];
-    } else {
-      C z;
-      z.key = 0;
-      z.row = 0xFFFFFFFFu;
-      srt[i] = z;
+  if (tid < 64) {
+    C me;
+    me.key = 0;
+    me.row = 0xFFFFFFFFu;
+    if (tid < n) me = src[tid];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      C o;
+      o.key = __shfl(me.key, j, 64);
+      o.row = __shfl(me.row, j, 64);
+      rank += cand_before<T>(o, me) ? 1 : 0;
     }
+    if (tid < n && rank < need) mark(a.mask, a.mw, me.row, c);
+    if (tid == 0) *cnt_ptr = 0;
   }
-  __syncthreads();
-  for (int size = 2; size <= np; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < np; i += blockDim.x) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool desc = (i & size) == 0;
-          const C x = srt[i], y = srt[j];
-          // descending blocks put the "before" element first
-          const bool swap = desc ? cand_before<T>(y, x) : cand_before<T>(x, y);
-          if (swap) {
-            srt[i] = y;
-            srt[j] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = tid; i < need && i < n; i += blockDim.x) mark(a.mask, a.mw, srt[i].row, c);
-  if (tid == 0) *cnt_ptr = 0;
 }
 
 template <typename T, int KPL>
@@ -382,9 +342,9 @@ hipError_t run(nmf_handle* h, SelArgs& a) {
   const size_t hbytes = static_cast<size_t>(a.k) * kPadBins * sizeof(uint32_t);
   const size_t stage = static_cast<size_t>(a.k) * kRowsPerBlock * sizeof(Cand<T>);
   hipLaunchKernelGGL((k_hist<T, KPL>), dim3(hblocks), dim3(256), hbytes, h->stream, a);
-  hipLaunchKernelGGL(k_pick, dim3(1), dim3(256), hbytes, h->stream, a);
+  hipLaunchKernelGGL(k_pick, dim3((a.k + 3) / 4), dim3(256), 0, h->stream, a);
   hipLaunchKernelGGL((k_collect<T, KPL>), dim3(blocks), dim3(256), stage, h->stream, a);
-  hipLaunchKernelGGL((k_refine<T>), dim3(a.k), dim3(1024), kSmall * sizeof(Cand<T>), h->stream, a);
+  hipLaunchKernelGGL((k_refine<T>), dim3(a.k), dim3(1024), 0, h->stream, a);
   return hipGetLastError();
 }
 

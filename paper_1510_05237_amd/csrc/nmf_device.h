@@ -83,6 +83,40 @@ __device__ __forceinline__ int block_excl_scan_256(int v, int* tmp, int* total) 
   return off + x - v;
 }
 
+// Radix-select step on one wave: given the 256-bin histogram of the
+// remaining candidates (lane l holds bins 4l .. 4l + 3 in v[0..3]) and need
+// >= 1, find the bin holding the need-th largest candidate: returns it and
+// sets *above to the count in higher bins.  Requires need <= the total.
+__device__ __forceinline__ int wave_pick_bin(const uint32_t* v, int64_t need, int64_t* above) {
+  const int lane = __lane_id();
+  const int64_t mine = static_cast<int64_t>(v[0]) + v[1] + v[2] + v[3];
+  // inclusive suffix sums over lanes (lane l: bins 4l and higher)
+  int64_t suf = mine;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_down(suf, d, 64);
+    if (lane + d < 64) suf += y;
+  }
+  const int64_t higher = suf - mine;  // bins above this lane's four
+  const bool here = higher < need && suf >= need;
+  const uint64_t hb = __ballot(here);
+  const int src = __builtin_ctzll(hb);  // exactly one lane qualifies
+  int bin = 0;
+  int64_t acc = higher;
+  if (here) {
+    bin = 4 * lane;
+    for (int i = 3; i >= 0; --i) {
+      if (acc + v[i] >= need) {
+        bin = 4 * lane + i;
+        break;
+      }
+      acc += v[i];
+    }
+  }
+  *above = __shfl(acc, src, 64);
+  return __shfl(bin, src, 64);
+}
+
 // Release/acquire fences at device (agent) scope around inter-block tickets.
 __device__ __forceinline__ void fence_release() { __threadfence(); }
 __device__ __forceinline__ void fence_acquire() { __threadfence(); }

@@ -21,7 +21,6 @@ constexpr int kChunk = 2048;     // nonzeros per SpMM work item; longer rows are
 // batch): 8 with one topic per lane, 4 with two.
 inline int spmm_row_group(int k) { return k > 64 ? 4 : 8; }
 constexpr int kBins = 256;       // radix digit width of the top-t select (8 bits)
-constexpr int kSmall = 2048;     // candidates finished by an in-LDS sort
 constexpr int kHistRing = 4096;  // iterations kept in the device history ring
 constexpr int kGramBlocks = 240; // Gram partial blocks (fixed: deterministic sums)
 constexpr int kMetricBlocks = 240;
