@@ -44,7 +44,8 @@ typedef enum {
   NMF_OK = 0,
   NMF_ERR_INVALID_ARG = -1,   /* bad size, null pointer, malformed CSR      */
   NMF_ERR_INVALID_INPUT = -2, /* negative, NaN or Inf value in A or factors  */
-  NMF_ERR_UNSUPPORTED = -3,   /* k > 128, unknown dtype or mode              */
+  NMF_ERR_UNSUPPORTED = -3,   /* k > 128, n or m >= 2^29, rows * k >= 2^31,
+                                 unknown dtype or mode                        */
   NMF_ERR_NOT_SPD = -4,       /* Gram matrix not positive definite           */
   NMF_ERR_NONFINITE = -5,     /* NaN/Inf produced (e.g. ||U_i|| = 0 in R)    */
   NMF_ERR_DEVICE = -6,        /* a HIP runtime call failed                   */
@@ -69,8 +70,8 @@ enum {
 };
 
 typedef struct {
-  int64_t n;     /* terms (rows of A, rows of U)                  */
-  int64_t m;     /* documents (columns of A, rows of V)           */
+  int64_t n;     /* terms (rows of A, rows of U), 1 <= n < 2^29   */
+  int64_t m;     /* documents (columns of A, rows of V), < 2^29   */
   int32_t k;     /* topics, 1 <= k <= min(n, m, 128)               */
   int32_t mode;  /* NMF_MODE_*                                     */
   int64_t t_u;   /* kept entries per column of U (>= 1)            */

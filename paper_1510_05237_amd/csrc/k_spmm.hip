@@ -42,12 +42,14 @@ constexpr int queue_len() {
   return WIDE ? 136 : 64;
 }
 
-__host__ __device__ inline int tile_pitch(int k) { return (k + 3) & ~3; }
+// Each wave's accumulator has a row slot for all 64 * KPL lanes of every
+// topic slice (RG * 64 * KPL = 512 entries), so lanes past k can add their
+// zero-weight sums without a guard and the row-change test stays uniform.
+constexpr int kTileEntries = 512;
 
 template <typename T, int RG, bool WIDE>
-__host__ __device__ inline size_t spmm_per_wave(int k) {
-  return queue_len<WIDE>() * (2 * sizeof(int32_t) + sizeof(T)) +
-         static_cast<size_t>(RG) * tile_pitch(k) * sizeof(T);
+__host__ __device__ inline size_t spmm_per_wave(int) {
+  return queue_len<WIDE>() * (sizeof(uint32_t) + sizeof(T)) + kTileEntries * sizeof(T);
 }
 
 // LDS of one block: W (unless raw), then each wave's buffers.
@@ -81,8 +83,7 @@ struct SpmmArgs {
 };
 
 struct WaveLds {
-  int32_t* q_off;  // dense-row queue: offset of the factor row in F
-  int32_t* q_row;  //                  row within the item
+  uint32_t* q_pk;  // dense-row queue: factor row * 8 + row within the item
   void* q_a;       //                  the nonzero's value
   void* tile;      // accumulator: tile[topic * RG + row]
 };
@@ -92,10 +93,9 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, size_t wave0, i
   constexpr int Q = queue_len<WIDE>();
   unsigned char* base = smem + wave0 + wv * spmm_per_wave<T, RG, WIDE>(k);
   WaveLds w;
-  w.q_off = reinterpret_cast<int32_t*>(base);
-  w.q_row = reinterpret_cast<int32_t*>(base + Q * sizeof(int32_t));
-  w.q_a = base + 2 * Q * sizeof(int32_t);
-  w.tile = base + Q * (2 * sizeof(int32_t) + sizeof(T));
+  w.q_a = base;  // T first: 8-byte aligned for double
+  w.q_pk = reinterpret_cast<uint32_t*>(base + Q * sizeof(T));
+  w.tile = base + Q * (sizeof(T) + sizeof(uint32_t));
   return w;
 }
 
@@ -112,42 +112,61 @@ __device__ __forceinline__ size_t load_block(const SpmmArgs& a, unsigned char* s
   return RAW ? 0 : static_cast<size_t>(k) * k * sizeof(double);
 }
 
-// Adds one part of the queue (entries [q0, q0 + n8), n8 a multiple of 8, in
-// row order) into the accumulator: eight factor rows in flight, from Fsrc at
-// the queued offsets; sums for the current row kept in acc.
+// Wave-uniform copy of a value every lane holds (an SGPR operand).
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// Adds the queued entries [0, n8) (n8 a multiple of 8, in row order) into
+// the accumulator: eight factor rows in flight, lanes = topics, sums for the
+// current row kept in acc.  The queued row word is the same on all lanes and
+// is moved to a scalar register, so the row address is formed on the scalar
+// unit and the row-change test is a scalar branch; the value is an LDS
+// broadcast.  A hit then costs one vector FMA per topic slice.
 template <typename T, int KPL, int RG>
-__device__ __forceinline__ void run_queue(const WaveLds& w, const T* Fsrc, int q0, int n8, int k, T* acc,
+__device__ __forceinline__ void run_queue(const WaveLds& w, const T* F, int ld, int n8, int k, T* acc,
                                           int& cur_r) {
   const int lane = lane_id();
   T* tile = static_cast<T*>(w.tile);
   const T* q_a = static_cast<const T*>(w.q_a);
-  for (int h = q0; h < q0 + n8; h += 8) {
-    int32_t o[8], rr[8];
+  uint32_t cc[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    cc[q] = static_cast<uint32_t>(c < k ? c : 0);
+  }
+  for (int h = 0; h < n8; h += 8) {
+    uint32_t pk[8];
     T aa[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      o[u] = w.q_off[h + u];
-      rr[u] = w.q_row[h + u];
+      pk[u] = uniform(w.q_pk[h + u]);
       aa[u] = q_a[h + u];
     }
     T f[8][KPL];
 #pragma unroll
-    for (int q = 0; q < KPL; ++q) {
-      const int c = lane + 64 * q;
-      const int cc = c < k ? c : 0;
+    for (int u = 0; u < 8; ++u) {
+      const T* row = F + static_cast<size_t>(pk[u] >> 3) * static_cast<uint32_t>(ld);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) f[u][q] = Fsrc[o[u] + cc];
+      for (int q = 0; q < KPL; ++q) f[u][q] = row[cc[q]];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (rr[u] != cur_r) {  // rows are queued in order: flush on a change
+      const int rr = static_cast<int>(pk[u] & 7u);
+      if (rr != cur_r) {  // rows are queued in order: flush on a change
 #pragma unroll
         for (int q = 0; q < KPL; ++q) {
-          const int c = lane + 64 * q;
-          if (c < k) tile[c * RG + cur_r] += acc[q];
+          tile[(lane + 64 * q) * RG + cur_r] += acc[q];
           acc[q] = T(0);
         }
-        cur_r = rr[u];
+        cur_r = rr;
       }
 #pragma unroll
       for (int q = 0; q < KPL; ++q) acc[q] = fma(aa[u], f[u][q], acc[q]);
@@ -160,7 +179,7 @@ __device__ __forceinline__ void run_queue(const WaveLds& w, const T* Fsrc, int q
 // batches of 8 with zero-weight reads of the first factor row at the last
 // hit's row; returns the padded length.
 template <typename T, int NS>
-__device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, const int32_t* off, const int* r,
+__device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, const int32_t* x, const int* r,
                                           const T* av) {
   const int lane = lane_id();
   T* q_a = static_cast<T*>(w.q_a);
@@ -178,8 +197,7 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
   for (int s = 0; s < NS; ++s) {
     if (hit[s]) {
       const int pos = before[s] + lane_rank(bal[s]);
-      w.q_off[pos] = off[s];
-      w.q_row[pos] = r[s];
+      w.q_pk[pos] = static_cast<uint32_t>(x[s]) * 8u + static_cast<uint32_t>(r[s]);
       q_a[pos] = av[s];
     }
   }
@@ -194,8 +212,7 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
   const int r_last = __shfl(r_src, 63 - __builtin_clzll(bal[last_s]), 64);
   const int nh8 = (nh + 7) & ~7;
   if (lane < nh8 - nh) {
-    w.q_off[nh + lane] = 0;
-    w.q_row[nh + lane] = r_last;
+    w.q_pk[nh + lane] = static_cast<uint32_t>(r_last);
     q_a[nh + lane] = T(0);
   }
   return nh8;
@@ -319,20 +336,13 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
     }
     // dense factor rows: queued, then one k-wide row per hit, lanes = topics
     bool hit[NS];
-    int32_t off[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      hit[s] = DENSE_IN ? valid[s] : cnt[s] > a.sparse_row;
-      off[s] = x[s] * a.ld;
-    }
-    const int nq = queue_hits<T, NS>(w, hit, off, r, av);
-    run_queue<T, KPL, RG>(w, F, 0, nq, k, acc, cur_r);
+    for (int s = 0; s < NS; ++s) hit[s] = DENSE_IN ? valid[s] : cnt[s] > a.sparse_row;
+    const int nq = queue_hits<T, NS>(w, hit, x, r, av);
+    run_queue<T, KPL, RG>(w, F, a.ld, nq, k, acc, cur_r);
   }
 #pragma unroll
-  for (int q = 0; q < KPL; ++q) {
-    const int c = lane + 64 * q;
-    if (c < k) tile[c * RG + cur_r] += acc[q];
-  }
+  for (int q = 0; q < KPL; ++q) tile[(lane + 64 * q) * RG + cur_r] += acc[q];
 }
 
 // tile layout: tile[rr * RG + r] = raw sum of row r, topic rr.
@@ -389,20 +399,15 @@ __device__ __forceinline__ void epilogue(const SpmmArgs& a, const T* tile, const
 }
 
 template <typename T, int KPL, int RG>
-__device__ __forceinline__ void clear_tile(T* tile, int k) {
+__device__ __forceinline__ void clear_tile(T* tile, int) {
   const int lane = lane_id();
 #pragma unroll
-  for (int q = 0; q < KPL; ++q) {
-    const int c = lane + 64 * q;
-    if (c < k) {
-#pragma unroll
-      for (int r = 0; r < RG; ++r) tile[c * RG + r] = T(0);
-    }
-  }
+  for (int i = 0; i < kTileEntries / 64; ++i) tile[lane + 64 * i] = T(0);
 }
 
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
 __global__ __launch_bounds__(64 * kWaves) void k_spmm(SpmmArgs a) {
+  static_assert(RG * 64 * KPL <= kTileEntries, "accumulator too small for the row group");
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
   const int k = a.k;
@@ -458,7 +463,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy(SpmmArgs a) {
   }
   __syncthreads();
   const size_t wave0 = RAW ? 0 : static_cast<size_t>(k) * k * sizeof(double);
-  T* tile = reinterpret_cast<T*>(smem + wave0) + static_cast<size_t>(wv) * RG * tile_pitch(k);
+  T* tile = reinterpret_cast<T*>(smem + wave0) + static_cast<size_t>(wv) * kTileEntries;
   const T* part = static_cast<const T*>(a.partials);
   const int bw = blockDim.x >> 6;
   const int nw = gridDim.x * bw;

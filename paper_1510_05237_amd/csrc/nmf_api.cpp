@@ -213,8 +213,9 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
 nmf_status check_config(const nmf_config* c) {
   if (c == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "config is NULL");
   if (c->n < 1 || c->m < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "n and m must be >= 1");
-  if (c->n >= (int64_t(1) << 31) || c->m >= (int64_t(1) << 31))
-    return fail(nullptr, NMF_ERR_UNSUPPORTED, "n and m must be below 2^31");
+  // the SpMM queues a factor row index * 8 + row-in-item in 32 bits
+  if (c->n >= (int64_t(1) << 29) || c->m >= (int64_t(1) << 29))
+    return fail(nullptr, NMF_ERR_UNSUPPORTED, "n and m must be below 2^29");
   if (c->k < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "k must be >= 1");
   if (c->k > kMaxK) return fail(nullptr, NMF_ERR_UNSUPPORTED, "k must be <= 128");
   if (c->k > c->n || c->k > c->m) return fail(nullptr, NMF_ERR_INVALID_ARG, "k must be <= min(n, m)");

@@ -52,6 +52,9 @@ def test_workspace_size_grows_with_problem():
     (dict(mode=7), B.NMF_ERR_UNSUPPORTED),
     (dict(dtype=3), B.NMF_ERR_UNSUPPORTED),
     (dict(n=0), B.NMF_ERR_INVALID_ARG),
+    (dict(n=1 << 29), B.NMF_ERR_UNSUPPORTED),
+    (dict(m=1 << 29), B.NMF_ERR_UNSUPPORTED),
+    (dict(m=(1 << 31) // 50, k=50), B.NMF_ERR_UNSUPPORTED),
 ])
 def test_config_validation(kw, status):
     with pytest.raises(B.NMFError) as ei:
