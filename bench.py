@@ -8,8 +8,11 @@ workload with k = 50, t_u = 1000, t_v = 2000.  Inputs are synthetic (Zipf
 terms, lognormal TF-IDF values) and resident in HBM before timing starts.
 
 Prints one JSON line: iterations/s, plus the SpMM roofline (algorithmic
-bytes per launch / event-timed launch duration) and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+bytes per launch / event-timed launch duration), the FP64 CPU oracle timed
+on a bounded sample of the same workload, and the batched comparison: 256
+independent corpora of uneven size (n in [500, 50k], m in [300, 20k],
+density 0.1-2 %, k in 5..64) solved per problem, per problem under a HIP
+graph, and with one launch per stage for all of them under a HIP graph.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
     python bench.py --copy-calibration      # plain copy kernel for counter scaling
@@ -102,6 +105,64 @@ def cpu_baseline(corpus, u0, p, iters: int):
     }
 
 
+def batch_bench(problems, iters: int, warmup: int):
+    """The many-corpora workload solved three ways from the same start: (i) a
+    per-problem loop of ALS iterations, (ii) that loop captured as a HIP
+    graph, (iii) one launch per stage for all problems, captured as a graph
+    (plus (iii) without the graph).  Every variant restarts each problem from
+    its U0 and must end at bit-identical errors (equal accuracy)."""
+    import numpy as np
+    import torch
+
+    from paper_1510_05237_amd import NMFBatch
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    b = NMFBatch(problems, dtype="f32", device=dev)
+    u0d = [torch.from_numpy(p["u0"]).to(dev) for p in problems]
+    torch.cuda.synchronize()
+    log(f"batch: created {len(problems)} problems in {time.perf_counter() - t0:.1f}s "
+        f"(workspace {b.ws_bytes / 2**30:.2f} GiB)")
+
+    def restart():
+        for i, u in enumerate(u0d):
+            b.problem(i).set_factors(u)
+        torch.cuda.synchronize()
+
+    res, errs = {}, {}
+    for how in ("loop", "loop_graph", "fused", "fused_graph"):
+        restart()
+        b.step(warmup, how)  # graph modes capture here
+        restart()
+        t0 = time.perf_counter()
+        b.step(iters, how)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        E, st = b.errors()
+        errs[how] = E
+        res[how] = dt * 1e3 / iters
+        log(f"batch {how}: {res[how]:.3f} ms per batch iteration")
+        if np.any(st != 0):
+            raise RuntimeError(f"batch {how}: member status {st[st != 0][:4]}")
+    equal = all(np.array_equal(errs["loop"], e) for e in errs.values())
+    nnz = sum(int(p["indptr"][-1]) for p in problems)
+    b.close()
+    del u0d
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"batch_{len(problems)}_corpora",
+        "problems": len(problems),
+        "nnz_total": nnz,
+        "iters": iters,
+        "warmup": warmup,
+        "ms_per_batch_iteration": {h: round(v, 3) for h, v in res.items()},
+        "problem_iters_per_s": {h: round(len(problems) * 1e3 / v, 1) for h, v in res.items()},
+        "speedup_vs_loop": {h: round(res["loop"] / v, 2) for h, v in res.items()},
+        "equal_accuracy": bool(equal),
+        "E_mean": float(np.mean(errs["fused_graph"])),
+    }
+
+
 def copy_calibration(gib: float = 1.0, reps: int = 5):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     import torch
@@ -124,6 +185,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="corpora in the batched comparison (0: skip)")
+    ap.add_argument("--batch-iters", type=int, default=30)
+    ap.add_argument("--batch-warmup", type=int, default=2)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -140,6 +204,14 @@ def main():
     import synth
     from paper_1510_05237_amd import NMF
 
+    batch = None
+    if args.batch > 0:
+        # drawn before anything touches the GPU: the generator forks workers
+        t0 = time.perf_counter()
+        batch = synth.make_batch(synth.batched_params(args.batch), dtype="f32",
+                                 workers=min(16, os.cpu_count() or 1))
+        log(f"generated the {args.batch}-corpus batch ({sum(p['nnz'] for p in batch)} nnz) "
+            f"in {time.perf_counter() - t0:.1f}s")
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     log(f"generating {args.workload}")
@@ -231,6 +303,8 @@ def main():
     prob.close()
     del rp, ci, cv, u0d
     torch.cuda.empty_cache()
+    out["batched"] = batch_bench(batch, args.batch_iters, args.batch_warmup) if batch else None
+    batch = None
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(corpus, u0, p, args.cpu_iters)

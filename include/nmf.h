@@ -223,6 +223,70 @@ const char* nmf_last_error(const nmf_handle* h);
  * Waits for the handle's stream.  NULL is allowed. */
 void nmf_destroy(nmf_handle* h);
 
+/* ---- Batched solving: many independent problems advanced together -------
+ *
+ * Each problem is the method above (Algorithm 2 with the per-column rule of
+ * Section 4) on its own A, U0, k and t; problems may differ in every size.
+ * A batch owns one handle per problem (reachable with nmf_batch_problem for
+ * errors, histories and factors) and advances all of them the same number of
+ * iterations.  Four ways to run the same iterations, all producing bitwise
+ * identical factors:
+ *   NMF_BATCH_LOOP         every problem's own launches, problem after problem
+ *                          (what a caller looping over nmf_als_step does);
+ *   NMF_BATCH_LOOP_GRAPH   the same launches captured once as a HIP graph of
+ *                          two iterations and replayed;
+ *   NMF_BATCH_FUSED        one launch per stage for all problems: every block
+ *                          of the launch serves one (problem, block) pair of
+ *                          that problem's own grid;
+ *   NMF_BATCH_FUSED_GRAPH  the fused launches captured as a HIP graph of two
+ *                          iterations and replayed. */
+typedef struct nmf_batch nmf_batch;
+
+enum { NMF_BATCH_LOOP = 0, NMF_BATCH_LOOP_GRAPH = 1, NMF_BATCH_FUSED = 2, NMF_BATCH_FUSED_GRAPH = 3 };
+
+/* Device workspace bytes for a batch of `count` problems (cfgs[i], nnz[i]):
+ * the problems' own workspaces plus the fused launch tables.
+ * Errors: INVALID_ARG, UNSUPPORTED (as nmf_workspace_size, per problem). */
+nmf_status nmf_batch_workspace_size(int32_t count, const nmf_config* cfgs, const int64_t* nnz, size_t* bytes);
+
+/* Create a batch.  Arrays of `count` entries: cfgs, a_rowptr, a_col, a_val,
+ * nnz and u0 are as the arguments of nmf_create for each problem (host or
+ * device pointers; V0 is not taken).  workspace: device, 256-byte aligned, at
+ * least nmf_batch_workspace_size bytes, owned by the caller and untouched
+ * after nmf_batch_destroy.  hip_stream: the stream every problem runs on; the
+ * graph modes need a stream that can be captured, so with NULL the batch
+ * creates (and later destroys) a stream of its own.  *out receives the
+ * batch.  Errors: those of nmf_create (the first failing problem's, with its
+ * index in the message), WORKSPACE. */
+nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t* const* a_rowptr,
+                            const int32_t* const* a_col, const void* const* a_val, const int64_t* nnz,
+                            const void* const* u0, void* workspace, size_t ws_bytes, void* hip_stream,
+                            nmf_batch** out);
+
+/* Enqueue `iters` ALS iterations of every problem, run as `how`
+ * (NMF_BATCH_*).  Asynchronous.  A problem whose device status turns sticky
+ * stops advancing (its kernels return at once) while the others continue.
+ * The first graph-mode call captures the graph (and so takes longer).
+ * Errors: INVALID_ARG (iters < 0, unknown how), DEVICE. */
+nmf_status nmf_batch_step(nmf_batch* b, int32_t iters, int32_t how);
+
+/* Wait for the batch, then for every problem i: E[i] = its relative error
+ * (as nmf_error) and status[i] = its status (NMF_OK or the sticky error).
+ * Either array may be NULL.  Returns NMF_OK when every problem is OK, else
+ * the first problem's error. */
+nmf_status nmf_batch_errors(nmf_batch* b, double* E, int32_t* status);
+
+/* The handle of problem i (owned by the batch: do not destroy it), or NULL. */
+nmf_handle* nmf_batch_problem(nmf_batch* b, int32_t i);
+
+/* Message for the last error of the batch (or of the last failed
+ * nmf_batch_create when b is NULL).  Never NULL. */
+const char* nmf_batch_last_error(const nmf_batch* b);
+
+/* Release the batch and its problems' handles (host memory and the batch's
+ * own stream and graphs).  NULL is allowed. */
+void nmf_batch_destroy(nmf_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

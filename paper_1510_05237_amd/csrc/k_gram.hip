@@ -18,6 +18,8 @@
 //        sets the sticky status NMF_ERR_NOT_SPD.
 // G itself is stored without the dead-topic substitution (the error of
 // Section 3.1 needs the true Gram matrices).
+#include <algorithm>
+
 #include "nmf_device.h"
 
 namespace nmfk {
@@ -42,6 +44,7 @@ struct GramArgs {
   const int32_t* counts_a;
   const int32_t* counts_b;
   int64_t* max_nnz;
+  int32_t nparts;  // partial blocks (grid of the partial kernel)
 };
 
 __device__ __forceinline__ void tri_index(int e, int k, int* pa, int* pb) {
@@ -58,7 +61,7 @@ __device__ __forceinline__ void tri_index(int e, int k, int* pa, int* pb) {
 }
 
 template <typename T, int JMAX>
-__global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) {
+__device__ __forceinline__ void k_gram_partial_body(const GramArgs& g, int blk, int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (*g.status != 0) return;
   const int k = g.k;
@@ -66,9 +69,9 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) {
   const int ne = k * (k + 1) / 2;
   const int tid = threadIdx.x;
   const int64_t R = g.rows_dev ? static_cast<int64_t>(*g.rows_dev) : g.rows_host;
-  const int P = gridDim.x;
-  const int64_t lo = R * blockIdx.x / P;
-  const int64_t hi = R * (blockIdx.x + 1) / P;
+  const int P = nblk;
+  const int64_t lo = R * blk / P;
+  const int64_t hi = R * (blk + 1) / P;
   T* stage = reinterpret_cast<T*>(smem);
   int ea[JMAX], eb[JMAX];
   T acc[JMAX];
@@ -109,36 +112,45 @@ __global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) {
       for (int j = 0; j < JMAX; ++j) acc[j] = fma(row[ea[j]], row[eb[j]], acc[j]);
     }
   }
-  T* part = static_cast<T*>(g.partials) + static_cast<int64_t>(blockIdx.x) * ne;
+  T* part = static_cast<T*>(g.partials) + static_cast<int64_t>(blk) * ne;
 #pragma unroll
   for (int j = 0; j < JMAX; ++j) {
     const int e = tid + 256 * j;
     if (e < ne) part[e] = acc[j];
   }
 }
+template <typename T, int JMAX>
+__global__ __launch_bounds__(256) void k_gram_partial(GramArgs g) { k_gram_partial_body<T, JMAX>(g, blockIdx.x, gridDim.x); }
+template <typename T, int JMAX>
+__global__ __launch_bounds__(256) void k_gram_partial_b(const GramArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const GramArgs g = as[m.prob];
+  k_gram_partial_body<T, JMAX>(g, m.blk, m.nblk);
+}
+
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
+__device__ __forceinline__ void k_gram_reduce_body(const GramArgs& g, int blk, int nblk) {
   __shared__ double red[4][kReduceEntries];
   if (*g.status != 0) return;
   const int k = g.k;
   const int ne = k * (k + 1) / 2;
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
-  const int e = blockIdx.x * kReduceEntries + lane;
+  const int e = blk * kReduceEntries + lane;
   const T* __restrict__ part = static_cast<const T*>(g.partials);
   double s = 0.0;
   if (e < ne) {
     // wave wv adds partials wv, wv + 4, ... in order, eight loads in flight
     int b = wv;
-    for (; b + 28 < kGramBlocks; b += 32) {
+    for (; b + 28 < g.nparts; b += 32) {
       T v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[u] = part[static_cast<int64_t>(b + 4 * u) * ne + e];
 #pragma unroll
       for (int u = 0; u < 8; ++u) s += static_cast<double>(v[u]);
     }
-    for (; b < kGramBlocks; b += 4) s += static_cast<double>(part[static_cast<int64_t>(b) * ne + e]);
+    for (; b < g.nparts; b += 4) s += static_cast<double>(part[static_cast<int64_t>(b) * ne + e]);
   }
   red[wv][lane] = s;
   __syncthreads();
@@ -150,6 +162,15 @@ __global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) {
     g.G[b * k + a] = t;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_reduce(GramArgs g) { k_gram_reduce_body<T>(g, blockIdx.x, gridDim.x); }
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_reduce_b(const GramArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const GramArgs g = as[m.prob];
+  k_gram_reduce_body<T>(g, m.blk, m.nblk);
+}
+
 
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
@@ -162,7 +183,7 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // a contiguous slice of the block's rows; the block adds its waves' tiles in
 // wave order and stores the upper triangle like k_gram_partial.
 template <int NB>
-__global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) {
+__device__ __forceinline__ void k_gram_mfma_body(const GramArgs& g, int blk, int nblk) {
   constexpr int NP = NB * (NB + 1) / 2;  // tiles (ta <= tb)
   __shared__ float red[4][NP][64][4];
   if (*g.status != 0) return;
@@ -171,8 +192,8 @@ __global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) {
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   const int64_t R = g.rows_dev ? static_cast<int64_t>(*g.rows_dev) : g.rows_host;
-  const int P = gridDim.x;
-  const int64_t blo = R * blockIdx.x / P, bhi = R * (blockIdx.x + 1) / P;
+  const int P = nblk;
+  const int64_t blo = R * blk / P, bhi = R * (blk + 1) / P;
   const int64_t lo = blo + (bhi - blo) * wv / 4, hi = blo + (bhi - blo) * (wv + 1) / 4;
   const float* __restrict__ F = static_cast<const float*>(g.F);
   mfma_f4 acc[NP];
@@ -210,7 +231,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) {
     for (int i = 0; i < 4; ++i) red[wv][t][lane][i] = acc[t][i];
   __syncthreads();
   const int ne = k * (k + 1) / 2;
-  float* part = static_cast<float*>(g.partials) + static_cast<int64_t>(blockIdx.x) * ne;
+  float* part = static_cast<float*>(g.partials) + static_cast<int64_t>(blk) * ne;
   for (int x = threadIdx.x; x < NP * 256; x += 256) {
     const int t = x >> 8, l = (x >> 2) & 63, i = x & 3;
     const float v = ((red[0][t][l][i] + red[1][t][l][i]) + red[2][t][l][i]) + red[3][t][l][i];
@@ -225,6 +246,15 @@ __global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) {
     if (a <= b && b < k) part[a * k - a * (a - 1) / 2 + (b - a)] = v;
   }
 }
+template <int NB>
+__global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) { k_gram_mfma_body<NB>(g, blockIdx.x, gridDim.x); }
+template <int NB>
+__global__ __launch_bounds__(256) void k_gram_mfma_b(const GramArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const GramArgs g = as[m.prob];
+  k_gram_mfma_body<NB>(g, m.blk, m.nblk);
+}
+
 
 // One block: the storage high-water mark, then W = G^-1 in float64 by
 // Gauss-Jordan elimination on the symmetric positive definite G.  Without
@@ -241,7 +271,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(GramArgs g) {
 constexpr int kFactorThreads = 1024;
 
 template <int KM>
-__global__ __launch_bounds__(kFactorThreads) void k_gram_factor(GramArgs g) {
+__device__ __forceinline__ void k_gram_factor_body(const GramArgs& g, int blk, int nblk) {
   constexpr int TPR = kFactorThreads / KM;  // threads per row
   constexpr int NQ = KM / TPR;              // entries per thread
   __shared__ double rowb[2][KM], colb[2][KM];
@@ -333,36 +363,45 @@ __global__ __launch_bounds__(kFactorThreads) void k_gram_factor(GramArgs g) {
     }
   }
 }
+template <int KM>
+__global__ __launch_bounds__(kFactorThreads) void k_gram_factor(GramArgs g) { k_gram_factor_body<KM>(g, blockIdx.x, gridDim.x); }
+template <int KM>
+__global__ __launch_bounds__(kFactorThreads) void k_gram_factor_b(const GramArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const GramArgs g = as[m.prob];
+  k_gram_factor_body<KM>(g, m.blk, m.nblk);
+}
+
 
 template <typename T>
-hipError_t launch(nmf_handle* h, GramArgs& g) {
+hipError_t launch(nmf_handle* h, GramArgs& g, int64_t rows_bound) {
   const int k = h->k;
   const int kpad = (k + 3) & ~3;
   const size_t stage = static_cast<size_t>(kStageRows) * kpad * sizeof(T);
+  // one partial block per 64 possible rows, at most kGramBlocks
+  g.nparts = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(kGramBlocks, (rows_bound + 63) / 64)));
+  const unsigned P = static_cast<unsigned>(g.nparts);
+  hipError_t e;
   if (sizeof(T) == 4) {
     if (k <= 32)
-      hipLaunchKernelGGL(k_gram_mfma<2>, dim3(kGramBlocks), dim3(256), 0, h->stream, g);
+      e = launch_rec(h, k_gram_mfma<2>, k_gram_mfma_b<2>, P, 256, 0, g);
     else if (k <= 64)
-      hipLaunchKernelGGL(k_gram_mfma<4>, dim3(kGramBlocks), dim3(256), 0, h->stream, g);
+      e = launch_rec(h, k_gram_mfma<4>, k_gram_mfma_b<4>, P, 256, 0, g);
     else
-      hipLaunchKernelGGL(k_gram_mfma<8>, dim3(kGramBlocks), dim3(256), 0, h->stream, g);
+      e = launch_rec(h, k_gram_mfma<8>, k_gram_mfma_b<8>, P, 256, 0, g);
   } else if (k <= 64) {
-    hipLaunchKernelGGL((k_gram_partial<T, 9>), dim3(kGramBlocks), dim3(256), stage, h->stream, g);
+    e = launch_rec(h, k_gram_partial<T, 9>, k_gram_partial_b<T, 9>, P, 256, stage, g);
   } else {
-    hipLaunchKernelGGL((k_gram_partial<T, 33>), dim3(kGramBlocks), dim3(256), stage, h->stream, g);
+    e = launch_rec(h, k_gram_partial<T, 33>, k_gram_partial_b<T, 33>, P, 256, stage, g);
   }
+  if (e != hipSuccess) return e;
   const int ne = k * (k + 1) / 2;
-  const int rblocks = (ne + kReduceEntries - 1) / kReduceEntries;
-  hipLaunchKernelGGL((k_gram_reduce<T>), dim3(rblocks), dim3(256), 0, h->stream, g);
-  if (g.W) {
-    if (k <= 32)
-      hipLaunchKernelGGL(k_gram_factor<32>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
-    else if (k <= 64)
-      hipLaunchKernelGGL(k_gram_factor<64>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
-    else
-      hipLaunchKernelGGL(k_gram_factor<128>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
-  }
-  return hipGetLastError();
+  const unsigned rblocks = static_cast<unsigned>((ne + kReduceEntries - 1) / kReduceEntries);
+  if ((e = launch_rec(h, k_gram_reduce<T>, k_gram_reduce_b<T>, rblocks, 256, 0, g)) != hipSuccess) return e;
+  if (!g.W) return hipSuccess;
+  if (k <= 32) return launch_rec(h, k_gram_factor<32>, k_gram_factor_b<32>, 1, kFactorThreads, 0, g);
+  if (k <= 64) return launch_rec(h, k_gram_factor<64>, k_gram_factor_b<64>, 1, kFactorThreads, 0, g);
+  return launch_rec(h, k_gram_factor<128>, k_gram_factor_b<128>, 1, kFactorThreads, 0, g);
 }
 
 }  // namespace
@@ -384,7 +423,7 @@ hipError_t gram(nmf_handle* h, const Factor& F, const Gram& out) {
   g.counts_a = F.counts;
   g.counts_b = is_v ? h->U[h->cur_u].counts : h->V.counts;
   g.max_nnz = h->met.max_nnz;
-  return launch<T>(h, g);
+  return launch<T>(h, g, F.rows);
 }
 
 template <typename T>
@@ -399,7 +438,7 @@ hipError_t gram_dense(nmf_handle* h, const T* F, int64_t rows, double* G) {
   g.G = G;
   g.W = nullptr;
   g.status = h->status;
-  return launch<T>(h, g);
+  return launch<T>(h, g, rows);
 }
 
 template hipError_t gram<float>(nmf_handle*, const Factor&, const Gram&);

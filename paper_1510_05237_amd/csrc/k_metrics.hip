@@ -11,6 +11,8 @@
 // one-block final kernel, so the history is reproducible bit for bit.
 #include <cmath>
 
+#include <algorithm>
+
 #include "nmf_device.h"
 
 namespace nmfk {
@@ -68,11 +70,12 @@ struct MetArgs {
   const int32_t* dead_u;
   const int32_t* dead_v;
   int32_t record;  // 0: only nnz / dead counts (E, R = NaN)
+  int32_t nparts;  // partial blocks of k_metrics
   int32_t* status;
 };
 
 template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
+__device__ __forceinline__ void k_metrics_body(const MetArgs& a, int blk, int nblk) {
   __shared__ double sh[12];
   __shared__ double tot[3];
   if (*a.status != 0) return;
@@ -81,9 +84,9 @@ __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
   const int wv = threadIdx.x >> 6;
   double d2 = 0.0, n2 = 0.0, x = 0.0;
   if (a.record) {
-    const int P = gridDim.x;
-    const int64_t lo = a.n * blockIdx.x / P;
-    const int64_t hi = a.n * (blockIdx.x + 1) / P;
+    const int P = nblk;
+    const int64_t lo = a.n * blk / P;
+    const int64_t hi = a.n * (blk + 1) / P;
     const T* __restrict__ Dn = static_cast<const T*>(a.dense_new);
     const T* __restrict__ Do = static_cast<const T*>(a.dense_old);
     const T* __restrict__ C = static_cast<const T*>(a.C);
@@ -135,16 +138,26 @@ __global__ __launch_bounds__(256) void k_metrics(MetArgs a) {
   }
   block_sum3(d2, n2, x, sh, tot);
   if (threadIdx.x == 0) {
-    double* p = a.partials + blockIdx.x * 4;
+    double* p = a.partials + blk * 4;
     p[0] = tot[0];
     p[1] = tot[1];
     p[2] = tot[2];
   }
 }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_metrics(MetArgs a) { k_metrics_body<T, KPL>(a, blockIdx.x, gridDim.x); }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_metrics_b(const MetArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const MetArgs a = as[m.prob];
+  k_metrics_body<T, KPL>(a, m.blk, m.nblk);
+}
+
 
 // One block: add the block partials in block order, the quadratic term
 // <G_U, G_V>, then E and R into the history ring.
-__global__ __launch_bounds__(256) void k_metrics_final(MetArgs a, int nparts) {
+__device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, int nblk) {
+  const int nparts = a.nparts;
   __shared__ double sh[12];
   __shared__ double tot[3];
   __shared__ double pv[kMetricBlocks * 3];
@@ -181,6 +194,13 @@ __global__ __launch_bounds__(256) void k_metrics_final(MetArgs a, int nparts) {
   rec[H_DEADV] = static_cast<double>(*a.dead_v);
   *a.it = it + 1;
 }
+__global__ __launch_bounds__(256) void k_metrics_final(MetArgs a) { k_metrics_final_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void k_metrics_final_b(const MetArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const MetArgs a = as[m.prob];
+  k_metrics_final_body(a, m.blk, m.nblk);
+}
+
 
 // <U, C> for dense U, C (n x k): block partials ...
 template <typename T>
@@ -334,12 +354,13 @@ hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const 
   a.dead_v = h->gV.dead;
   a.record = record ? 1 : 0;
   a.status = h->status;
-  if (h->k > 64)
-    hipLaunchKernelGGL((k_metrics<T, 2>), dim3(kMetricBlocks), dim3(256), 0, h->stream, a);
-  else
-    hipLaunchKernelGGL((k_metrics<T, 1>), dim3(kMetricBlocks), dim3(256), 0, h->stream, a);
-  hipLaunchKernelGGL(k_metrics_final, dim3(1), dim3(256), 0, h->stream, a, kMetricBlocks);
-  return hipGetLastError();
+  // one partial block per 64 rows, at most kMetricBlocks
+  a.nparts = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(kMetricBlocks, (h->n + 63) / 64)));
+  const unsigned P = static_cast<unsigned>(a.nparts);
+  hipError_t e = h->k > 64 ? launch_rec(h, k_metrics<T, 2>, k_metrics_b<T, 2>, P, 256, 0, a)
+                           : launch_rec(h, k_metrics<T, 1>, k_metrics_b<T, 1>, P, 256, 0, a);
+  if (e != hipSuccess) return e;
+  return launch_rec(h, k_metrics_final, k_metrics_final_b, 1, 256, 0, a);
 }
 
 template <typename T>

@@ -50,10 +50,10 @@ __device__ __forceinline__ int block_sum_256(int v, int* tmp) {
   return t;
 }
 
-__global__ __launch_bounds__(256) void k_scan_count(RepackArgs a) {
+__device__ __forceinline__ void k_scan_count_body(const RepackArgs& a, int blk, int nblk) {
   __shared__ int tmp[8];
   if (*a.status != 0) return;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kScanRows + threadIdx.x * kRowsPerThread;
+  const int64_t r0 = static_cast<int64_t>(blk) * kScanRows + threadIdx.x * kRowsPerThread;
   int cnt = 0, ne = 0;
 #pragma unroll
   for (int i = 0; i < kRowsPerThread; ++i) {
@@ -67,13 +67,20 @@ __global__ __launch_bounds__(256) void k_scan_count(RepackArgs a) {
   const int tc = block_sum_256(cnt, tmp);
   const int tn = block_sum_256(ne, tmp);
   if (threadIdx.x == 0) {
-    a.part_cnt[blockIdx.x] = tc;
-    a.part_ne[blockIdx.x] = tn;
+    a.part_cnt[blk] = tc;
+    a.part_ne[blk] = tn;
   }
 }
+__global__ __launch_bounds__(256) void k_scan_count(RepackArgs a) { k_scan_count_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void k_scan_count_b(const RepackArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const RepackArgs a = as[m.prob];
+  k_scan_count_body(a, m.blk, m.nblk);
+}
+
 
 template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_build(RepackArgs a) {
+__device__ __forceinline__ void k_build_body(const RepackArgs& a, int blk, int nblk) {
   __shared__ int tmp[8];
   __shared__ uint32_t smask[kScanRows * 4];
   __shared__ int s_rp[kScanRows];
@@ -84,13 +91,13 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
   const int tid = threadIdx.x;
   // offsets of this block: the totals of all earlier blocks
   int oc = 0, on = 0;
-  for (int b = tid; b < static_cast<int>(blockIdx.x); b += 256) {
+  for (int b = tid; b < static_cast<int>(blk); b += 256) {
     oc += a.part_cnt[b];
     on += a.part_ne[b];
   }
   const int off_c = block_sum_256(oc, tmp);
   const int off_n = block_sum_256(on, tmp);
-  const int64_t rb0 = static_cast<int64_t>(blockIdx.x) * kScanRows;
+  const int64_t rb0 = static_cast<int64_t>(blk) * kScanRows;
   const int64_t r0 = rb0 + tid * kRowsPerThread;
   int cnt[kRowsPerThread];
   int tc = 0, tn = 0;
@@ -133,7 +140,7 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
     lc += cnt[i];
     ln += ne ? 1 : 0;
   }
-  if (blockIdx.x == gridDim.x - 1 && tid == 255) {
+  if (blk == nblk - 1 && tid == 255) {
     // lc / ln now hold the totals over every block
     a.F.counts[0] = lc;
     a.F.counts[1] = ln;
@@ -213,6 +220,15 @@ __global__ __launch_bounds__(256) void k_build(RepackArgs a) {
     }
   }
 }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_build(RepackArgs a) { k_build_body<T, KPL>(a, blockIdx.x, gridDim.x); }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_build_b(const RepackArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const RepackArgs a = as[m.prob];
+  k_build_body<T, KPL>(a, m.blk, m.nblk);
+}
+
 
 }  // namespace
 
@@ -230,13 +246,10 @@ hipError_t repack(nmf_handle* h, const T* X, int64_t rows, const Factor& out_f, 
   a.part_ne = h->sel.scan_part + blocks + 1;
   a.F = out_f;
   a.status = h->status;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_count, dim3(blocks), dim3(256), 0, h->stream, a);
-  if (h->k > 64)
-    hipLaunchKernelGGL((k_build<T, 2>), dim3(blocks), dim3(256), 0, h->stream, a);
-  else
-    hipLaunchKernelGGL((k_build<T, 1>), dim3(blocks), dim3(256), 0, h->stream, a);
-  return hipGetLastError();
+  hipError_t e = launch_rec(h, k_scan_count, k_scan_count_b, blocks, 256, 0, a);
+  if (e != hipSuccess) return e;
+  if (h->k > 64) return launch_rec(h, k_build<T, 2>, k_build_b<T, 2>, blocks, 256, 0, a);
+  return launch_rec(h, k_build<T, 1>, k_build_b<T, 1>, blocks, 256, 0, a);
 }
 
 template hipError_t repack<float>(nmf_handle*, const float*, int64_t, const Factor&, int);

@@ -54,7 +54,7 @@ struct SelArgs {
 };
 
 template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_hist(SelArgs a) {
+__device__ __forceinline__ void k_hist_body(const SelArgs& a, int blk, int nblk) {
   using KO = KeyOf<T>;
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins]
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   const T* __restrict__ X = static_cast<const T*>(a.X);
-  const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * a.hist_rows;
+  const int64_t r_begin = static_cast<int64_t>(blk) * a.hist_rows;
   int64_t r_end = r_begin + a.hist_rows;
   if (r_end > a.rows) r_end = a.rows;
   // four rows per wave per step keep four loads in flight
@@ -90,15 +90,24 @@ __global__ __launch_bounds__(256) void k_hist(SelArgs a) {
     if (v) atomicAdd(&a.hist[i], v);
   }
 }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_hist(SelArgs a) { k_hist_body<T, KPL>(a, blockIdx.x, gridDim.x); }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_hist_b(const SelArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const SelArgs a = as[m.prob];
+  k_hist_body<T, KPL>(a, m.blk, m.nblk);
+}
+
 
 // The threshold digit of every column from the full histogram, one wave per
 // column; the histogram is cleared for the next use.
-__global__ __launch_bounds__(256) void k_pick(SelArgs a) {
+__device__ __forceinline__ void k_pick_body(const SelArgs& a, int blk, int nblk) {
   if (*a.status != 0) return;
   const int k = a.k;
   const int lane = lane_id();
-  const int nw = gridDim.x * (blockDim.x >> 6);
-  for (int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < k; c += nw) {
+  const int nw = nblk * (blockDim.x >> 6);
+  for (int c = blk * (blockDim.x >> 6) + (threadIdx.x >> 6); c < k; c += nw) {
     uint4* hc = reinterpret_cast<uint4*>(a.hist + static_cast<size_t>(c) * kBins);
     const uint4 q = hc[lane];
     hc[lane] = make_uint4(0u, 0u, 0u, 0u);
@@ -119,9 +128,16 @@ __global__ __launch_bounds__(256) void k_pick(SelArgs a) {
     if (lane == 0) a.sel[c] = s;
   }
 }
+__global__ __launch_bounds__(256) void k_pick(SelArgs a) { k_pick_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void k_pick_b(const SelArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const SelArgs a = as[m.prob];
+  k_pick_body(a, m.blk, m.nblk);
+}
+
 
 template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_collect(SelArgs a) {
+__device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nblk) {
   using KO = KeyOf<T>;
   using C = Cand<T>;
   __shared__ int32_t lcnt[kMaxK];
@@ -141,7 +157,7 @@ __global__ __launch_bounds__(256) void k_collect(SelArgs a) {
   }
   __syncthreads();
   const T* __restrict__ X = static_cast<const T*>(a.X);
-  const int64_t r_begin = static_cast<int64_t>(blockIdx.x) * kRowsPerBlock;
+  const int64_t r_begin = static_cast<int64_t>(blk) * kRowsPerBlock;
   int64_t r_end = r_begin + kRowsPerBlock;
   if (r_end > a.rows) r_end = a.rows;
   for (int64_t r4 = r_begin + wv; r4 < r_end; r4 += 16) {
@@ -200,6 +216,15 @@ __global__ __launch_bounds__(256) void k_collect(SelArgs a) {
       out[static_cast<int64_t>(c) * a.stride + lbase[c] + i] = stage[c * kRowsPerBlock + i];
   }
 }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_collect(SelArgs a) { k_collect_body<T, KPL>(a, blockIdx.x, gridDim.x); }
+template <typename T, int KPL>
+__global__ __launch_bounds__(256) void k_collect_b(const SelArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const SelArgs a = as[m.prob];
+  k_collect_body<T, KPL>(a, m.blk, m.nblk);
+}
+
 
 // digit of a candidate under the compound order; `kb` value bits and `rb`
 // row bits remain below the digits already fixed
@@ -221,12 +246,12 @@ __device__ __forceinline__ void mark(uint32_t* mask, int mw, uint32_t row, int c
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
+__device__ __forceinline__ void k_refine_body(const SelArgs& a, int blk, int nblk) {
   using C = Cand<T>;
   __shared__ uint32_t h[kBins];
   __shared__ int s_bin, s_need, s_n, s_cnt;
   if (*a.status != 0) return;
-  const int c = blockIdx.x;
+  const int c = blk;
   const int tid = threadIdx.x;
   const ColSel s = a.sel[c];
   int* cnt_ptr = &a.cand_cnt[c * kCntStride];
@@ -329,23 +354,31 @@ __global__ __launch_bounds__(1024) void k_refine(SelArgs a) {
     if (tid == 0) *cnt_ptr = 0;
   }
 }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_refine(SelArgs a) { k_refine_body<T>(a, blockIdx.x, gridDim.x); }
+template <typename T>
+__global__ __launch_bounds__(1024) void k_refine_b(const SelArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const SelArgs a = as[m.prob];
+  k_refine_body<T>(a, m.blk, m.nblk);
+}
+
 
 template <typename T, int KPL>
 hipError_t run(nmf_handle* h, SelArgs& a) {
-  const int blocks = static_cast<int>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
-  if (blocks == 0) return hipSuccess;
+  const unsigned blocks = static_cast<unsigned>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
   // a few hundred histogram blocks: enough rows each that the flush of the
   // block histograms stays small
   const int64_t want = 2 * static_cast<int64_t>(h->num_cus);
   a.hist_rows = static_cast<int32_t>(std::max<int64_t>(kRowsPerBlock, (a.rows + want - 1) / want));
-  const int hblocks = static_cast<int>((a.rows + a.hist_rows - 1) / a.hist_rows);
+  const unsigned hblocks = static_cast<unsigned>((a.rows + a.hist_rows - 1) / a.hist_rows);
   const size_t hbytes = static_cast<size_t>(a.k) * kPadBins * sizeof(uint32_t);
   const size_t stage = static_cast<size_t>(a.k) * kRowsPerBlock * sizeof(Cand<T>);
-  hipLaunchKernelGGL((k_hist<T, KPL>), dim3(hblocks), dim3(256), hbytes, h->stream, a);
-  hipLaunchKernelGGL(k_pick, dim3((a.k + 3) / 4), dim3(256), 0, h->stream, a);
-  hipLaunchKernelGGL((k_collect<T, KPL>), dim3(blocks), dim3(256), stage, h->stream, a);
-  hipLaunchKernelGGL((k_refine<T>), dim3(a.k), dim3(1024), 0, h->stream, a);
-  return hipGetLastError();
+  hipError_t e;
+  if ((e = launch_rec(h, k_hist<T, KPL>, k_hist_b<T, KPL>, hblocks, 256, hbytes, a)) != hipSuccess) return e;
+  if ((e = launch_rec(h, k_pick, k_pick_b, (a.k + 3) / 4, 256, 0, a)) != hipSuccess) return e;
+  if ((e = launch_rec(h, k_collect<T, KPL>, k_collect_b<T, KPL>, blocks, 256, stage, a)) != hipSuccess) return e;
+  return launch_rec(h, k_refine<T>, k_refine_b<T>, a.k, 1024, 0, a);
 }
 
 }  // namespace

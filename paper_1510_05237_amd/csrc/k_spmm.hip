@@ -27,6 +27,8 @@
 // Pieces of long rows store their raw sums; k_spmm_heavy adds them in piece
 // order and runs the same epilogue.  One wave owns each accumulator and LDS
 // executes a wave's instructions in order, so the sums are reproducible.
+#include <algorithm>
+
 #include "nmf_device.h"
 
 namespace nmfk {
@@ -405,8 +407,9 @@ __device__ __forceinline__ void clear_tile(T* tile, int) {
   for (int i = 0; i < kTileEntries / 64; ++i) tile[lane + 64 * i] = T(0);
 }
 
+// Block `blk` of a grid of `nblk` blocks over the items of one problem.
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
-__global__ __launch_bounds__(64 * kWaves) void k_spmm(SpmmArgs a) {
+__device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) {
   static_assert(RG * 64 * KPL <= kTileEntries, "accumulator too small for the row group");
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
@@ -419,8 +422,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_spmm(SpmmArgs a) {
   T* tile = static_cast<T*>(w.tile);
 
   const int bw = blockDim.x >> 6;
-  const int nw = gridDim.x * bw;
-  for (int it = blockIdx.x * bw + wv; it < a.n_items; it += nw) {
+  const int nw = nblk * bw;
+  for (int it = blk * bw + wv; it < a.n_items; it += nw) {
     const WorkItem wi = a.items[it];
     clear_tile<T, KPL, RG>(tile, k);
     if (wi.heavy < 0) {
@@ -449,9 +452,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_spmm(SpmmArgs a) {
   }
 }
 
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
+__global__ __launch_bounds__(64 * kWaves) void k_spmm(SpmmArgs a) {
+  spmm_body<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>(a, blockIdx.x, gridDim.x);
+}
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
+__global__ __launch_bounds__(64 * kWaves) void k_spmm_b(const SpmmArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const SpmmArgs a = as[m.prob];
+  spmm_body<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>(a, m.blk, m.nblk);
+}
+
 // Long rows: add the pieces' raw sums in piece order, then the epilogue.
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C>
-__global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy(SpmmArgs a) {
+__device__ __forceinline__ void spmm_heavy_body(const SpmmArgs& a, int blk, int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
   const int k = a.k;
@@ -466,8 +480,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy(SpmmArgs a) {
   T* tile = reinterpret_cast<T*>(smem + wave0) + static_cast<size_t>(wv) * kTileEntries;
   const T* part = static_cast<const T*>(a.partials);
   const int bw = blockDim.x >> 6;
-  const int nw = gridDim.x * bw;
-  for (int hh = blockIdx.x * bw + wv; hh < a.n_heavy; hh += nw) {
+  const int nw = nblk * bw;
+  for (int hh = blk * bw + wv; hh < a.n_heavy; hh += nw) {
     const int nch = a.heavy_nchunks[hh];
     const int p0 = a.heavy_part0[hh];
 #pragma unroll
@@ -491,6 +505,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy(SpmmArgs a) {
   }
 }
 
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C>
+__global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy(SpmmArgs a) {
+  spmm_heavy_body<T, KPL, RG, RAW, STORE_C>(a, blockIdx.x, gridDim.x);
+}
+template <typename T, int KPL, int RG, bool RAW, bool STORE_C>
+__global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy_b(const SpmmArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const SpmmArgs a = as[m.prob];
+  spmm_heavy_body<T, KPL, RG, RAW, STORE_C>(a, m.blk, m.nblk);
+}
+
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
 hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
   // W (float64, k x k) is shared by the block; with large k fewer waves fit
@@ -505,21 +530,15 @@ hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
                                                    64 * waves, lds) != hipSuccess)
     return hipErrorInvalidValue;
   if (per_cu < 1) per_cu = 1;
-  if (a.n_items > 0) {
-    int blocks = (a.n_items + waves - 1) / waves;
-    const int cap = h->num_cus * per_cu;
-    if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>), dim3(blocks), dim3(64 * waves), lds,
-                       h->stream, a);
-  }
-  if (a.n_heavy > 0) {
-    int blocks = (a.n_heavy + waves - 1) / waves;
-    const int cap = h->num_cus * per_cu;
-    if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL((k_spmm_heavy<T, KPL, RG, RAW, STORE_C>), dim3(blocks), dim3(64 * waves), lds,
-                       h->stream, a);
-  }
-  return hipGetLastError();
+  const int cap = h->num_cus * per_cu;
+  const int items = std::min((a.n_items + waves - 1) / waves, cap);
+  hipError_t e = launch_rec(h, k_spmm<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>,
+                            k_spmm_b<T, KPL, RG, RAW, STORE_C, DENSE_IN, WIDE>, static_cast<unsigned>(items),
+                            64u * waves, lds, a);
+  if (e != hipSuccess) return e;
+  const int heavy = std::min((a.n_heavy + waves - 1) / waves, cap);
+  return launch_rec(h, k_spmm_heavy<T, KPL, RG, RAW, STORE_C>, k_spmm_heavy_b<T, KPL, RG, RAW, STORE_C>,
+                    static_cast<unsigned>(heavy), 64u * waves, lds, a);
 }
 
 }  // namespace

@@ -879,3 +879,366 @@ void nmf_destroy(nmf_handle* h) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+//
+// A batch is one handle per problem, all on one stream, plus the fused
+// launch plans: every problem's launches of one iteration are recorded (for
+// each parity of the current-U slot), and launch j of every problem becomes
+// one launch of the kernel's batched form whose blocks are mapped to
+// (problem, block of that problem's own grid).  Problems whose launch j is a
+// different kernel (another template instance) get a launch of their own at
+// the same position.
+
+struct nmf_batch {
+  struct Launch {
+    const void* fn;
+    unsigned blocks;
+    unsigned block;
+    size_t lds;
+    const void* args;  // device: the members' argument structs
+    const void* map;   // device: BlockMap per block
+  };
+  std::vector<nmf_handle*> h;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<Launch> plan[2];  // one iteration starting at current-U slot 0 / 1
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [loop, fused][start slot]
+  std::string last_error;
+};
+
+namespace {
+
+thread_local std::string g_batch_error = "no error";
+
+nmf_status batch_fail(nmf_batch* b, nmf_status s, const std::string& msg) {
+  if (b)
+    b->last_error = msg;
+  else
+    g_batch_error = msg;
+  return s;
+}
+
+#define BCHK(b, expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return batch_fail((b), NMF_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Upper bound of the fused-table bytes one problem adds (both slots): its
+// argument structs and one BlockMap per block of every launch of an
+// iteration (grid bounds as in the launchers).
+size_t batch_table_bound(const nmf_config& c, int64_t nnz) {
+  const int64_t ch = nnz / kChunk + 2;
+  auto sel = [&](int64_t r) { return 2 * ((r + 63) / 64 + 1) + (c.k + 3) / 4 + c.k; };
+  auto rep = [&](int64_t r) { return 2 * ((r + 511) / 512 + 1); };
+  const int64_t gram = kGramBlocks + 130 + 1;
+  const int64_t blocks = (c.m + 2 * ch + 1) + ch + (c.n + 2 * ch + 1) + ch + sel(c.m) + sel(c.n) + rep(c.m) +
+                         rep(c.n) + 2 * gram + kMetricBlocks + 1;
+  const int64_t launches = 40;
+  return 2 * (static_cast<size_t>(blocks) * sizeof(BlockMap) + launches * (512 + 512));
+}
+
+// The host-side state one iteration changes, to undo a recorded or captured
+// iteration and to apply replayed ones.
+struct HostState {
+  int cur_u;
+  int64_t iters_done;
+  bool have_v, have_pre_v, have_pre_u, metrics_valid, prof_on;
+};
+HostState save_state(const nmf_handle* h) {
+  return HostState{h->cur_u, h->iters_done, h->have_v, h->have_pre_v, h->have_pre_u, h->metrics_valid, h->prof_on};
+}
+void restore_state(nmf_handle* h, const HostState& s) {
+  h->cur_u = s.cur_u;
+  h->iters_done = s.iters_done;
+  h->have_v = s.have_v;
+  h->have_pre_v = s.have_pre_v;
+  h->have_pre_u = s.have_pre_u;
+  h->metrics_valid = s.metrics_valid;
+  h->prof_on = s.prof_on;
+}
+void advance_state(nmf_handle* h, int32_t iters) {
+  if (iters <= 0) return;
+  if (iters & 1) h->cur_u = 1 - h->cur_u;
+  h->iters_done += iters;
+  h->have_v = h->have_pre_v = h->have_pre_u = true;
+  h->metrics_valid = !(h->cfg.flags & NMF_FLAG_NO_METRICS);
+}
+
+nmf_status steps_of(nmf_handle* h, int32_t iters) {
+  return h->elt == 8 ? do_steps<double>(h, iters) : do_steps<float>(h, iters);
+}
+
+nmf_status build_plans(nmf_batch* b, char* tables, size_t table_bytes) {
+  std::vector<char> stage;
+  size_t used = 0;
+  auto put = [&](const void* src, size_t bytes) {
+    used = align_up(used, 256);
+    const size_t at = used;
+    if (stage.size() < used + bytes) stage.resize(used + bytes);
+    std::memcpy(stage.data() + at, src, bytes);
+    used += bytes;
+    return at;
+  };
+  struct Pending {
+    int slot;
+    const void* fn;
+    unsigned blocks, block;
+    size_t lds, args_at, map_at;
+  };
+  std::vector<Pending> pend;
+  const size_t np = b->h.size();
+  for (int slot = 0; slot < 2; ++slot) {
+    std::vector<std::vector<LaunchRecord>> recs(np);
+    for (size_t i = 0; i < np; ++i) {
+      nmf_handle* h = b->h[i];
+      const HostState st = save_state(h);
+      h->prof_on = false;
+      h->cur_u = slot;
+      h->rec = &recs[i];
+      nmf_status s = steps_of(h, 1);
+      h->rec = nullptr;
+      restore_state(h, st);
+      if (s != NMF_OK) return batch_fail(b, s, "recording problem " + std::to_string(i) + ": " + h->last_error);
+    }
+    const size_t L = recs[0].size();
+    for (size_t i = 1; i < np; ++i)
+      if (recs[i].size() != L) return batch_fail(b, NMF_ERR_DEVICE, "internal: launch sequences differ");
+    for (size_t j = 0; j < L; ++j) {
+      std::vector<std::pair<const void*, unsigned>> keys;
+      std::vector<std::vector<size_t>> members;
+      for (size_t i = 0; i < np; ++i) {
+        const LaunchRecord& r = recs[i][j];
+        if (r.grid == 0) continue;
+        size_t g = 0;
+        while (g < keys.size() && (keys[g].first != r.batched || keys[g].second != r.block)) ++g;
+        if (g == keys.size()) {
+          keys.emplace_back(r.batched, r.block);
+          members.emplace_back();
+        }
+        members[g].push_back(i);
+      }
+      for (size_t g = 0; g < keys.size(); ++g) {
+        std::vector<unsigned char> args;
+        std::vector<BlockMap> map;
+        size_t lds = 0;
+        for (size_t mi = 0; mi < members[g].size(); ++mi) {
+          const LaunchRecord& r = recs[members[g][mi]][j];
+          args.insert(args.end(), r.args.begin(), r.args.end());
+          for (unsigned blk = 0; blk < r.grid; ++blk)
+            map.push_back(BlockMap{static_cast<int32_t>(mi), static_cast<int32_t>(blk),
+                                   static_cast<int32_t>(r.grid), 0});
+          lds = std::max(lds, r.lds);
+        }
+        Pending p;
+        p.slot = slot;
+        p.fn = keys[g].first;
+        p.blocks = static_cast<unsigned>(map.size());
+        p.block = keys[g].second;
+        p.lds = lds;
+        p.args_at = put(args.data(), args.size());
+        p.map_at = put(map.data(), map.size() * sizeof(BlockMap));
+        pend.push_back(p);
+      }
+    }
+  }
+  if (used > table_bytes) return batch_fail(b, NMF_ERR_WORKSPACE, "internal: fused tables exceed their bound");
+  BCHK(b, hipMemcpy(tables, stage.data(), used, hipMemcpyHostToDevice));
+  for (const Pending& p : pend)
+    b->plan[p.slot].push_back(nmf_batch::Launch{p.fn, p.blocks, p.block, p.lds, tables + p.args_at, tables + p.map_at});
+  return NMF_OK;
+}
+
+nmf_status launch_plan(nmf_batch* b, int slot) {
+  for (const nmf_batch::Launch& L : b->plan[slot]) {
+    void* kargs[2] = {const_cast<void**>(&L.args), const_cast<void**>(&L.map)};
+    BCHK(b, hipLaunchKernel(L.fn, dim3(L.blocks), dim3(L.block), kargs, L.lds, b->stream));
+  }
+  return NMF_OK;
+}
+
+// Every problem must sit at the same current-U slot for the fused plans.
+nmf_status common_slot(nmf_batch* b, int* slot) {
+  *slot = b->h[0]->cur_u;
+  for (nmf_handle* h : b->h)
+    if (h->cur_u != *slot)
+      return batch_fail(b, NMF_ERR_STATE, "problems were stepped separately: their iterates are out of step");
+  return NMF_OK;
+}
+
+// One iteration of the batch without graphs (fused or loop); the host state
+// is advanced.
+nmf_status batch_iteration(nmf_batch* b, bool fused) {
+  if (fused) {
+    int slot;
+    nmf_status s = common_slot(b, &slot);
+    if (s != NMF_OK) return s;
+    if ((s = launch_plan(b, slot)) != NMF_OK) return s;
+    for (nmf_handle* h : b->h) advance_state(h, 1);
+    return NMF_OK;
+  }
+  for (size_t i = 0; i < b->h.size(); ++i) {
+    nmf_status s = steps_of(b->h[i], 1);
+    if (s != NMF_OK) return batch_fail(b, s, "problem " + std::to_string(i) + ": " + b->h[i]->last_error);
+  }
+  return NMF_OK;
+}
+
+// Capture two iterations starting at the current slot as a graph; the host
+// state is left as it was.
+nmf_status capture_pair(nmf_batch* b, bool fused, int slot, hipGraphExec_t* exec) {
+  std::vector<HostState> st;
+  for (nmf_handle* h : b->h) st.push_back(save_state(h));
+  BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  nmf_status s = NMF_OK;
+  for (int it = 0; it < 2 && s == NMF_OK; ++it) s = batch_iteration(b, fused);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+  for (size_t i = 0; i < b->h.size(); ++i) restore_state(b->h[i], st[i]);
+  if (s != NMF_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (ec != hipSuccess) return batch_fail(b, NMF_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+  const hipError_t ei = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return batch_fail(b, NMF_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+  (void)slot;
+  return NMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_batch_workspace_size(int32_t count, const nmf_config* cfgs, const int64_t* nnz, size_t* bytes) {
+  if (count < 1 || cfgs == nullptr || nnz == nullptr || bytes == nullptr)
+    return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "count < 1 or a NULL argument");
+  size_t total = 0, tables = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    size_t w = 0;
+    nmf_status s = nmf_workspace_size(&cfgs[i], nnz[i], &w);
+    if (s != NMF_OK) return batch_fail(nullptr, s, "problem " + std::to_string(i) + ": " + nmf_last_error(nullptr));
+    total += align_up(w, 256);
+    tables += batch_table_bound(cfgs[i], nnz[i]);
+  }
+  *bytes = total + align_up(tables, 256);
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t* const* a_rowptr,
+                            const int32_t* const* a_col, const void* const* a_val, const int64_t* nnz,
+                            const void* const* u0, void* workspace, size_t ws_bytes, void* hip_stream,
+                            nmf_batch** out) {
+  if (out == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || cfgs == nullptr || a_rowptr == nullptr || a_col == nullptr || a_val == nullptr ||
+      nnz == nullptr || u0 == nullptr)
+    return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "count < 1 or a NULL array");
+  size_t need = 0;
+  nmf_status s = nmf_batch_workspace_size(count, cfgs, nnz, &need);
+  if (s != NMF_OK) return s;
+  if (workspace == nullptr || ws_bytes < need)
+    return batch_fail(nullptr, NMF_ERR_WORKSPACE, "workspace smaller than nmf_batch_workspace_size()");
+  nmf_batch* b = new (std::nothrow) nmf_batch();
+  if (b == nullptr) return batch_fail(nullptr, NMF_ERR_DEVICE, "out of host memory");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  if (b->stream == nullptr) {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return batch_fail(nullptr, NMF_ERR_DEVICE, "cannot create a stream");
+    }
+    b->own_stream = true;
+  }
+  char* base = static_cast<char*>(workspace);
+  size_t off = 0;
+  for (int32_t i = 0; i < count && s == NMF_OK; ++i) {
+    size_t w = 0;
+    nmf_workspace_size(&cfgs[i], nnz[i], &w);
+    nmf_handle* h = nullptr;
+    s = nmf_create(&cfgs[i], a_rowptr[i], a_col[i], a_val[i], nnz[i], u0[i], nullptr, base + off, w, b->stream, &h);
+    if (s != NMF_OK) {
+      batch_fail(nullptr, s, "problem " + std::to_string(i) + ": " + nmf_last_error(nullptr));
+      break;
+    }
+    b->h.push_back(h);
+    off += align_up(w, 256);
+  }
+  if (s == NMF_OK) {
+    s = build_plans(b, base + off, ws_bytes - off);
+    if (s != NMF_OK) g_batch_error = b->last_error;
+  }
+  if (s != NMF_OK) {
+    const std::string msg = g_batch_error;
+    nmf_batch_destroy(b);
+    g_batch_error = msg;
+    return s;
+  }
+  *out = b;
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_step(nmf_batch* b, int32_t iters, int32_t how) {
+  if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
+  if (iters < 0) return batch_fail(b, NMF_ERR_INVALID_ARG, "iters < 0");
+  if (how < NMF_BATCH_LOOP || how > NMF_BATCH_FUSED_GRAPH) return batch_fail(b, NMF_ERR_INVALID_ARG, "unknown mode");
+  const bool fused = how == NMF_BATCH_FUSED || how == NMF_BATCH_FUSED_GRAPH;
+  const bool graph = how == NMF_BATCH_LOOP_GRAPH || how == NMF_BATCH_FUSED_GRAPH;
+  nmf_status s;
+  if (!graph) {
+    for (int32_t it = 0; it < iters; ++it)
+      if ((s = batch_iteration(b, fused)) != NMF_OK) return s;
+    return NMF_OK;
+  }
+  int slot;
+  if ((s = common_slot(b, &slot)) != NMF_OK) return s;
+  hipGraphExec_t& ex = b->exec[fused ? 1 : 0][slot];
+  if (iters >= 2 && ex == nullptr && (s = capture_pair(b, fused, slot, &ex)) != NMF_OK) return s;
+  for (int32_t it = 0; it + 1 < iters; it += 2) {
+    BCHK(b, hipGraphLaunch(ex, b->stream));
+    for (nmf_handle* h : b->h) advance_state(h, 2);
+  }
+  if (iters & 1) return batch_iteration(b, fused);
+  return NMF_OK;
+}
+
+nmf_status nmf_batch_errors(nmf_batch* b, double* E, int32_t* status) {
+  if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
+  BCHK(b, hipStreamSynchronize(b->stream));
+  nmf_status first = NMF_OK;
+  for (size_t i = 0; i < b->h.size(); ++i) {
+    double e = __builtin_nan("");
+    nmf_status s = nmf_error(b->h[i], &e);
+    if (E) E[i] = e;
+    if (status) status[i] = s;
+    if (s != NMF_OK && first == NMF_OK) {
+      first = s;
+      b->last_error = "problem " + std::to_string(i) + ": " + b->h[i]->last_error;
+    }
+  }
+  return first;
+}
+
+nmf_handle* nmf_batch_problem(nmf_batch* b, int32_t i) {
+  if (b == nullptr || i < 0 || static_cast<size_t>(i) >= b->h.size()) return nullptr;
+  return b->h[i];
+}
+
+const char* nmf_batch_last_error(const nmf_batch* b) {
+  return b ? b->last_error.c_str() : g_batch_error.c_str();
+}
+
+void nmf_batch_destroy(nmf_batch* b) {
+  if (b == nullptr) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto& row : b->exec)
+    for (auto& e : row)
+      if (e) (void)hipGraphExecDestroy(e);
+  for (nmf_handle* h : b->h) nmf_destroy(h);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+}  // extern "C"

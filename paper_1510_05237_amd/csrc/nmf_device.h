@@ -117,6 +117,29 @@ __device__ __forceinline__ int wave_pick_bin(const uint32_t* v, int64_t need, in
   return __shfl(bin, src, 64);
 }
 
+// Issues a kernel on the handle's stream, or, while the handle records,
+// appends the launch (with the kernel's batched form) to the record.  A grid
+// of zero blocks is recorded too, so that every problem of a batch records
+// the same sequence of launches.
+template <typename Args>
+hipError_t launch_rec(nmf_handle* h, void (*single)(Args), void (*batched)(const Args*, const BlockMap*),
+                      unsigned grid, unsigned block, size_t lds, const Args& a) {
+  if (h->rec) {
+    LaunchRecord r;
+    r.batched = reinterpret_cast<const void*>(batched);
+    r.args.resize(sizeof(Args));
+    __builtin_memcpy(r.args.data(), &a, sizeof(Args));
+    r.grid = grid;
+    r.block = block;
+    r.lds = lds;
+    h->rec->push_back(std::move(r));
+    return hipSuccess;
+  }
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(single, dim3(grid), dim3(block), lds, h->stream, a);
+  return hipGetLastError();
+}
+
 // Release/acquire fences at device (agent) scope around inter-block tickets.
 __device__ __forceinline__ void fence_release() { __threadfence(); }
 __device__ __forceinline__ void fence_acquire() { __threadfence(); }

@@ -134,6 +134,30 @@ struct Metrics {
 
 }  // namespace nmfk
 
+namespace nmfk {
+
+// One block of a batched launch: the problem it serves and the block of that
+// problem's own grid it plays (blk of nblk).
+struct BlockMap {
+  int32_t prob;
+  int32_t blk;
+  int32_t nblk;
+  int32_t pad;
+};
+
+// Launches recorded instead of issued (to build a batched replay): the
+// batched form of the kernel, its argument struct, the problem's own grid,
+// the block size and the dynamic LDS bytes.
+struct LaunchRecord {
+  const void* batched = nullptr;
+  std::vector<unsigned char> args;
+  unsigned grid = 0;
+  unsigned block = 0;
+  size_t lds = 0;
+};
+
+}  // namespace nmfk
+
 struct nmf_handle {
   nmf_config cfg{};
   int64_t n = 0, m = 0, nnz = 0;
@@ -180,6 +204,8 @@ struct nmf_handle {
   double prof_ms[NMF_NUM_STAGES] = {0};
   int64_t prof_cnt[NMF_NUM_STAGES] = {0};
   std::string last_error;
+  // when set, kernel launches are appended here instead of being issued
+  std::vector<nmfk::LaunchRecord>* rec = nullptr;
 };
 
 namespace nmfk {

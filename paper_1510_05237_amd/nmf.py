@@ -94,6 +94,14 @@ SIGNATURES = {
     "nmf_profile_read": (_I32, [_P, _P, _P, _I32]),
     "nmf_last_error": (ctypes.c_char_p, [_P]),
     "nmf_destroy": (None, [_P]),
+    "nmf_batch_workspace_size": (_I32, [_I32, ctypes.POINTER(nmf_config), _PI64, ctypes.POINTER(ctypes.c_size_t)]),
+    "nmf_batch_create": (_I32, [_I32, ctypes.POINTER(nmf_config), _P, _P, _P, _PI64, _P, _P, ctypes.c_size_t, _P,
+                                ctypes.POINTER(_P)]),
+    "nmf_batch_step": (_I32, [_P, _I32, _I32]),
+    "nmf_batch_errors": (_I32, [_P, _P, _P]),
+    "nmf_batch_problem": (_P, [_P, _I32]),
+    "nmf_batch_last_error": (ctypes.c_char_p, [_P]),
+    "nmf_batch_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -261,6 +269,51 @@ def nmf_destroy(h: int):
     load_library().nmf_destroy(h)
 
 
+NMF_BATCH_LOOP = 0
+NMF_BATCH_LOOP_GRAPH = 1
+NMF_BATCH_FUSED = 2
+NMF_BATCH_FUSED_GRAPH = 3
+BATCH_MODES = {"loop": NMF_BATCH_LOOP, "loop_graph": NMF_BATCH_LOOP_GRAPH, "fused": NMF_BATCH_FUSED,
+               "fused_graph": NMF_BATCH_FUSED_GRAPH}
+
+
+def _bcheck(st: int, b=None):
+    if st != NMF_OK:
+        msg = load_library().nmf_batch_last_error(b)
+        raise NMFError(st, msg.decode() if msg else "")
+
+
+def nmf_batch_workspace_size(cfgs, nnz) -> int:
+    n = len(cfgs)
+    arr = (nmf_config * n)(*cfgs)
+    nz = np.ascontiguousarray(nnz, np.int64)
+    out = ctypes.c_size_t()
+    _bcheck(load_library().nmf_batch_workspace_size(n, arr, nz.ctypes.data_as(_PI64), ctypes.byref(out)))
+    return out.value
+
+
+def nmf_batch_create(cfgs, rowptrs, cols, vals, nnz, u0s, workspace, ws_bytes, stream) -> int:
+    n = len(cfgs)
+    arr = (nmf_config * n)(*cfgs)
+    ptrs = [(_P * n)(*[_ptr(x) for x in xs]) for xs in (rowptrs, cols, vals, u0s)]
+    nz = np.ascontiguousarray(nnz, np.int64)
+    b = _P()
+    _bcheck(load_library().nmf_batch_create(n, arr, ptrs[0], ptrs[1], ptrs[2], nz.ctypes.data_as(_PI64), ptrs[3],
+                                            _ptr(workspace), ws_bytes, stream, ctypes.byref(b)))
+    return b.value
+
+
+def nmf_batch_step(b: int, iters: int, how: int):
+    _bcheck(load_library().nmf_batch_step(b, iters, how), b)
+
+
+def nmf_batch_errors(b: int, count: int):
+    E = np.zeros(count, np.float64)
+    st = np.zeros(count, np.int32)
+    load_library().nmf_batch_errors(b, _ptr(E), _ptr(st))
+    return E, st
+
+
 # ---------------------------------------------------------------- handle object
 
 _MODES = {"column": NMF_MODE_COLUMN, "none": NMF_MODE_NONE, "whole": NMF_MODE_WHOLE}
@@ -411,3 +464,81 @@ class NMFLoss:
     @classmethod
     def apply(cls, problem, U, V):
         return cls._function().apply(problem, U, V)
+
+
+class _BatchMember(NMF):
+    """View of one problem of an ``NMFBatch`` (its handle belongs to the batch)."""
+
+    def __init__(self, h, n, m, k, dtype, device):
+        import torch
+
+        self.h = h
+        self.n, self.m, self.k = n, m, k
+        self.dtype = dtype
+        self.np_dtype = np.float32 if dtype == "f32" else np.float64
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.device = device
+
+    def close(self):
+        self.h = None
+
+
+class NMFBatch:
+    """Independent problems advanced together on one GPU.
+
+    ``problems``: sequence of dicts with ``n, m, indptr, indices, data, u0,
+    t_u, t_v`` (A in CSR over term rows; host or device arrays of ``dtype``).
+    ``step(iters, how)`` runs ``iters`` iterations of every problem as
+    ``how``: "loop" (each problem's own launches), "loop_graph" (that loop
+    captured as a HIP graph), "fused" (one launch per stage for all problems)
+    or "fused_graph" (the fused launches captured as a graph).
+    """
+
+    def __init__(self, problems, *, dtype="f32", mode="column", flags=0, device="cuda:0", stream=None):
+        import torch
+
+        load_library()
+        self.device = torch.device(device)
+        self.dtype = dtype
+        cfgs, nnz = [], []
+        for p in problems:
+            k = int(p["u0"].shape[1])
+            cfgs.append(nmf_config(n=int(p["n"]), m=int(p["m"]), k=k, mode=_MODES[mode], t_u=int(p["t_u"]),
+                                   t_v=int(p["t_v"]), dtype=NMF_F32 if dtype == "f32" else NMF_F64,
+                                   flags=int(flags)))
+            nnz.append(int(p["indptr"][-1]))
+        self.count = len(cfgs)
+        with torch.cuda.device(self.device):
+            self.ws_bytes = nmf_batch_workspace_size(cfgs, nnz)
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            torch.cuda.current_stream(self.device).synchronize()
+            s = stream.cuda_stream if stream is not None else None
+            self.b = nmf_batch_create(cfgs, [p["indptr"] for p in problems], [p["indices"] for p in problems],
+                                      [p["data"] for p in problems], nnz, [p["u0"] for p in problems],
+                                      self.workspace, self.ws_bytes, s)
+        lib = load_library()
+        self.members = [_BatchMember(lib.nmf_batch_problem(self.b, i), c.n, c.m, c.k, dtype, self.device)
+                        for i, c in enumerate(cfgs)]
+
+    def step(self, iters: int = 1, how: str = "fused_graph"):
+        nmf_batch_step(self.b, iters, BATCH_MODES[how])
+
+    def errors(self):
+        """(E, status) per problem, after waiting for the batch."""
+        return nmf_batch_errors(self.b, self.count)
+
+    def problem(self, i: int) -> NMF:
+        return self.members[i]
+
+    def close(self):
+        if getattr(self, "b", None):
+            for mem in self.members:
+                mem.close()
+            load_library().nmf_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,5 +14,6 @@ from .corpus import (  # noqa: F401
     pairs_structure,
     per_doc_structure,
     batched_params,
+    make_batch,
     sparse_factor_init,
 )

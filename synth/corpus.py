@@ -92,20 +92,44 @@ def pairs_structure(n: int, m: int, nnz: int, alpha: float, rng: np.random.Gener
         raise ValueError("nnz exceeds n*m")
     draw = zipf_terms(n, alpha, rng)
     keys = np.empty(0, dtype=np.int64)
+    accept = 1.0  # fraction of the last round's draws that were new pairs
     while True:
         have = keys.size
-        batch = max(4096, int(1.25 * (nnz - have)) + 1024)
+        # size a round by the last acceptance rate, so that saturated head rows
+        # (most draws repeat an existing pair) do not need many rounds
+        batch = max(4096, int(1.25 * (nnz - have) / max(accept, 0.02)) + 1024)
         i = draw(batch)
         j = rng.integers(0, m, size=batch, dtype=np.int64)
         keys = np.concatenate([keys, i * m + j])
-        _, first = np.unique(keys, return_index=True)
-        first.sort()
+        first = _first_occurrences(keys, n * m)
         if first.size >= nnz:
             keys = keys[first[:nnz]]
             break
+        accept = (first.size - have) / batch
         keys = keys[first]
     keys.sort()
     return keys
+
+
+def _first_occurrences(keys: np.ndarray, bound: int) -> np.ndarray:
+    """Ascending positions of the first occurrence of each distinct value of
+    ``keys`` (all in [0, bound)): what ``np.unique(return_index=True)`` gives,
+    sorted, but through one unstable sort of key * len + position."""
+    size = keys.size
+    if size == 0:
+        return np.empty(0, dtype=np.int64)
+    if bound * size >= 2**62:
+        _, first = np.unique(keys, return_index=True)
+        first.sort()
+        return first
+    c = keys * size + np.arange(size, dtype=np.int64)
+    c.sort()
+    k = c // size
+    head = np.ones(size, dtype=bool)
+    head[1:] = k[1:] != k[:-1]
+    first = c[head] - k[head] * size
+    first.sort()
+    return first
 
 
 _PER_DOC_CHUNK = 16384
@@ -277,4 +301,34 @@ def batched_params(count: int = 256, seed: int = 5):
         k = int(rng.integers(5, 65))
         out.append(dict(n=n, m=m, density=dens, nnz=int(round(dens * n * m)), k=k,
                         t_u=n // 20, t_v=m // 20, seed=5000 + i))
+    return out
+
+
+def _batch_member(job):
+    p, dtype, alpha = job
+    c = make_corpus(p["n"], p["m"], seed=p["seed"], alpha=alpha, nnz=max(1, p["nnz"]), dtype=dtype)
+    u0, _ = make_init(p["n"], p["m"], p["k"], seed=p["seed"], dtype=dtype)
+    return dict(n=p["n"], m=p["m"], k=p["k"], t_u=p["t_u"], t_v=p["t_v"], nnz=c.nnz,
+                indptr=c.indptr, indices=c.indices, data=c.data, u0=u0, corpus=c)
+
+
+def make_batch(params, dtype: str = "f32", alpha: float = 1.1, workers: int = 1):
+    """The corpora and initial U of a batch described by ``batched_params``:
+    per problem a dict with n, m, k, t_u, t_v, indptr, indices, data, u0
+    ("pairs" structure with the problem's nnz, U0 from PCG64(seed + 1000)).
+
+    Each problem depends only on its own seed, so ``workers`` > 1 draws them
+    in forked processes (call it before the process touches a GPU)."""
+    jobs = [(p, dtype, alpha) for p in params]
+    if workers <= 1 or len(jobs) <= 1:
+        return [_batch_member(j) for j in jobs]
+    import multiprocessing as mp
+
+    # largest first, so the pool's tail is short
+    order = sorted(range(len(jobs)), key=lambda i: -jobs[i][0]["nnz"])
+    with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+        done = pool.map(_batch_member, [jobs[i] for i in order], chunksize=1)
+    out = [None] * len(jobs)
+    for i, r in zip(order, done):
+        out[i] = r
     return out

@@ -1,0 +1,173 @@
+"""GPU: the batched solver (many independent problems per launch).
+
+A batch runs the same kernels as the per-problem path, with each block
+mapped to one (problem, block) pair, so every mode must give bit-identical
+iterates to solving each problem on its own; one member is also checked
+against the FP64 oracle.  Every test prints its case before touching the GPU.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from tests.parity import rel_fro
+
+pytestmark = pytest.mark.gpu
+
+# (n, m, nnz, k, t_u, t_v, seed): uneven sizes, k from 5 to 80 (one above 64,
+# which takes the wider Gram factorisation and a narrower SpMM), a problem
+# smaller than one select tile and one whose term rows saturate.
+SHAPES = [
+    (700, 500, 9000, 12, 35, 25, 7001),
+    (2600, 1200, 60000, 33, 130, 60, 7002),
+    (90, 60, 700, 5, 4, 3, 7003),
+    (1500, 2100, 45000, 64, 75, 105, 7004),
+    (1100, 800, 30000, 80, 55, 40, 7005),
+    (400, 3000, 70000, 20, 20, 150, 7006),
+]
+
+
+def _lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_05237_amd import NMF, NMFBatch, NMFError
+
+    return NMF, NMFBatch, NMFError
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _problems(dtype, shapes=SHAPES):
+    out = []
+    for n, m, nnz, k, t_u, t_v, seed in shapes:
+        c = synth.make_corpus(n, m, seed=seed, alpha=1.1, nnz=nnz, dtype=dtype)
+        u0, _ = synth.make_init(n, m, k, seed=seed, dtype=dtype)
+        out.append(dict(n=n, m=m, k=k, t_u=t_u, t_v=t_v, indptr=c.indptr, indices=c.indices, data=c.data,
+                        u0=u0, corpus=c))
+    return out
+
+
+def _alone(NMF, probs, dtype, iters):
+    res = []
+    for p in probs:
+        s = NMF(p["n"], p["m"], p["indptr"], p["indices"], p["data"], p["u0"], t_u=p["t_u"], t_v=p["t_v"],
+                dtype=dtype)
+        s.step(iters)
+        U, V = s.factors()
+        res.append((U, V, s.history(), s.error(), s.residual()))
+        s.close()
+    return res
+
+
+def _same(member, ref):
+    U, V = member.factors()
+    np.testing.assert_array_equal(U, ref[0])
+    np.testing.assert_array_equal(V, ref[1])
+    E, R, nu, nv = member.history()
+    for a, b in zip((E, R, nu, nv), ref[2]):
+        np.testing.assert_array_equal(a, b)
+    assert member.error() == ref[3] and member.residual() == ref[4]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("how", ["loop", "loop_graph", "fused", "fused_graph"])
+def test_batch_matches_alone(dtype, how):
+    NMF, NMFBatch, _ = _lib()
+    probs = _problems(dtype)
+    _say(f"batch {how} {dtype}: {len(probs)} problems, k={[p['k'] for p in probs]}, 3+2 iterations")
+    ref = _alone(NMF, probs, dtype, 5)
+    b = NMFBatch(probs, dtype=dtype)
+    b.step(3, how)   # a graph pair plus one plain iteration in the graph modes
+    b.step(2, how)
+    E, st = b.errors()
+    assert list(st) == [0] * len(probs)
+    for i, p in enumerate(probs):
+        _same(b.problem(i), ref[i])
+        assert E[i] == ref[i][3]
+    b.close()
+
+
+def test_batch_modes_interleave():
+    """Modes may be mixed between calls (graphs for both current-U slots)."""
+    NMF, NMFBatch, _ = _lib()
+    probs = _problems("f32")
+    _say("batch f32: fused_graph 2, loop 1, fused_graph 2, loop_graph 2, fused 1")
+    ref = _alone(NMF, probs, "f32", 8)
+    b = NMFBatch(probs, dtype="f32")
+    for iters, how in [(2, "fused_graph"), (1, "loop"), (2, "fused_graph"), (2, "loop_graph"), (1, "fused")]:
+        b.step(iters, how)
+    for i in range(len(probs)):
+        _same(b.problem(i), ref[i])
+    b.close()
+
+
+def test_batch_member_vs_oracle():
+    """One FP64 member of a batch against the oracle after 6 fused-graph
+    iterations (FP64: only summation order differs)."""
+    _, NMFBatch, _ = _lib()
+    probs = _problems("f64")
+    _say("batch fused_graph f64, member 1 vs oracle, 6 iterations")
+    b = NMFBatch(probs, dtype="f64")
+    b.step(6, "fused_graph")
+    p = probs[1]
+    st = oracle.als(p["corpus"].scipy(), p["u0"], p["t_u"], p["t_v"], 6)
+    U, V = b.problem(1).factors()
+    assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9
+    np.testing.assert_array_equal(U != 0, st.U != 0)
+    E, R, _, _ = b.problem(1).history()
+    np.testing.assert_allclose(E, st.E, rtol=1e-9)
+    np.testing.assert_allclose(R, st.R, rtol=1e-8)
+    b.close()
+
+
+def test_batch_out_of_step_member():
+    """A member stepped on its own leaves the batch out of step: the fused
+    and graph modes refuse with NMF_ERR_STATE, the plain loop still runs."""
+    _, NMFBatch, NMFError = _lib()
+    probs = _problems("f32", SHAPES[:3])
+    _say("batch f32 member 0 stepped alone -> fused modes refuse")
+    b = NMFBatch(probs, dtype="f32")
+    b.step(1, "fused")
+    b.problem(0).step(1)
+    for how in ("fused", "fused_graph", "loop_graph"):
+        with pytest.raises(NMFError) as ei:
+            b.step(2, how)
+        assert ei.value.status == -7, how
+    b.step(1, "loop")
+    E, st = b.errors()
+    assert list(st) == [0, 0, 0]
+    b.close()
+
+
+def test_batch_single_problem_and_zero_iters():
+    NMF, NMFBatch, _ = _lib()
+    probs = _problems("f32", SHAPES[1:2])
+    _say("batch of one f32 problem, 0 then 4 fused_graph iterations")
+    ref = _alone(NMF, probs, "f32", 4)
+    b = NMFBatch(probs, dtype="f32")
+    b.step(0, "fused_graph")
+    b.step(4, "fused_graph")
+    _same(b.problem(0), ref[0])
+    b.close()
+
+
+def test_batch_create_reports_failing_member():
+    """A member whose first Gram is singular fails the batch's create with
+    NMF_ERR_NOT_SPD, naming the member."""
+    _, NMFBatch, NMFError = _lib()
+    probs = _problems("f64", SHAPES[:2])
+    u = np.array([[2.0, 2.0], [1.0, 1.0], [2.0, 2.0], [0.0, 0.0]])
+    A = sp.csr_matrix(np.ones((4, 3)))
+    probs.append(dict(n=4, m=3, k=2, t_u=2, t_v=2, indptr=A.indptr.astype(np.int64),
+                      indices=A.indices.astype(np.int32), data=A.data, u0=u))
+    _say("batch f64 with an exactly singular member 2 -> NMF_ERR_NOT_SPD at create")
+    with pytest.raises(NMFError) as ei:
+        NMFBatch(probs, dtype="f64")
+    assert ei.value.status == -4
+    assert "problem 2" in str(ei.value)
