@@ -44,7 +44,8 @@ typedef enum {
   NMF_OK = 0,
   NMF_ERR_INVALID_ARG = -1,   /* bad size, null pointer, malformed CSR      */
   NMF_ERR_INVALID_INPUT = -2, /* negative, NaN or Inf value in A or factors  */
-  NMF_ERR_UNSUPPORTED = -3,   /* k > 128, n or m >= 2^29, rows * k >= 2^31,
+  NMF_ERR_UNSUPPORTED = -3,   /* k > 128, n or m >= 2^29, a dense factor of
+                                 4 GiB or more (rows x k padded to 64 bytes),
                                  unknown dtype or mode                        */
   NMF_ERR_NOT_SPD = -4,       /* Gram matrix not positive definite           */
   NMF_ERR_NONFINITE = -5,     /* NaN/Inf produced (e.g. ||U_i|| = 0 in R)    */

@@ -49,9 +49,16 @@ constexpr int queue_len() {
 // zero-weight sums without a guard and the row-change test stays uniform.
 constexpr int kTileEntries = 512;
 
+// Dense factor rows in flight per wave in the queue loop (per topic slice:
+// halved when each lane holds two topics).
+constexpr int kQueueBatch = 8;
+
+// Per wave: the queue's values, byte offsets and item rows, then the
+// accumulator.
 template <typename T, int RG, bool WIDE>
 __host__ __device__ inline size_t spmm_per_wave(int) {
-  return queue_len<WIDE>() * (sizeof(uint32_t) + sizeof(T)) + kTileEntries * sizeof(T);
+  constexpr size_t Q = queue_len<WIDE>();
+  return Q * (sizeof(T) + sizeof(uint32_t)) + (Q + 15) / 16 * 16 + kTileEntries * sizeof(T);
 }
 
 // LDS of one block: W (unless raw), then each wave's buffers.
@@ -77,6 +84,7 @@ struct SpmmArgs {
   const void* ents;    // stored factor entries {value, topic}
   const void* F;       // compact dense factor rows (or the dense input)
   int32_t ld;          // row pitch of F
+  uint32_t F_bytes;    // bytes of F (its loads are range-checked against this)
   const double* W;
   void* X;
   void* C;
@@ -85,9 +93,10 @@ struct SpmmArgs {
 };
 
 struct WaveLds {
-  uint32_t* q_pk;  // dense-row queue: factor row * 8 + row within the item
-  void* q_a;       //                  the nonzero's value
-  void* tile;      // accumulator: tile[topic * RG + row]
+  uint32_t* q_off;  // dense-row queue: byte offset of the factor row in F
+  uint8_t* q_r;     //                  row within the item
+  void* q_a;        //                  the nonzero's value
+  void* tile;       // accumulator: tile[topic * RG + row]
 };
 
 template <typename T, int RG, bool WIDE>
@@ -96,8 +105,9 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, size_t wave0, i
   unsigned char* base = smem + wave0 + wv * spmm_per_wave<T, RG, WIDE>(k);
   WaveLds w;
   w.q_a = base;  // T first: 8-byte aligned for double
-  w.q_pk = reinterpret_cast<uint32_t*>(base + Q * sizeof(T));
-  w.tile = base + Q * (sizeof(T) + sizeof(uint32_t));
+  w.q_off = reinterpret_cast<uint32_t*>(base + Q * sizeof(T));
+  w.q_r = base + Q * (sizeof(T) + sizeof(uint32_t));
+  w.tile = base + Q * (sizeof(T) + sizeof(uint32_t)) + (Q + 15) / 16 * 16;
   return w;
 }
 
@@ -126,63 +136,125 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
-// Adds the queued entries [0, n8) (n8 a multiple of 8, in row order) into
-// the accumulator: eight factor rows in flight, lanes = topics, sums for the
-// current row kept in acc.  The queued row word is the same on all lanes and
-// is moved to a scalar register, so the row address is formed on the scalar
-// unit and the row-change test is a scalar branch; the value is an LDS
-// broadcast.  A hit then costs one vector FMA per topic slice.
-template <typename T, int KPL, int RG>
-__device__ __forceinline__ void run_queue(const WaveLds& w, const T* F, int ld, int n8, int k, T* acc,
-                                          int& cur_r) {
+// A load of F at a byte offset through a buffer resource: the hardware
+// returns zero for offsets at or past the resource's size.
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  // raw buffer (stride 0): 32-bit elements, range-checked by byte offset
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                           0x00020000);
+}
+
+// Adds queued entries [h, h + B) into the accumulator: B factor rows in
+// flight, lanes = topics, sums for the current row kept in acc.  A row's
+// address is its queued byte offset plus the lane's topic offset (one
+// vector add; the queued words are LDS broadcasts).  Rows are queued in
+// order, so a batch whose first and last entries share an item row lies in
+// that row: it needs one row test instead of one per entry.
+template <typename T, int KPL, int RG, int B>
+__device__ __forceinline__ void queue_batch(const WaveLds& w, __amdgpu_buffer_rsrc_t F, int h,
+                                            const uint32_t* lo, const bool* live, T* acc, int& cur_r) {
   const int lane = lane_id();
   T* tile = static_cast<T*>(w.tile);
   const T* q_a = static_cast<const T*>(w.q_a);
-  uint32_t cc[KPL];
+  const int ra = static_cast<int>(uniform(static_cast<uint32_t>(w.q_r[h])));
+  const int rb = static_cast<int>(uniform(static_cast<uint32_t>(w.q_r[h + B - 1])));
+  uint32_t off[B];
+  T aa[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    off[u] = w.q_off[h + u];
+    aa[u] = q_a[h + u];
+  }
+  // lanes past k load nothing (their quarter-waves then touch no line)
+  T f[B][KPL];
 #pragma unroll
   for (int q = 0; q < KPL; ++q) {
-    const int c = lane + 64 * q;
-    cc[q] = static_cast<uint32_t>(c < k ? c : 0);
+    if (live[q]) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) f[u][q] = buf_load<T>(F, off[u] + lo[q]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < B; ++u) f[u][q] = T(0);
+    }
   }
-  for (int h = 0; h < n8; h += 8) {
-    uint32_t pk[8];
-    T aa[8];
+  auto flush = [&](int rr) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      pk[u] = uniform(w.q_pk[h + u]);
-      aa[u] = q_a[h + u];
+    for (int q = 0; q < KPL; ++q) {
+      tile[(lane + 64 * q) * RG + cur_r] += acc[q];
+      acc[q] = T(0);
     }
-    T f[8][KPL];
+    cur_r = rr;
+  };
+  if (ra == rb) {
+    if (ra != cur_r) flush(ra);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const T* row = F + static_cast<size_t>(pk[u] >> 3) * static_cast<uint32_t>(ld);
+    for (int u = 0; u < B; ++u)
 #pragma unroll
-      for (int q = 0; q < KPL; ++q) f[u][q] = row[cc[q]];
-    }
+      for (int q = 0; q < KPL; ++q) acc[q] = fma(aa[u], f[u][q], acc[q]);
+  } else {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int rr = static_cast<int>(pk[u] & 7u);
-      if (rr != cur_r) {  // rows are queued in order: flush on a change
-#pragma unroll
-        for (int q = 0; q < KPL; ++q) {
-          tile[(lane + 64 * q) * RG + cur_r] += acc[q];
-          acc[q] = T(0);
-        }
-        cur_r = rr;
-      }
+    for (int u = 0; u < B; ++u) {
+      const int rr = static_cast<int>(uniform(static_cast<uint32_t>(w.q_r[h + u])));
+      if (rr != cur_r) flush(rr);
 #pragma unroll
       for (int q = 0; q < KPL; ++q) acc[q] = fma(aa[u], f[u][q], acc[q]);
     }
   }
 }
 
+// Adds the queued entries [0, n8) (n8 a multiple of 8, in row order): whole
+// batches of kQueueBatch rows, then the tail in batches of halving size.
+// Lanes past k add zeros into unused accumulator slots.
+template <typename T, int KPL, int RG>
+__device__ __forceinline__ void run_queue(const WaveLds& w, __amdgpu_buffer_rsrc_t F, int n8, int k, T* acc,
+                                          int& cur_r) {
+  const int lane = lane_id();
+  uint32_t lo[KPL];
+  bool live[KPL];
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    live[q] = c < k;
+    lo[q] = static_cast<uint32_t>(c) * static_cast<uint32_t>(sizeof(T));
+  }
+  constexpr int QB = kQueueBatch / KPL < 8 ? 8 : kQueueBatch / KPL;
+  int h = 0;
+  for (; h + QB <= n8; h += QB) queue_batch<T, KPL, RG, QB>(w, F, h, lo, live, acc, cur_r);
+  if constexpr (QB > 32) {
+    if (h + 32 <= n8) {
+      queue_batch<T, KPL, RG, 32>(w, F, h, lo, live, acc, cur_r);
+      h += 32;
+    }
+  }
+  if constexpr (QB > 16) {
+    if (h + 16 <= n8) {
+      queue_batch<T, KPL, RG, 16>(w, F, h, lo, live, acc, cur_r);
+      h += 16;
+    }
+  }
+  if constexpr (QB > 8) {
+    if (h + 8 <= n8) queue_batch<T, KPL, RG, 8>(w, F, h, lo, live, acc, cur_r);
+  }
+}
+
 // Queues a step's dense hits (one per lane, or two in the wide form: lane
 // positions base + 64 * s) in step order = row order, padded to whole
 // batches of 8 with zero-weight reads of the first factor row at the last
-// hit's row; returns the padded length.
+// hit's row; returns the padded length.  `ldb` is F's row pitch in bytes.
 template <typename T, int NS>
 __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, const int32_t* x, const int* r,
-                                          const T* av) {
+                                          const T* av, uint32_t ldb) {
   const int lane = lane_id();
   T* q_a = static_cast<T*>(w.q_a);
   uint64_t bal[NS];
@@ -199,7 +271,8 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
   for (int s = 0; s < NS; ++s) {
     if (hit[s]) {
       const int pos = before[s] + lane_rank(bal[s]);
-      w.q_pk[pos] = static_cast<uint32_t>(x[s]) * 8u + static_cast<uint32_t>(r[s]);
+      w.q_off[pos] = static_cast<uint32_t>(x[s]) * ldb;
+      w.q_r[pos] = static_cast<uint8_t>(r[s]);
       q_a[pos] = av[s];
     }
   }
@@ -214,7 +287,8 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
   const int r_last = __shfl(r_src, 63 - __builtin_clzll(bal[last_s]), 64);
   const int nh8 = (nh + 7) & ~7;
   if (lane < nh8 - nh) {
-    w.q_pk[nh + lane] = static_cast<uint32_t>(r_last);
+    w.q_off[nh + lane] = 0u;
+    w.q_r[nh + lane] = static_cast<uint8_t>(r_last);
     q_a[nh + lane] = T(0);
   }
   return nh8;
@@ -239,7 +313,8 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
   const int k = a.k;
   const int32_t* __restrict__ col = a.col;
   const T* __restrict__ val = static_cast<const T*>(a.val);
-  const T* __restrict__ F = static_cast<const T*>(a.F);
+  const __amdgpu_buffer_rsrc_t Fr = make_rsrc(a.F, a.F_bytes);
+  const uint32_t ldb = static_cast<uint32_t>(a.ld) * static_cast<uint32_t>(sizeof(T));
   const FactorEnt<T>* __restrict__ ents = static_cast<const FactorEnt<T>*>(a.ents);
   T* tile = static_cast<T*>(w.tile);
   T acc[KPL];
@@ -340,8 +415,8 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
     bool hit[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) hit[s] = DENSE_IN ? valid[s] : cnt[s] > a.sparse_row;
-    const int nq = queue_hits<T, NS>(w, hit, x, r, av);
-    run_queue<T, KPL, RG>(w, F, a.ld, nq, k, acc, cur_r);
+    const int nq = queue_hits<T, NS>(w, hit, x, r, av, ldb);
+    run_queue<T, KPL, RG>(w, Fr, nq, k, acc, cur_r);
   }
 #pragma unroll
   for (int q = 0; q < KPL; ++q) tile[(lane + 64 * q) * RG + cur_r] += acc[q];
@@ -562,6 +637,7 @@ hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, 
   a.ents = F.packed;
   a.F = dense_in ? static_cast<const void*>(dense_in) : static_cast<const void*>(F.dense);
   a.ld = dense_in ? h->k : F.ld;
+  a.F_bytes = static_cast<uint32_t>(F.rows * a.ld * static_cast<int64_t>(sizeof(T)));
   a.W = W;
   a.X = X;
   a.C = C;

@@ -213,7 +213,7 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
 nmf_status check_config(const nmf_config* c) {
   if (c == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "config is NULL");
   if (c->n < 1 || c->m < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "n and m must be >= 1");
-  // the SpMM queues a factor row index * 8 + row-in-item in 32 bits
+  // row indices and per-row offsets are held in 32 bits
   if (c->n >= (int64_t(1) << 29) || c->m >= (int64_t(1) << 29))
     return fail(nullptr, NMF_ERR_UNSUPPORTED, "n and m must be below 2^29");
   if (c->k < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "k must be >= 1");
@@ -223,10 +223,12 @@ nmf_status check_config(const nmf_config* c) {
   if (c->mode != NMF_MODE_COLUMN && c->mode != NMF_MODE_NONE)
     return fail(nullptr, NMF_ERR_UNSUPPORTED, "mode not supported");
   if (c->dtype != NMF_F32 && c->dtype != NMF_F64) return fail(nullptr, NMF_ERR_UNSUPPORTED, "dtype");
-  // int32 offsets into the k-wide matrices and the compact dense copies
-  const int64_t ld = dense_ld(c->k, c->dtype == NMF_F32 ? 4 : 8);
-  if (c->n * ld >= (int64_t(1) << 31) || c->m * ld >= (int64_t(1) << 31))
-    return fail(nullptr, NMF_ERR_UNSUPPORTED, "rows * k must be below 2^31");
+  // int32 element offsets into the k-wide matrices, and 32-bit byte offsets
+  // into the dense factor copies the SpMM gathers from
+  const int64_t elt = c->dtype == NMF_F32 ? 4 : 8;
+  const int64_t ld = dense_ld(c->k, elt);
+  if (c->n * ld * elt >= (int64_t(1) << 32) || c->m * ld * elt >= (int64_t(1) << 32))
+    return fail(nullptr, NMF_ERR_UNSUPPORTED, "a dense factor (rows x k, k padded to 64 bytes) must be below 4 GiB");
   return NMF_OK;
 }
 

@@ -59,7 +59,7 @@ struct Plan {
 };
 
 // A factor as stored (row-compressed sparse) plus the gather cache the SpMM
-// reads: every nonempty row expanded to a dense row (16-byte aligned rows, so
+// reads: every nonempty row expanded to a dense row (64-byte aligned rows, so
 // one lane can load four floats or two doubles of a row at once).
 struct Factor {
   int64_t rows = 0;
@@ -69,7 +69,7 @@ struct Factor {
   int32_t* slot = nullptr;     // [rows]: -1 empty, else compact row index
   int32_t* rowid = nullptr;    // [rows]: compact row index -> row
   void* dense = nullptr;       // [rows][ld] T: compact dense rows 0..R-1, zero past k
-  int32_t ld = 0;              // row pitch of `dense`: k rounded up to 16 bytes
+  int32_t ld = 0;              // row pitch of `dense`: k rounded up to 64 bytes
   int32_t* counts = nullptr;   // device [0] = nnz, [1] = R (nonempty rows)
   // SpMM gather metadata: per row {compact dense row (rows with more entries
   // than the gathering SpMM's threshold) or first stored entry, entry count};
@@ -85,10 +85,11 @@ struct FactorEnt {
   uint32_t t;
 };
 
-// Row pitch of a factor's compact dense copy: k rounded up to whole 16-byte
-// vectors (four floats or two doubles).
+// Row pitch of a factor's compact dense copy: k rounded up to whole 64-byte
+// lines (16 floats or 8 doubles), so that each quarter of a wave reading a
+// row (lanes = topics) touches exactly one cache line.
 inline int32_t dense_ld(int32_t k, size_t elt) {
-  const int32_t v = static_cast<int32_t>(16 / elt);
+  const int32_t v = static_cast<int32_t>(64 / elt);
   return (k + v - 1) / v * v;
 }
 

@@ -62,6 +62,18 @@ def test_config_validation(kw, status):
     assert ei.value.status == status
 
 
+@pytest.mark.parametrize("k,dtype,row_bytes", [(52, B.NMF_F32, 64 * 4), (50, B.NMF_F64, 56 * 8),
+                                                (5, B.NMF_F32, 16 * 4), (128, B.NMF_F32, 128 * 4)])
+def test_dense_factor_limit(k, dtype, row_bytes):
+    """A dense factor copy (rows x k, rows padded to 64 bytes) must stay below
+    4 GiB: the largest accepted row count and the first refused one."""
+    top = ((1 << 32) - 1) // row_bytes
+    assert B.nmf_workspace_size(_cfg(m=top, k=k, dtype=dtype), 100) > 0
+    with pytest.raises(B.NMFError) as ei:
+        B.nmf_workspace_size(_cfg(m=top + 1, k=k, dtype=dtype), 100)
+    assert ei.value.status == B.NMF_ERR_UNSUPPORTED
+
+
 def test_create_rejects_null_arguments_without_a_device():
     lib = B.load_library()
     cfg = _cfg()
