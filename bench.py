@@ -109,8 +109,9 @@ def batch_bench(problems, iters: int, warmup: int):
     """The many-corpora workload solved three ways from the same start: (i) a
     per-problem loop of ALS iterations, (ii) that loop captured as a HIP
     graph, (iii) one launch per stage for all problems, captured as a graph
-    (plus (iii) without the graph).  Every variant restarts each problem from
-    its U0 and must end at bit-identical errors (equal accuracy)."""
+    (plus (iii) without the graph).  The SpMM forms are first picked by the
+    batch autotuner; every variant then restarts each problem from its U0 and
+    must end at bit-identical errors (equal accuracy)."""
     import numpy as np
     import torch
 
@@ -128,6 +129,14 @@ def batch_bench(problems, iters: int, warmup: int):
         for i, u in enumerate(u0d):
             b.problem(i).set_factors(u)
         torch.cuda.synchronize()
+
+    # the autotuner picks each half's SpMM form on the fused batch; every
+    # variant below then runs with that choice
+    b.step(2, "fused")
+    t0 = time.perf_counter()
+    tuned = b.tune(iters=1)
+    torch.cuda.synchronize()
+    log(f"batch: tuned in {time.perf_counter() - t0:.1f}s: {tuned}")
 
     res, errs = {}, {}
     for how in ("loop", "loop_graph", "fused", "fused_graph"):
@@ -159,6 +168,7 @@ def batch_bench(problems, iters: int, warmup: int):
         "problem_iters_per_s": {h: round(len(problems) * 1e3 / v, 1) for h, v in res.items()},
         "speedup_vs_loop": {h: round(res["loop"] / v, 2) for h, v in res.items()},
         "equal_accuracy": bool(equal),
+        "tuned_spmm": tuned,
         "E_mean": float(np.mean(errs["fused_graph"])),
     }
 

@@ -200,8 +200,8 @@ nmf_status nmf_profile_read(nmf_handle* h, double* ms, int64_t* count, int32_t n
 enum {
   NMF_PARAM_SPARSE_ROW_V = 0, /* V half: U rows with <= this many entries are
                                  gathered entry by entry, denser rows whole
-                                 (0..128; default 3)                        */
-  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V             */
+                                 (0..128; default 1)                        */
+  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V (default 3) */
   NMF_PARAM_WIDE_V = 2,       /* V half SpMM step form: 0 = 64 nonzeros per
                                  step with loads only on the lanes that need
                                  them (default; suits factors whose gathered
@@ -209,12 +209,22 @@ enum {
                                  step with every load issued on all lanes
                                  (suits very sparse gathered rows)          */
   NMF_PARAM_WIDE_U = 3,       /* U half: the same (default 1)               */
-  NMF_NUM_PARAMS = 4
+  NMF_PARAM_WAVES_V = 4,      /* V half SpMM: waves per block, 1/2/4/8/16
+                                 (default 16; fewer when the k x k inverse
+                                 and the wave buffers exceed the LDS)       */
+  NMF_PARAM_WAVES_U = 5,      /* U half: the same (default 8)               */
+  NMF_NUM_PARAMS = 6
 };
 
-/* Set a tuning parameter of a handle (applies to later launches).
+/* Set a tuning parameter of a handle (applies to later launches).  A problem
+ * of a batch takes new values through nmf_batch_set_param.  The parameters
+ * change which kernels and launch shapes run; results change at most by
+ * float32 summation order (the waves setting not at all).
  * Errors: INVALID_ARG for an unknown parameter or a value out of range. */
 nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value);
+
+/* Read a tuning parameter into *value.  Errors: INVALID_ARG. */
+nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value);
 
 /* Message for the last error on this handle (or of the last failed
  * nmf_create when h is NULL).  Never NULL. */
@@ -268,8 +278,26 @@ nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t
  * (NMF_BATCH_*).  Asynchronous.  A problem whose device status turns sticky
  * stops advancing (its kernels return at once) while the others continue.
  * The first graph-mode call captures the graph (and so takes longer).
- * Errors: INVALID_ARG (iters < 0, unknown how), DEVICE. */
+ * Errors: INVALID_ARG (iters < 0, unknown how), DEVICE, STATE (a graph or
+ * fused mode after some problem was stepped on its own handle: the problems'
+ * iterates are out of step; NMF_BATCH_LOOP still runs). */
 nmf_status nmf_batch_step(nmf_batch* b, int32_t iters, int32_t how);
+
+/* Set a tuning parameter (as nmf_set_param) of problem i, or of every
+ * problem for i = -1, and record the fused launches again (captured graphs
+ * are dropped and captured anew by the next graph-mode call).  Synchronizes.
+ * Errors: INVALID_ARG, those of nmf_set_param (with the problem's index). */
+nmf_status nmf_batch_set_param(nmf_batch* b, int32_t i, int32_t param, int64_t value);
+
+/* Autotuner of the fused form: for each half-step in turn (V, then U), tries
+ * a fixed list of SpMM forms (step form, entry-by-entry threshold, waves per
+ * block) on all problems at once, each for 1 + `iters` fused iterations
+ * timed with HIP events on the batch's stream, and keeps the fastest.  The
+ * trials are real iterations: every problem advances 16 * (1 + iters)
+ * iterations.  chosen (may be NULL) receives 6 ints: {wide, entry threshold,
+ * waves} of the V half, then of the U half.  Synchronizes.
+ * Errors: INVALID_ARG (iters < 1), STATE (problems out of step), DEVICE. */
+nmf_status nmf_batch_tune(nmf_batch* b, int32_t iters, int32_t* chosen);
 
 /* Wait for the batch, then for every problem i: E[i] = its relative error
  * (as nmf_error) and status[i] = its status (NMF_OK or the sticky error).

@@ -35,7 +35,7 @@ namespace nmfk {
 
 namespace {
 
-constexpr int kWaves = 8;  // waves per block (fewer when W and the wave buffers exceed the LDS)
+constexpr int kWaves = 16;  // most waves per block (fewer when W and the wave buffers exceed the LDS)
 constexpr size_t kLdsBytes = 160 * 1024;
 // Dense-row queue: one step's hits (64, or 128 in the wide form) padded to
 // whole batches of 8.
@@ -592,9 +592,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_spmm_heavy_b(const SpmmArgs* as
 }
 
 template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bool WIDE>
-hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
+hipError_t launch(nmf_handle* h, const SpmmArgs& a, int waves_max) {
   // W (float64, k x k) is shared by the block; with large k fewer waves fit
-  int waves = kWaves;
+  int waves = std::min(waves_max, kWaves);
   while (waves > 1 && spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves) > kLdsBytes) waves /= 2;
   const size_t lds = spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves);
   if (lds > kLdsBytes) return hipErrorInvalidValue;
@@ -620,7 +620,7 @@ hipError_t launch(nmf_handle* h, const SpmmArgs& a) {
 
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                bool raw, const T* dense_in, int sparse_row, bool wide) {
+                bool raw, const T* dense_in, int sparse_row, bool wide, int waves) {
   SpmmArgs a{};
   a.rowptr = p.rowptr;
   a.col = p.col;
@@ -647,22 +647,22 @@ hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, 
   const bool dense = dense_in != nullptr;
   if (raw) {
     if (dense)
-      return two ? launch<T, 2, 4, true, false, true, false>(h, a) : launch<T, 1, 8, true, false, true, false>(h, a);
-    return two ? launch<T, 2, 4, true, false, false, false>(h, a) : launch<T, 1, 8, true, false, false, false>(h, a);
+      return two ? launch<T, 2, 4, true, false, true, false>(h, a, waves) : launch<T, 1, 8, true, false, true, false>(h, a, waves);
+    return two ? launch<T, 2, 4, true, false, false, false>(h, a, waves) : launch<T, 1, 8, true, false, false, false>(h, a, waves);
   }
   if (C != nullptr) {
     if (wide)
-      return two ? launch<T, 2, 4, false, true, false, true>(h, a) : launch<T, 1, 8, false, true, false, true>(h, a);
-    return two ? launch<T, 2, 4, false, true, false, false>(h, a) : launch<T, 1, 8, false, true, false, false>(h, a);
+      return two ? launch<T, 2, 4, false, true, false, true>(h, a, waves) : launch<T, 1, 8, false, true, false, true>(h, a, waves);
+    return two ? launch<T, 2, 4, false, true, false, false>(h, a, waves) : launch<T, 1, 8, false, true, false, false>(h, a, waves);
   }
   if (wide)
-    return two ? launch<T, 2, 4, false, false, false, true>(h, a) : launch<T, 1, 8, false, false, false, true>(h, a);
-  return two ? launch<T, 2, 4, false, false, false, false>(h, a) : launch<T, 1, 8, false, false, false, false>(h, a);
+    return two ? launch<T, 2, 4, false, false, false, true>(h, a, waves) : launch<T, 1, 8, false, false, false, true>(h, a, waves);
+  return two ? launch<T, 2, 4, false, false, false, false>(h, a, waves) : launch<T, 1, 8, false, false, false, false>(h, a, waves);
 }
 
 template hipError_t spmm<float>(nmf_handle*, const Plan&, const Factor&, const double*, float*,
-                                float*, bool, const float*, int, bool);
+                                float*, bool, const float*, int, bool, int);
 template hipError_t spmm<double>(nmf_handle*, const Plan&, const Factor&, const double*, double*,
-                                 double*, bool, const double*, int, bool);
+                                 double*, bool, const double*, int, bool, int);
 
 }  // namespace nmfk

@@ -348,7 +348,7 @@ nmf_status v_half(nmf_handle* h) {
   Factor& U = h->U[h->cur_u];
   T* vpre = static_cast<T*>(h->vpre);
   PROF(h, -1);
-  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr, h->sparse_row[0], h->wide[0]));
+  HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr, h->sparse_row[0], h->wide[0], h->waves[0]));
   PROF(h, NMF_STAGE_SPMM_V);
   HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
   PROF(h, NMF_STAGE_SELECT_V);
@@ -367,7 +367,7 @@ nmf_status u_half(nmf_handle* h, bool keep_c) {
   Factor& Un = h->U[nxt];
   T* upre = static_cast<T*>(h->upre);
   HIPCHK(h, spmm<T>(h, h->planA, h->V, h->gV.W, upre, keep_c ? static_cast<T*>(h->cbuf) : nullptr,
-                    false, nullptr, h->sparse_row[1], h->wide[1]));
+                    false, nullptr, h->sparse_row[1], h->wide[1], h->waves[1]));
   PROF(h, NMF_STAGE_SPMM_U);
   HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
   PROF(h, NMF_STAGE_SELECT_U);
@@ -819,6 +819,26 @@ nmf_status reload_meta(nmf_handle* h, int which) {
   return sync_status(h);
 }
 
+nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value) {
+  if (h == nullptr || value == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  switch (param) {
+    case NMF_PARAM_SPARSE_ROW_V:
+    case NMF_PARAM_SPARSE_ROW_U:
+      *value = h->sparse_row[param];
+      return NMF_OK;
+    case NMF_PARAM_WIDE_V:
+    case NMF_PARAM_WIDE_U:
+      *value = h->wide[param - NMF_PARAM_WIDE_V] ? 1 : 0;
+      return NMF_OK;
+    case NMF_PARAM_WAVES_V:
+    case NMF_PARAM_WAVES_U:
+      *value = h->waves[param - NMF_PARAM_WAVES_V];
+      return NMF_OK;
+    default:
+      return fail(h, NMF_ERR_INVALID_ARG, "unknown parameter");
+  }
+}
+
 nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value) {
   if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
   switch (param) {
@@ -833,6 +853,12 @@ nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value) {
     case NMF_PARAM_WIDE_U:
       if (value != 0 && value != 1) return fail(h, NMF_ERR_INVALID_ARG, "step form must be 0 or 1");
       h->wide[param - NMF_PARAM_WIDE_V] = value != 0;
+      return NMF_OK;
+    case NMF_PARAM_WAVES_V:
+    case NMF_PARAM_WAVES_U:
+      if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+        return fail(h, NMF_ERR_INVALID_ARG, "waves per block must be 1, 2, 4, 8 or 16");
+      h->waves[param - NMF_PARAM_WAVES_V] = static_cast<int>(value);
       return NMF_OK;
     default:
       return fail(h, NMF_ERR_INVALID_ARG, "unknown parameter");
@@ -906,6 +932,8 @@ struct nmf_batch {
   bool own_stream = false;
   std::vector<Launch> plan[2];  // one iteration starting at current-U slot 0 / 1
   hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [loop, fused][start slot]
+  char* tables = nullptr;       // device: the fused launches' argument structs and block maps
+  size_t table_bytes = 0;
   std::string last_error;
 };
 
@@ -1053,6 +1081,20 @@ nmf_status build_plans(nmf_batch* b, char* tables, size_t table_bytes) {
   return NMF_OK;
 }
 
+// Drop the fused plans and every captured graph, then record the plans
+// again (after the members' tuning parameters changed).
+nmf_status rebuild_plans(nmf_batch* b) {
+  BCHK(b, hipStreamSynchronize(b->stream));
+  for (auto& row : b->exec)
+    for (auto& e : row) {
+      if (e) (void)hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+  b->plan[0].clear();
+  b->plan[1].clear();
+  return build_plans(b, b->tables, b->table_bytes);
+}
+
 nmf_status launch_plan(nmf_batch* b, int slot) {
   for (const nmf_batch::Launch& L : b->plan[slot]) {
     void* kargs[2] = {const_cast<void**>(&L.args), const_cast<void**>(&L.map)};
@@ -1169,7 +1211,9 @@ nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t
     off += align_up(w, 256);
   }
   if (s == NMF_OK) {
-    s = build_plans(b, base + off, ws_bytes - off);
+    b->tables = base + off;
+    b->table_bytes = ws_bytes - off;
+    s = build_plans(b, b->tables, b->table_bytes);
     if (s != NMF_OK) g_batch_error = b->last_error;
   }
   if (s != NMF_OK) {
@@ -1221,6 +1265,77 @@ nmf_status nmf_batch_errors(nmf_batch* b, double* E, int32_t* status) {
     }
   }
   return first;
+}
+
+nmf_status nmf_batch_set_param(nmf_batch* b, int32_t i, int32_t param, int64_t value) {
+  if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
+  if (i < -1 || i >= static_cast<int32_t>(b->h.size())) return batch_fail(b, NMF_ERR_INVALID_ARG, "no such problem");
+  BCHK(b, hipStreamSynchronize(b->stream));
+  for (size_t j = 0; j < b->h.size(); ++j) {
+    if (i >= 0 && static_cast<int32_t>(j) != i) continue;
+    nmf_status s = nmf_set_param(b->h[j], param, value);
+    if (s != NMF_OK) return batch_fail(b, s, "problem " + std::to_string(j) + ": " + b->h[j]->last_error);
+  }
+  return rebuild_plans(b);
+}
+
+nmf_status nmf_batch_tune(nmf_batch* b, int32_t iters, int32_t* chosen) {
+  if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
+  if (iters < 1) return batch_fail(b, NMF_ERR_INVALID_ARG, "iters < 1");
+  int slot;
+  nmf_status s = common_slot(b, &slot);
+  if (s != NMF_OK) return s;
+  // SpMM forms tried for each half: {wide step, entry-by-entry threshold, waves per block}
+  static const int kCands[][3] = {{0, 1, 16}, {0, 1, 8}, {0, 3, 8}, {0, 0, 16},
+                                  {1, 3, 8},  {1, 1, 8}, {1, 3, 16}, {1, 0, 8}};
+  const int n_cands = static_cast<int>(sizeof(kCands) / sizeof(kCands[0]));
+  auto apply = [&](int half, const int* c) -> nmf_status {
+    const int32_t params[3] = {half == 0 ? NMF_PARAM_WIDE_V : NMF_PARAM_WIDE_U,
+                               half == 0 ? NMF_PARAM_SPARSE_ROW_V : NMF_PARAM_SPARSE_ROW_U,
+                               half == 0 ? NMF_PARAM_WAVES_V : NMF_PARAM_WAVES_U};
+    for (size_t j = 0; j < b->h.size(); ++j)
+      for (int q = 0; q < 3; ++q) {
+        nmf_status st = nmf_set_param(b->h[j], params[q], c[q]);
+        if (st != NMF_OK) return batch_fail(b, st, "problem " + std::to_string(j) + ": " + b->h[j]->last_error);
+      }
+    return rebuild_plans(b);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BCHK(b, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return batch_fail(b, NMF_ERR_DEVICE, "hipEventCreate failed");
+  }
+  int best[2] = {0, 0};
+  for (int half = 0; half < 2 && s == NMF_OK; ++half) {
+    float best_ms = 0.f;
+    for (int c = 0; c < n_cands && s == NMF_OK; ++c) {
+      if ((s = apply(half, kCands[c])) != NMF_OK) break;
+      // one untimed iteration under the new form, then `iters` timed ones
+      if ((s = batch_iteration(b, true)) != NMF_OK) break;
+      if (hipEventRecord(e0, b->stream) != hipSuccess) s = batch_fail(b, NMF_ERR_DEVICE, "hipEventRecord failed");
+      for (int32_t it = 0; it < iters && s == NMF_OK; ++it) s = batch_iteration(b, true);
+      if (s != NMF_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        s = batch_fail(b, NMF_ERR_DEVICE, "timing a tuning trial failed");
+        break;
+      }
+      if (c == 0 || ms < best_ms) {
+        best_ms = ms;
+        best[half] = c;
+      }
+    }
+    if (s == NMF_OK) s = apply(half, kCands[best[half]]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != NMF_OK) return s;
+  if (chosen)
+    for (int half = 0; half < 2; ++half)
+      for (int q = 0; q < 3; ++q) chosen[half * 3 + q] = kCands[best[half]][q];
+  return NMF_OK;
 }
 
 nmf_handle* nmf_batch_problem(nmf_batch* b, int32_t i) {

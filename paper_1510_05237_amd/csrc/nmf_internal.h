@@ -195,8 +195,9 @@ struct nmf_handle {
   bool have_v = false;
   bool have_pre_v = false, have_pre_u = false;
   bool metrics_valid = false;  // the newest history record describes the current U, V
-  int sparse_row[2] = {nmfk::kSparseRow, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
-  bool wide[2] = {false, true};                               // NMF_PARAM_WIDE_V / _U
+  int sparse_row[2] = {1, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
+  bool wide[2] = {false, true};               // NMF_PARAM_WIDE_V / _U
+  int waves[2] = {16, 8};                     // NMF_PARAM_WAVES_V / _U: waves per SpMM block
   // stage timing (nmf_profile)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;      // pool
@@ -215,7 +216,7 @@ namespace nmfk {
 // double.  All enqueue on h->stream and return hipSuccess or the launch error.
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                bool raw, const T* dense_in, int sparse_row, bool wide = false);
+                bool raw, const T* dense_in, int sparse_row, bool wide = false, int waves = 8);
 template <typename T>
 hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int mode,
                        const Factor& out_f);

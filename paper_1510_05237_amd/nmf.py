@@ -98,6 +98,9 @@ SIGNATURES = {
     "nmf_batch_create": (_I32, [_I32, ctypes.POINTER(nmf_config), _P, _P, _P, _PI64, _P, _P, ctypes.c_size_t, _P,
                                 ctypes.POINTER(_P)]),
     "nmf_batch_step": (_I32, [_P, _I32, _I32]),
+    "nmf_batch_set_param": (_I32, [_P, _I32, _I32, ctypes.c_int64]),
+    "nmf_batch_tune": (_I32, [_P, _I32, _P]),
+    "nmf_get_param": (_I32, [_P, _I32, _P]),
     "nmf_batch_errors": (_I32, [_P, _P, _P]),
     "nmf_batch_problem": (_P, [_P, _I32]),
     "nmf_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -239,10 +242,18 @@ NMF_PARAM_SPARSE_ROW_V = 0
 NMF_PARAM_SPARSE_ROW_U = 1
 NMF_PARAM_WIDE_V = 2
 NMF_PARAM_WIDE_U = 3
+NMF_PARAM_WAVES_V = 4
+NMF_PARAM_WAVES_U = 5
 
 
 def nmf_set_param(h: int, param: int, value: int):
     _check(load_library().nmf_set_param(h, param, value), h)
+
+
+def nmf_get_param(h: int, param: int) -> int:
+    v = ctypes.c_int64()
+    _check(load_library().nmf_get_param(h, param, ctypes.byref(v)), h)
+    return v.value
 
 
 NMF_NUM_STAGES = 9
@@ -305,6 +316,17 @@ def nmf_batch_create(cfgs, rowptrs, cols, vals, nnz, u0s, workspace, ws_bytes, s
 
 def nmf_batch_step(b: int, iters: int, how: int):
     _bcheck(load_library().nmf_batch_step(b, iters, how), b)
+
+
+def nmf_batch_set_param(b: int, i: int, param: int, value: int):
+    _bcheck(load_library().nmf_batch_set_param(b, i, param, value), b)
+
+
+def nmf_batch_tune(b: int, iters: int = 2):
+    out = np.zeros(6, np.int32)
+    _bcheck(load_library().nmf_batch_tune(b, iters, _ptr(out)), b)
+    keys = ("wide", "sparse_row", "waves")
+    return {"v": dict(zip(keys, map(int, out[:3]))), "u": dict(zip(keys, map(int, out[3:])))}
 
 
 def nmf_batch_errors(b: int, count: int):
@@ -404,6 +426,9 @@ class NMF:
 
     def set_param(self, param: int, value: int):
         nmf_set_param(self.h, param, value)
+
+    def get_param(self, param: int) -> int:
+        return nmf_get_param(self.h, param)
 
     def profile(self, enable: bool):
         nmf_profile(self.h, enable)
@@ -522,6 +547,15 @@ class NMFBatch:
 
     def step(self, iters: int = 1, how: str = "fused_graph"):
         nmf_batch_step(self.b, iters, BATCH_MODES[how])
+
+    def set_param(self, param: int, value: int, problem: int = -1):
+        """Tuning parameter of one problem (or all, -1); re-records the fused launches."""
+        nmf_batch_set_param(self.b, problem, param, value)
+
+    def tune(self, iters: int = 2):
+        """Pick each half-step's SpMM form by timing the fused batch (advances
+        every problem 16 * (1 + iters) iterations); returns the choice."""
+        return nmf_batch_tune(self.b, iters)
 
     def errors(self):
         """(E, status) per problem, after waiting for the batch."""

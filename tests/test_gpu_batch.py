@@ -171,3 +171,86 @@ def test_batch_create_reports_failing_member():
         NMFBatch(probs, dtype="f64")
     assert ei.value.status == -4
     assert "problem 2" in str(ei.value)
+
+
+def _alone_with(NMF, probs, dtype, iters, params):
+    """Per-problem runs with the given tuning parameters (dict param -> value
+    per problem), set before the first iteration."""
+    res = []
+    for p, prm in zip(probs, params):
+        s = NMF(p["n"], p["m"], p["indptr"], p["indices"], p["data"], p["u0"], t_u=p["t_u"], t_v=p["t_v"],
+                dtype=dtype)
+        for k_, v_ in prm.items():
+            s.set_param(k_, v_)
+        s.step(iters)
+        U, V = s.factors()
+        res.append((U, V, s.history(), s.error(), s.residual()))
+        s.close()
+    return res
+
+
+def _same_tail(member, ref):
+    U, V = member.factors()
+    np.testing.assert_array_equal(U, ref[0])
+    np.testing.assert_array_equal(V, ref[1])
+    E, R, _, _ = member.history()
+    n = len(ref[2][0])
+    np.testing.assert_array_equal(E[-n:], ref[2][0])
+    np.testing.assert_array_equal(R[-n:], ref[2][1])
+
+
+def test_batch_set_param():
+    """Parameters set through the batch (one problem, then all) re-record
+    the fused launches: the iterates equal per-problem runs with the same
+    parameters."""
+    NMF, NMFBatch, _ = _lib()
+    from paper_1510_05237_amd import NMF_PARAM_SPARSE_ROW_V, NMF_PARAM_WAVES_V, NMF_PARAM_WIDE_U
+
+    probs = _problems("f32")
+    _say("batch f32: wide_u=0 on problem 1, waves_v=4 and sparse_row_v=3 on all, 3 fused_graph iterations")
+    b = NMFBatch(probs, dtype="f32")
+    b.set_param(NMF_PARAM_WIDE_U, 0, problem=1)
+    b.set_param(NMF_PARAM_WAVES_V, 4)
+    b.set_param(NMF_PARAM_SPARSE_ROW_V, 3)
+    prm = [{NMF_PARAM_WAVES_V: 4, NMF_PARAM_SPARSE_ROW_V: 3} for _ in probs]
+    prm[1][NMF_PARAM_WIDE_U] = 0
+    for i, pr in enumerate(prm):
+        for k_, v_ in pr.items():
+            assert b.problem(i).get_param(k_) == v_
+    ref = _alone_with(NMF, probs, "f32", 3, prm)
+    b.step(3, "fused_graph")
+    for i in range(len(probs)):
+        _same(b.problem(i), ref[i])
+    b.close()
+
+
+def test_batch_tune_then_restart():
+    """The autotuner leaves every problem on one of its candidate forms; from
+    a restart at U0 the tuned batch equals per-problem runs with the chosen
+    parameters."""
+    NMF, NMFBatch, _ = _lib()
+    from paper_1510_05237_amd import (NMF_PARAM_SPARSE_ROW_U, NMF_PARAM_SPARSE_ROW_V, NMF_PARAM_WAVES_U,
+                                      NMF_PARAM_WAVES_V, NMF_PARAM_WIDE_U, NMF_PARAM_WIDE_V)
+
+    probs = _problems("f32")
+    _say("batch f32: 2 fused iterations, tune(iters=1), restart from U0, 3 fused_graph iterations")
+    b = NMFBatch(probs, dtype="f32")
+    b.step(2, "fused")
+    ch = b.tune(iters=1)
+    keymap = {("v", "wide"): NMF_PARAM_WIDE_V, ("v", "sparse_row"): NMF_PARAM_SPARSE_ROW_V,
+              ("v", "waves"): NMF_PARAM_WAVES_V, ("u", "wide"): NMF_PARAM_WIDE_U,
+              ("u", "sparse_row"): NMF_PARAM_SPARSE_ROW_U, ("u", "waves"): NMF_PARAM_WAVES_U}
+    prm = {keymap[(h, k)]: v for h in ("v", "u") for k, v in ch[h].items()}
+    assert ch["v"]["waves"] in (8, 16) and ch["u"]["wide"] in (0, 1)
+    for i in range(len(probs)):
+        for k_, v_ in prm.items():
+            assert b.problem(i).get_param(k_) == v_
+    E, st = b.errors()
+    assert list(st) == [0] * len(probs) and np.all(np.isfinite(E))
+    for i, p in enumerate(probs):
+        b.problem(i).set_factors(p["u0"])
+    b.step(3, "fused_graph")
+    ref = _alone_with(NMF, probs, "f32", 3, [prm] * len(probs))
+    for i in range(len(probs)):
+        _same_tail(b.problem(i), ref[i])
+    b.close()

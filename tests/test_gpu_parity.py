@@ -257,35 +257,40 @@ def test_determinism_and_resume():
 
 
 def test_tuning_parameters_fp64():
-    """Every SpMM configuration (entry-by-entry threshold 0, 1, 3, 128 and
-    both step forms, on both halves, changed between iterations) reproduces
-    the oracle's FP64 trajectory; out-of-range settings are refused."""
-    from paper_1510_05237_amd import (NMF_PARAM_SPARSE_ROW_U, NMF_PARAM_SPARSE_ROW_V, NMF_PARAM_WIDE_U,
-                                      NMF_PARAM_WIDE_V)
+    """Every SpMM configuration (entry-by-entry threshold 0, 1, 3, 128, both
+    step forms and 1 to 16 waves per block, on both halves, changed between
+    iterations) reproduces the oracle's FP64 trajectory; out-of-range
+    settings are refused."""
+    from paper_1510_05237_amd import (NMF_PARAM_SPARSE_ROW_U, NMF_PARAM_SPARSE_ROW_V, NMF_PARAM_WAVES_U,
+                                      NMF_PARAM_WAVES_V, NMF_PARAM_WIDE_U, NMF_PARAM_WIDE_V)
 
     _, NMFError = _nmf()
     c, u0, v0, p = synth.make_workload("plain_f64_2000x1000")
     A = c.scipy()
-    settings = [(0, 0, 0, 0), (0, 1, 0, 1), (3, 1, 3, 0), (128, 0, 128, 1), (1, 0, 1, 1), (3, 0, 3, 1)]
+    settings = [(0, 0, 0, 0, 16, 8), (0, 1, 0, 1, 8, 16), (3, 1, 3, 0, 1, 2), (128, 0, 128, 1, 4, 1),
+                (1, 0, 1, 1, 2, 4), (3, 0, 3, 1, 16, 16)]
     _say(f"fp64 2000x1000 k={p['k']}: {len(settings)} tuning settings, one per iteration")
     prob = _problem(c, u0, p["k"], p["t_u"], p["t_v"], "f64")
     st = None
-    for it, (srv, wv, sru, wu) in enumerate(settings):
+    for it, (srv, wv, sru, wu, nwv, nwu) in enumerate(settings):
         prob.set_param(NMF_PARAM_SPARSE_ROW_V, srv)
         prob.set_param(NMF_PARAM_WIDE_V, wv)
         prob.set_param(NMF_PARAM_SPARSE_ROW_U, sru)
         prob.set_param(NMF_PARAM_WIDE_U, wu)
+        prob.set_param(NMF_PARAM_WAVES_V, nwv)
+        prob.set_param(NMF_PARAM_WAVES_U, nwu)
         prob.step(1)
         st = oracle.als(A, u0, p["t_u"], p["t_v"], 1, state=st)
         U, V = prob.factors()
-        assert rel_fro(U, st.U) < 1e-9, (it, srv, wv, sru, wu)
-        assert rel_fro(V, st.V) < 1e-9, (it, srv, wv, sru, wu)
+        assert rel_fro(U, st.U) < 1e-9, (it, srv, wv, sru, wu, nwv, nwu)
+        assert rel_fro(V, st.V) < 1e-9, (it, srv, wv, sru, wu, nwv, nwu)
         np.testing.assert_array_equal(U != 0, st.U != 0)
         np.testing.assert_array_equal(V != 0, st.V != 0)
     E, R, _, _ = prob.history()
     np.testing.assert_allclose(E, st.E, rtol=1e-9)
     for param, bad in ((NMF_PARAM_SPARSE_ROW_V, -1), (NMF_PARAM_SPARSE_ROW_U, 129), (NMF_PARAM_WIDE_V, 2),
-                       (NMF_PARAM_WIDE_U, -1), (99, 0)):
+                       (NMF_PARAM_WIDE_U, -1), (NMF_PARAM_WAVES_V, 3), (NMF_PARAM_WAVES_U, 32),
+                       (NMF_PARAM_WAVES_U, 0), (99, 0)):
         with pytest.raises(NMFError):
             prob.set_param(param, bad)
     prob.close()
