@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="corpora in the batched comparison (0: skip)")
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched comparison (for profiling it); prints its JSON object")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,6 +225,11 @@ def main():
         log(f"generated the {args.batch}-corpus batch ({sum(p['nnz'] for p in batch)} nnz) "
             f"in {time.perf_counter() - t0:.1f}s")
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch_only:
+        if not batch:
+            sys.exit("--batch-only needs --batch > 0")
+        print(json.dumps({"batched": batch_bench(batch, args.batch_iters, args.batch_warmup)}), flush=True)
+        return
     dev = torch.device("cuda:0")
     log(f"generating {args.workload}")
     t0 = time.perf_counter()

@@ -367,9 +367,9 @@ __global__ __launch_bounds__(1024) void k_refine_b(const SelArgs* as, const Bloc
 template <typename T, int KPL>
 hipError_t run(nmf_handle* h, SelArgs& a) {
   const unsigned blocks = static_cast<unsigned>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
-  // a few hundred histogram blocks: enough rows each that the flush of the
-  // block histograms stays small
-  const int64_t want = 2 * static_cast<int64_t>(h->num_cus);
+  // two histogram blocks per compute unit the problem has: enough rows each
+  // that the flush of the block histograms stays small
+  const int64_t want = 2 * static_cast<int64_t>(h->hist_cus);
   a.hist_rows = static_cast<int32_t>(std::max<int64_t>(kRowsPerBlock, (a.rows + want - 1) / want));
   const unsigned hblocks = static_cast<unsigned>((a.rows + a.hist_rows - 1) / a.hist_rows);
   const size_t hbytes = static_cast<size_t>(a.k) * kPadBins * sizeof(uint32_t);

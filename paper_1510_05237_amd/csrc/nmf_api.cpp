@@ -590,6 +590,7 @@ nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int3
     delete h;
     return fail(nullptr, NMF_ERR_DEVICE, "no HIP device");
   }
+  h->hist_cus = h->num_cus;
   carve(h, h->ws, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
   s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)
                   : do_create<float>(h, a_rowptr, a_col, a_val, u0, v0);
@@ -1028,7 +1029,9 @@ nmf_status build_plans(nmf_batch* b, char* tables, size_t table_bytes) {
       h->prof_on = false;
       h->cur_u = slot;
       h->rec = &recs[i];
+      h->hist_cus = h->batch_cus > 0 ? h->batch_cus : h->num_cus;
       nmf_status s = steps_of(h, 1);
+      h->hist_cus = h->num_cus;
       h->rec = nullptr;
       restore_state(h, st);
       if (s != NMF_OK) return batch_fail(b, s, "recording problem " + std::to_string(i) + ": " + h->last_error);
@@ -1211,6 +1214,16 @@ nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t
     off += align_up(w, 256);
   }
   if (s == NMF_OK) {
+    // each problem's histogram pass is sized for its share of the GPU (by
+    // select work, (n + m) k), four times over so that the fused launch
+    // still balances; a problem alone uses every compute unit
+    double total = 0;
+    for (nmf_handle* h : b->h) total += static_cast<double>(h->n + h->m) * h->k;
+    for (nmf_handle* h : b->h) {
+      const double w = static_cast<double>(h->n + h->m) * h->k;
+      const int share = static_cast<int>(std::ceil(4.0 * h->num_cus * w / total));
+      h->batch_cus = std::max(1, std::min(h->num_cus, share));
+    }
     b->tables = base + off;
     b->table_bytes = ws_bytes - off;
     s = build_plans(b, b->tables, b->table_bytes);

@@ -168,6 +168,11 @@ struct nmf_handle {
   hipStream_t stream = nullptr;
   int device = 0;
   int num_cus = 256;
+  // Compute units this problem's histogram pass is sized for: all of them
+  // alone and in a batch's per-problem loop, its share of the GPU in a
+  // batch's fused launches (block counts only; no result depends on it).
+  int hist_cus = 256;
+  int batch_cus = 0;  // that share (0: not in a batch)
   char* ws = nullptr;
   size_t ws_bytes = 0;
 
