@@ -58,7 +58,9 @@ typedef enum {
 enum {
   NMF_MODE_COLUMN = 0, /* t largest per column (Section 4)                    */
   NMF_MODE_NONE = 1,   /* projection only: Algorithm 1                        */
-  NMF_MODE_WHOLE = 2   /* t largest of the whole matrix (Algorithm 2 printed) */
+  NMF_MODE_WHOLE = 2   /* t largest of the whole matrix (Algorithm 2 printed);
+                          ties at the t-th value go to the lowest (row, column)
+                          in row-major order                                  */
 };
 
 /* Arithmetic type of A, U, V and of the sparse products.  The k x k Gram

@@ -22,6 +22,11 @@
 // Only integer atomics are used, so the kept set does not depend on
 // scheduling; the row-compressed factor is then built in row order from the
 // keep masks (k_repack.hip).
+//
+// Whole-matrix form (Algorithm 2 as printed, Section 2): the same passes with
+// one histogram, one threshold and one candidate list for all entries; a
+// candidate's "row" is its row-major flat index r * k + c, so ties at the
+// t-th largest value go to the lowest (row, column) in row-major order.
 #include <algorithm>
 
 #include "nmf_device.h"
@@ -51,16 +56,18 @@ struct SelArgs {
   uint32_t* mask;
   int32_t* ticket;
   int32_t* status;
+  int32_t flat_k;  // whole-matrix form: k (candidates carry r * k + c); 0 per column
 };
 
-template <typename T, int KPL>
+template <typename T, int KPL, bool WHOLE>
 __device__ __forceinline__ void k_hist_body(const SelArgs& a, int blk, int nblk) {
   using KO = KeyOf<T>;
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins]
+  uint32_t* h = reinterpret_cast<uint32_t*>(smem);  // [k][kPadBins] (whole matrix: [1][kPadBins])
   if (*a.status != 0) return;
   const int k = a.k;
-  for (int i = threadIdx.x; i < k * kPadBins; i += 256) h[i] = 0;
+  const int nh = WHOLE ? 1 : k;
+  for (int i = threadIdx.x; i < nh * kPadBins; i += 256) h[i] = 0;
   __syncthreads();
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
@@ -79,24 +86,24 @@ __device__ __forceinline__ void k_hist_body(const SelArgs& a, int blk, int nblk)
         for (int u = 0; u < 4; ++u) key[u] = r + 4 * u < r_end ? KO::key(X[(r + 4 * u) * k + c]) : 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (key[u] != 0) atomicAdd(&h[c * kPadBins + top_digit<T>(key[u])], 1u);
+          if (key[u] != 0) atomicAdd(&h[(WHOLE ? 0 : c * kPadBins) + top_digit<T>(key[u])], 1u);
       }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < k * kBins; i += 256) {
+  for (int i = threadIdx.x; i < nh * kBins; i += 256) {
     const int c = i / kBins, d = i - c * kBins;
     const uint32_t v = h[c * kPadBins + d];
     if (v) atomicAdd(&a.hist[i], v);
   }
 }
-template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_hist(SelArgs a) { k_hist_body<T, KPL>(a, blockIdx.x, gridDim.x); }
-template <typename T, int KPL>
+template <typename T, int KPL, bool WHOLE>
+__global__ __launch_bounds__(256) void k_hist(SelArgs a) { k_hist_body<T, KPL, WHOLE>(a, blockIdx.x, gridDim.x); }
+template <typename T, int KPL, bool WHOLE>
 __global__ __launch_bounds__(256) void k_hist_b(const SelArgs* as, const BlockMap* map) {
   const BlockMap m = map[blockIdx.x];
   const SelArgs a = as[m.prob];
-  k_hist_body<T, KPL>(a, m.blk, m.nblk);
+  k_hist_body<T, KPL, WHOLE>(a, m.blk, m.nblk);
 }
 
 
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(256) void k_pick_b(const SelArgs* as, const BlockMa
 }
 
 
-template <typename T, int KPL>
+template <typename T, int KPL, bool WHOLE>
 __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nblk) {
   using KO = KeyOf<T>;
   using C = Cand<T>;
@@ -153,7 +160,7 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
 #pragma unroll
   for (int q = 0; q < KPL; ++q) {
     const int c = lane + 64 * q;
-    s[q] = c < k ? a.sel[c] : ColSel{0, 0, 1, 0};
+    s[q] = c < k ? a.sel[WHOLE ? 0 : c] : ColSel{0, 0, 1, 0};
   }
   __syncthreads();
   const T* __restrict__ X = static_cast<const T*>(a.X);
@@ -184,11 +191,15 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
           const int d = top_digit<T>(key);
           keep = s[q].all || d > s[q].b1;
           if (!s[q].all && d == s[q].b1) {
-            const int pos = atomicAdd(&lcnt[c], 1);
             C cd;
             cd.key = key;
-            cd.row = static_cast<uint32_t>(r);
-            stage[c * kRowsPerBlock + pos] = cd;
+            if (WHOLE) {
+              cd.row = static_cast<uint32_t>(r * k + c);
+              stage[atomicAdd(&lcnt[0], 1)] = cd;  // one list, up to 64 * k entries per block
+            } else {
+              cd.row = static_cast<uint32_t>(r);
+              stage[c * kRowsPerBlock + atomicAdd(&lcnt[c], 1)] = cd;
+            }
           }
         }
       }
@@ -204,25 +215,31 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
    }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < k; c += 256) {
+  const int nl = WHOLE ? 1 : k;
+  for (int c = threadIdx.x; c < nl; c += 256) {
     const int n = lcnt[c];
     lbase[c] = n ? atomicAdd(&a.cand_cnt[c * kCntStride], n) : 0;
   }
   __syncthreads();
   C* __restrict__ out = static_cast<C*>(a.candA);
+  if (WHOLE) {
+    const int n = lcnt[0];
+    for (int i = threadIdx.x; i < n; i += 256) out[lbase[0] + i] = stage[i];
+    return;
+  }
   for (int c = wv; c < k; c += 4) {
     const int n = lcnt[c];
     for (int i = lane; i < n; i += 64)
       out[static_cast<int64_t>(c) * a.stride + lbase[c] + i] = stage[c * kRowsPerBlock + i];
   }
 }
-template <typename T, int KPL>
-__global__ __launch_bounds__(256) void k_collect(SelArgs a) { k_collect_body<T, KPL>(a, blockIdx.x, gridDim.x); }
-template <typename T, int KPL>
+template <typename T, int KPL, bool WHOLE>
+__global__ __launch_bounds__(256) void k_collect(SelArgs a) { k_collect_body<T, KPL, WHOLE>(a, blockIdx.x, gridDim.x); }
+template <typename T, int KPL, bool WHOLE>
 __global__ __launch_bounds__(256) void k_collect_b(const SelArgs* as, const BlockMap* map) {
   const BlockMap m = map[blockIdx.x];
   const SelArgs a = as[m.prob];
-  k_collect_body<T, KPL>(a, m.blk, m.nblk);
+  k_collect_body<T, KPL, WHOLE>(a, m.blk, m.nblk);
 }
 
 
@@ -243,6 +260,14 @@ __device__ __forceinline__ int cand_digit(const Cand<T>& cd, int kb, int rb, int
 
 __device__ __forceinline__ void mark(uint32_t* mask, int mw, uint32_t row, int c) {
   atomicOr(&mask[static_cast<int64_t>(row) * mw + (c >> 5)], 1u << (c & 31));
+}
+
+// Keep a refined candidate of list c (whole-matrix form: decode its flat index).
+__device__ __forceinline__ void mark_cand(const SelArgs& a, uint32_t row, int c) {
+  if (a.flat_k > 0)
+    mark(a.mask, a.mw, row / static_cast<uint32_t>(a.flat_k), static_cast<int>(row % static_cast<uint32_t>(a.flat_k)));
+  else
+    mark(a.mask, a.mw, row, c);
 }
 
 template <typename T>
@@ -308,7 +333,7 @@ __device__ __forceinline__ void k_refine_body(const SelArgs& a, int blk, int nbl
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (d[u] > bin) mark(a.mask, a.mw, cd[u].row, c);
+        if (d[u] > bin) mark_cand(a, cd[u].row, c);
         // one LDS atomic per wave for the equal-digit entries
         const uint64_t eq = __ballot(d[u] == bin);
         int base = 0;
@@ -350,7 +375,7 @@ __device__ __forceinline__ void k_refine_body(const SelArgs& a, int blk, int nbl
       o.row = __shfl(me.row, j, 64);
       rank += cand_before<T>(o, me) ? 1 : 0;
     }
-    if (tid < n && rank < need) mark(a.mask, a.mw, me.row, c);
+    if (tid < n && rank < need) mark_cand(a, me.row, c);
     if (tid == 0) *cnt_ptr = 0;
   }
 }
@@ -364,7 +389,7 @@ __global__ __launch_bounds__(1024) void k_refine_b(const SelArgs* as, const Bloc
 }
 
 
-template <typename T, int KPL>
+template <typename T, int KPL, bool WHOLE>
 hipError_t run(nmf_handle* h, SelArgs& a) {
   const unsigned blocks = static_cast<unsigned>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
   // two histogram blocks per compute unit the problem has: enough rows each
@@ -372,13 +397,21 @@ hipError_t run(nmf_handle* h, SelArgs& a) {
   const int64_t want = 2 * static_cast<int64_t>(h->hist_cus);
   a.hist_rows = static_cast<int32_t>(std::max<int64_t>(kRowsPerBlock, (a.rows + want - 1) / want));
   const unsigned hblocks = static_cast<unsigned>((a.rows + a.hist_rows - 1) / a.hist_rows);
-  const size_t hbytes = static_cast<size_t>(a.k) * kPadBins * sizeof(uint32_t);
+  const size_t hbytes = static_cast<size_t>(WHOLE ? 1 : a.k) * kPadBins * sizeof(uint32_t);
   const size_t stage = static_cast<size_t>(a.k) * kRowsPerBlock * sizeof(Cand<T>);
   hipError_t e;
-  if ((e = launch_rec(h, k_hist<T, KPL>, k_hist_b<T, KPL>, hblocks, 256, hbytes, a)) != hipSuccess) return e;
-  if ((e = launch_rec(h, k_pick, k_pick_b, (a.k + 3) / 4, 256, 0, a)) != hipSuccess) return e;
-  if ((e = launch_rec(h, k_collect<T, KPL>, k_collect_b<T, KPL>, blocks, 256, stage, a)) != hipSuccess) return e;
-  return launch_rec(h, k_refine<T>, k_refine_b<T>, a.k, 1024, 0, a);
+  // the whole-matrix form picks and refines one list: k = 1 for those passes
+  SelArgs one = a;
+  if (WHOLE) {
+    one.k = 1;
+    one.flat_k = a.k;
+  }
+  if ((e = launch_rec(h, k_hist<T, KPL, WHOLE>, k_hist_b<T, KPL, WHOLE>, hblocks, 256, hbytes, a)) != hipSuccess)
+    return e;
+  if ((e = launch_rec(h, k_pick, k_pick_b, (one.k + 3) / 4, 256, 0, one)) != hipSuccess) return e;
+  if ((e = launch_rec(h, k_collect<T, KPL, WHOLE>, k_collect_b<T, KPL, WHOLE>, blocks, 256, stage, a)) != hipSuccess)
+    return e;
+  return launch_rec(h, k_refine<T>, k_refine_b<T>, one.k, 1024, 0, one);
 }
 
 }  // namespace
@@ -403,7 +436,12 @@ hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int m
   a.mask = h->sel.mask;
   a.ticket = h->sel.ticket;
   a.status = h->status;
-  return h->k > 64 ? run<T, 2>(h, a) : run<T, 1>(h, a);
+  a.flat_k = 0;
+  if (mode == NMF_MODE_WHOLE) {
+    a.stride = h->sel.cand_stride * h->k;  // the one list may use every list's room
+    return h->k > 64 ? run<T, 2, true>(h, a) : run<T, 1, true>(h, a);
+  }
+  return h->k > 64 ? run<T, 2, false>(h, a) : run<T, 1, false>(h, a);
 }
 
 // Keep every nonzero entry (used to load given factors).

@@ -220,7 +220,7 @@ nmf_status check_config(const nmf_config* c) {
   if (c->k > kMaxK) return fail(nullptr, NMF_ERR_UNSUPPORTED, "k must be <= 128");
   if (c->k > c->n || c->k > c->m) return fail(nullptr, NMF_ERR_INVALID_ARG, "k must be <= min(n, m)");
   if (c->t_u < 1 || c->t_v < 1) return fail(nullptr, NMF_ERR_INVALID_ARG, "t_u and t_v must be >= 1");
-  if (c->mode != NMF_MODE_COLUMN && c->mode != NMF_MODE_NONE)
+  if (c->mode != NMF_MODE_COLUMN && c->mode != NMF_MODE_NONE && c->mode != NMF_MODE_WHOLE)
     return fail(nullptr, NMF_ERR_UNSUPPORTED, "mode not supported");
   if (c->dtype != NMF_F32 && c->dtype != NMF_F64) return fail(nullptr, NMF_ERR_UNSUPPORTED, "dtype");
   // int32 element offsets into the k-wide matrices, and 32-bit byte offsets

@@ -6,7 +6,8 @@ A factor from the GPU and one from the oracle are compared in two parts:
 * supports: every entry kept by one side only is a mismatch.  It is a
   near-tie when its pre-selection value lies within ``tol * theta_c`` of the
   oracle's threshold theta_c of that column (the smallest value the oracle
-  keeps there); otherwise it is a non-tie mismatch.
+  keeps there; for the whole-matrix rule, the smallest it keeps anywhere);
+  otherwise it is a non-tie mismatch.
 """
 
 from __future__ import annotations
@@ -27,7 +28,10 @@ class FactorDiff:
         return self.rel <= tol and self.non_ties == 0
 
 
-def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol: float = 1e-4) -> FactorDiff:
+def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol: float = 1e-4,
+                   whole: bool = False) -> FactorDiff:
+    """``whole``: the factors come from the whole-matrix rule, whose one
+    threshold is the smallest value the oracle keeps anywhere."""
     X_gpu = np.asarray(X_gpu, np.float64)
     X_or = np.asarray(X_or, np.float64)
     Xpre = np.where(np.asarray(Xpre_or, np.float64) > 0, Xpre_or, 0.0)
@@ -37,9 +41,10 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
     rel = float(np.linalg.norm(X_gpu[both] - X_or[both]) / den) if den > 0 else float(np.linalg.norm(X_gpu))
     mism = kg != ko
     near = non = 0
+    theta_all = X_or[ko].min() if ko.any() else 0.0
     for c in np.nonzero(mism.any(axis=0))[0]:
         kept = X_or[ko[:, c], c]
-        theta = kept.min() if kept.size else 0.0
+        theta = theta_all if whole else (kept.min() if kept.size else 0.0)
         for r in np.nonzero(mism[:, c])[0]:
             v = Xpre[r, c]
             if abs(v - theta) <= tol * max(theta, 1e-300):

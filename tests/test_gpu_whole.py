@@ -1,0 +1,140 @@
+"""GPU parity of the whole-matrix rule (Algorithm 2 as printed: the t largest
+entries of the whole factor survive; ties at the t-th value go to the lowest
+(row, column) in row-major order) against the FP64 oracle.  Every test prints
+its case before touching the GPU."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from tests.parity import compare_factor, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_05237_amd import NMF, NMFBatch
+
+    return NMF, NMFBatch
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def test_whole_fp64_trajectory():
+    """10 iterations of the 2000 x 1000 FP64 workload under the whole-matrix
+    rule (t_u = 1500, t_v = 700 entries in all): every iterate and the E and R
+    curves match the oracle; the supports are identical."""
+    NMF, _ = _lib()
+    c, u0, _, p = synth.make_workload("plain_f64_2000x1000")
+    A = c.scipy()
+    t_u, t_v = 1500, 700
+    _say(f"fp64 whole-matrix 2000x1000 nnz={c.nnz} k={p['k']} t_u={t_u} t_v={t_v}, 10 iterations")
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=t_u, t_v=t_v, dtype="f64", mode="whole")
+    st = None
+    for it in range(10):
+        prob.step(1)
+        st = oracle.als(A, u0, t_u, t_v, 1, mode="whole", state=st)
+        U, V = prob.factors()
+        assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9, it
+        np.testing.assert_array_equal(U != 0, st.U != 0)
+        np.testing.assert_array_equal(V != 0, st.V != 0)
+        assert np.count_nonzero(U) <= t_u and np.count_nonzero(V) <= t_v
+    E, R, nu, nv = prob.history()
+    np.testing.assert_allclose(E, st.E, rtol=1e-9)
+    np.testing.assert_allclose(R, st.R, rtol=1e-8)
+    np.testing.assert_array_equal(nu, st.nnz_u)
+    np.testing.assert_array_equal(nv, st.nnz_v)
+    prob.close()
+
+
+@pytest.mark.parametrize("k", [16, 80])
+def test_whole_fp32_teacher_forced(k):
+    """FP32 half-steps from the oracle's states: pre-selection matrices to
+    1e-4, supports equal up to near-ties at the one global threshold."""
+    NMF, _ = _lib()
+    c = synth.make_corpus(3000, 5000, seed=61 + k, alpha=1.1, per_doc=40, dtype="f32")
+    u0, _ = synth.make_init(3000, 5000, k, seed=61 + k, dtype="f32")
+    t_u, t_v = 60 * k, 90 * k
+    _say(f"fp32 whole-matrix teacher-forced 3000x5000 nnz={c.nnz} k={k} t_u={t_u} t_v={t_v}")
+    st = oracle.als(c.scipy(), u0, t_u, t_v, 3, mode="whole", keep_steps=True)
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=t_u, t_v=t_v, dtype="f32", mode="whole")
+    for i, s in enumerate(st.steps):
+        prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32))
+        prob.half_step(0)
+        assert rel_fro(prob.pre(0), oracle.clamp(s["V_pre"])) <= 1e-4, ("V_pre", i)
+        _, V = prob.factors()
+        dv = compare_factor(V, s["V"], s["V_pre"], 1e-4, whole=True)
+        prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32), v=np.ascontiguousarray(s["V"], np.float32))
+        prob.half_step(1)
+        assert rel_fro(prob.pre(1), oracle.clamp(s["U_pre"])) <= 1e-4, ("U_pre", i)
+        U, _ = prob.factors()
+        du = compare_factor(U, s["U"], s["U_pre"], 1e-4, whole=True)
+        _say(f"  iter {i}: V rel {dv.rel:.2e} mism {dv.mismatches} (near-tie {dv.near_ties}) | "
+             f"U rel {du.rel:.2e} mism {du.mismatches} (near-tie {du.near_ties})")
+        assert dv.ok(1e-4) and du.ok(1e-4), (i, dv, du)
+        assert np.count_nonzero(V) == min(t_v, np.count_nonzero(oracle.clamp(s["V_pre"])))
+        assert np.count_nonzero(U) == min(t_u, np.count_nonzero(oracle.clamp(s["U_pre"])))
+    prob.close()
+
+
+def test_whole_forced_ties_lowest_index_wins():
+    """Duplicated documents give identical rows of V_pre; with t cutting
+    through those ties the kept set must be the oracle's exactly (lowest
+    row-major index first)."""
+    NMF, _ = _lib()
+    rng = np.random.default_rng(11)
+    n, m_base, k = 300, 200, 4
+    base = sp.random(n, m_base, density=0.05, random_state=rng, format="csc",
+                     data_rvs=lambda s: rng.uniform(0.1, 2.0, s)).toarray()
+    cols = list(range(m_base)) + [5] * 40 + [17] * 40
+    perm = rng.permutation(len(cols))
+    A = sp.csr_matrix(base[:, [cols[p] for p in perm]])
+    A.sort_indices()
+    u0 = rng.uniform(0.1, 1.0, (n, k))
+    Vpre = oracle.clamp(oracle.half_step(sp.csr_matrix(A.T), u0, 10**9, mode="none")[0])
+    for t_v in (50, 140, 320):
+        _say(f"fp64 whole-matrix forced ties: 80 duplicated documents, t_v={t_v}")
+        prob = NMF(n, A.shape[1], A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                   A.data.astype(np.float64), u0, t_u=40, t_v=t_v, dtype="f64", mode="whole")
+        prob.half_step(0)
+        _, V = prob.factors()
+        Vo, _ = oracle.half_step(sp.csr_matrix(A.T), u0, t_v, mode="whole")
+        np.testing.assert_array_equal(V != 0, Vo != 0)
+        np.testing.assert_allclose(V, Vo, rtol=1e-10, atol=1e-14)
+        prob.close()
+    # the cut really falls inside a run of equal values for at least one t
+    vals = np.sort(Vpre[Vpre > 0])[::-1]
+    assert all(vals[t - 1] == vals[t] for t in (140, 320))
+
+
+def test_whole_batch_matches_alone():
+    """A batch in the whole-matrix mode gives bitwise the per-problem iterates."""
+    NMF, NMFBatch = _lib()
+    probs = []
+    for n, m, nnz, k, seed in ((700, 500, 9000, 12, 7101), (2600, 1200, 60000, 33, 7102), (1100, 800, 30000, 80, 7103)):
+        c = synth.make_corpus(n, m, seed=seed, alpha=1.1, nnz=nnz, dtype="f32")
+        u0, _ = synth.make_init(n, m, k, seed=seed, dtype="f32")
+        probs.append(dict(n=n, m=m, k=k, t_u=n * k // 25, t_v=m * k // 25, indptr=c.indptr, indices=c.indices,
+                          data=c.data, u0=u0))
+    _say("batch f32 whole-matrix: 3 problems, 4 fused_graph iterations vs alone")
+    b = NMFBatch(probs, dtype="f32", mode="whole")
+    b.step(4, "fused_graph")
+    for i, p in enumerate(probs):
+        s = NMF(p["n"], p["m"], p["indptr"], p["indices"], p["data"], p["u0"], t_u=p["t_u"], t_v=p["t_v"],
+                dtype="f32", mode="whole")
+        s.step(4)
+        U, V = s.factors()
+        Ub, Vb = b.problem(i).factors()
+        np.testing.assert_array_equal(Ub, U)
+        np.testing.assert_array_equal(Vb, V)
+        assert np.count_nonzero(U) <= p["t_u"]
+        s.close()
+    b.close()
