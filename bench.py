@@ -173,6 +173,50 @@ def batch_bench(problems, iters: int, warmup: int):
     }
 
 
+def sweep_maxnnz(iters: int = 50):
+    """Storage of enforced sparsity against the dense baseline (Section 3.2):
+    on a PubMed-sized stand-in (20 112 terms x 7 510 docs, 0.4 % density,
+    k = 5), the largest number of nonzeros of U and V stored at any half-step
+    end, and the final E, for column-wise enforcement at several t and initial
+    guesses U0 with several numbers of nonzeros per column; and Algorithm 1
+    (dense) with the rule applied once after its last iteration."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1510_05237_amd import NMF
+
+    n, m, k = 20112, 7510, 5
+    c = synth.make_corpus(n, m, seed=7, alpha=1.1, nnz=int(round(0.004 * n * m)), dtype="f32")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(c.indptr).to(dev)
+    ci = torch.from_numpy(c.indices).to(dev)
+    cv = torch.from_numpy(c.data).to(dev)
+    ts = [10, 30, 100, 300, 1000, 3000]
+    rows = []
+    for p0 in [20, 200, 2000, n]:
+        rng = np.random.Generator(np.random.PCG64(1000 + p0))
+        u0 = synth.sparse_factor_init(n, k, p0, rng=rng, dtype="f32")
+        for t in ts:
+            h = NMF(n, m, rp, ci, cv, torch.from_numpy(u0).to(dev), t_u=t, t_v=t, dtype="f32", device=dev)
+            h.step(iters)
+            rows.append(dict(u0_nnz_per_col=p0, t=t, rule="during", max_nnz=h.max_nnz(), E=h.error()))
+            h.close()
+        log(f"sweep: U0 with {p0} nonzeros per column done")
+    u0, _ = synth.make_init(n, m, k, seed=7, dtype="f32")
+    dense = []
+    for t in ts:
+        h = NMF(n, m, rp, ci, cv, torch.from_numpy(u0).to(dev), t_u=1, t_v=1, dtype="f32", device=dev,
+                mode="none")
+        h.step(iters)
+        E_dense, mx = h.error(), h.max_nnz()
+        h.enforce(t, t)
+        dense.append(dict(t=t, rule="after", max_nnz=mx, E_dense=E_dense, E=h.error()))
+        h.close()
+    return {"workload": f"pubmed_like_{n}x{m}", "nnz": c.nnz, "k": k, "iters": iters,
+            "enforced_during": rows, "dense_then_enforced": dense}
+
+
 def copy_calibration(gib: float = 1.0, reps: int = 5):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     import torch
@@ -198,6 +242,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="corpora in the batched comparison (0: skip)")
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--sweep-maxnnz", action="store_true",
+                    help="print the max-NNZ sweep (enforced sparsity against dense ALS) and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched comparison (for profiling it); prints its JSON object")
     args = ap.parse_args()
@@ -208,6 +254,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep_maxnnz:
+        print(json.dumps({"maxnnz_sweep": sweep_maxnnz()}), flush=True)
         return
 
     import numpy as np

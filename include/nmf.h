@@ -225,6 +225,16 @@ enum {
  * Errors: INVALID_ARG for an unknown parameter or a value out of range. */
 nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value);
 
+/* Apply the top-t rule once to the current U (t_u) and V (t_v): mode
+ * NMF_MODE_COLUMN per column (Section 4), NMF_MODE_WHOLE over the whole
+ * factor (Section 2), with the tie-breaks of the iteration; their Gram
+ * matrices are rebuilt.  With a handle in NMF_MODE_NONE this is the
+ * "enforce sparsity after ALS" of Section 3.2 (Algorithm 1 to the end, then
+ * one top-t).  Later iterations continue from the sparsified factors under
+ * the handle's own mode.  The next nmf_error computes E of the new factors.
+ * Synchronizes.  Errors: INVALID_ARG, STATE (no V yet), NOT_SPD, DEVICE. */
+nmf_status nmf_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v);
+
 /* Read a tuning parameter into *value.  Errors: INVALID_ARG. */
 nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value);
 

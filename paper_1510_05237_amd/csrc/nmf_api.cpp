@@ -539,6 +539,29 @@ nmf_status do_error(nmf_handle* h, double* E) {
   return NMF_OK;
 }
 
+// The top-t rule applied once to the current U and V (their dense forms go
+// through the select and the repack of an iteration), then their Gram
+// matrices and inverses are rebuilt.
+template <typename T>
+nmf_status do_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v) {
+  if (!h->have_v) return fail(h, NMF_ERR_STATE, "no V yet: take a step or pass v0");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  Factor& U = h->U[h->cur_u];
+  T* xu = static_cast<T*>(h->lossC);  // n x k scratch
+  T* xv = static_cast<T*>(h->lossB);  // m x k scratch
+  HIPCHK(h, densify<T>(h, U, xu));
+  HIPCHK(h, select_topt<T>(h, xu, h->n, t_u, mode, U));
+  HIPCHK(h, repack<T>(h, xu, h->n, U, sparse_row_of(h, U)));
+  HIPCHK(h, densify<T>(h, h->V, xv));
+  HIPCHK(h, select_topt<T>(h, xv, h->m, t_v, mode, h->V));
+  HIPCHK(h, repack<T>(h, xv, h->m, h->V, sparse_row_of(h, h->V)));
+  HIPCHK(h, gram<T>(h, U, h->gU));
+  HIPCHK(h, gram<T>(h, h->V, h->gV));
+  h->metrics_valid = false;
+  return sync_status(h);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -818,6 +841,14 @@ nmf_status reload_meta(nmf_handle* h, int which) {
     HIPCHK(h, repack<float>(h, static_cast<float*>(stage), F.rows, F, sparse_row_of(h, F)));
   }
   return sync_status(h);
+}
+
+nmf_status nmf_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  if (mode != NMF_MODE_COLUMN && mode != NMF_MODE_WHOLE)
+    return fail(h, NMF_ERR_INVALID_ARG, "mode must be NMF_MODE_COLUMN or NMF_MODE_WHOLE");
+  if (t_u < 1 || t_v < 1) return fail(h, NMF_ERR_INVALID_ARG, "t_u and t_v must be >= 1");
+  return h->elt == 8 ? do_enforce<double>(h, mode, t_u, t_v) : do_enforce<float>(h, mode, t_u, t_v);
 }
 
 nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value) {

@@ -101,6 +101,7 @@ SIGNATURES = {
     "nmf_batch_set_param": (_I32, [_P, _I32, _I32, ctypes.c_int64]),
     "nmf_batch_tune": (_I32, [_P, _I32, _P]),
     "nmf_get_param": (_I32, [_P, _I32, _P]),
+    "nmf_enforce": (_I32, [_P, _I32, _I64, _I64]),
     "nmf_batch_errors": (_I32, [_P, _P, _P]),
     "nmf_batch_problem": (_P, [_P, _I32]),
     "nmf_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -248,6 +249,10 @@ NMF_PARAM_WAVES_U = 5
 
 def nmf_set_param(h: int, param: int, value: int):
     _check(load_library().nmf_set_param(h, param, value), h)
+
+
+def nmf_enforce(h: int, mode: int, t_u: int, t_v: int):
+    _check(load_library().nmf_enforce(h, mode, t_u, t_v), h)
 
 
 def nmf_get_param(h: int, param: int) -> int:
@@ -429,6 +434,10 @@ class NMF:
 
     def get_param(self, param: int) -> int:
         return nmf_get_param(self.h, param)
+
+    def enforce(self, t_u: int, t_v: int, mode: str = "column"):
+        """Apply the top-t rule once to the current U and V."""
+        nmf_enforce(self.h, _MODES[mode], t_u, t_v)
 
     def profile(self, enable: bool):
         nmf_profile(self.h, enable)
