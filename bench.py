@@ -217,6 +217,40 @@ def sweep_maxnnz(iters: int = 50):
             "enforced_during": rows, "dense_then_enforced": dense}
 
 
+def sweep_accuracy(iters: int = 50):
+    """Clustering accuracy of Eq. (acc) against sparsity (Section 3.2) on a
+    PubMed-shaped corpus with planted labels (20 112 terms x 7 510 docs,
+    5 journals, 80 distinct terms per doc, k = 5): the mean over topics for
+    t per column enforced on U and V, on U only, on V only, and for dense
+    Algorithm 1 with the rule applied once afterwards."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1510_05237_amd import NMF
+
+    n, m, k, n_j = 20112, 7510, 5, 5
+    c, labels = synth.make_labeled_corpus(n, m, n_j, 80, seed=9, dtype="f32")
+    u0, _ = synth.make_init(n, m, k, seed=9, dtype="f32")
+    dev = torch.device("cuda:0")
+    args = [torch.from_numpy(x).to(dev) for x in (c.indptr, c.indices, c.data, u0)]
+    lab = torch.from_numpy(labels).to(dev)
+    rows = []
+    for t in [10, 30, 100, 300, 1000, 3000]:
+        res = dict(t=t)
+        for name, tu, tv, mode in (("both", t, t, "column"), ("u_only", t, m, "column"),
+                                   ("v_only", n, t, "column"), ("after", 1, 1, "none")):
+            h = NMF(n, m, *args, t_u=tu, t_v=tv, dtype="f32", device=dev, mode=mode)
+            h.step(iters)
+            if name == "after":
+                h.enforce(t, t)
+            res[name] = float(np.mean(h.topic_accuracy(lab, n_j)))
+            h.close()
+        rows.append(res)
+        log(f"accuracy sweep: t={t} {res}")
+    return {"workload": f"planted_{n}x{m}_{n_j}_journals", "nnz": c.nnz, "k": k, "iters": iters, "rows": rows}
+
+
 def copy_calibration(gib: float = 1.0, reps: int = 5):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     import torch
@@ -244,6 +278,8 @@ def main():
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--sweep-maxnnz", action="store_true",
                     help="print the max-NNZ sweep (enforced sparsity against dense ALS) and exit")
+    ap.add_argument("--sweep-accuracy", action="store_true",
+                    help="print the clustering-accuracy sweep (Eq. (acc) against t) and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched comparison (for profiling it); prints its JSON object")
     args = ap.parse_args()
@@ -254,6 +290,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.sweep_accuracy:
+        print(json.dumps({"accuracy_sweep": sweep_accuracy()}), flush=True)
         return
     if args.sweep_maxnnz:
         print(json.dumps({"maxnnz_sweep": sweep_maxnnz()}), flush=True)

@@ -235,6 +235,14 @@ nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value);
  * Synchronizes.  Errors: INVALID_ARG, STATE (no V yet), NOT_SPD, DEVICE. */
 nmf_status nmf_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v);
 
+/* Documents per topic and label, for the clustering accuracy of Eq. (acc)
+ * (Section 3.2): counts[c * n_labels + l] (k x n_labels, host) = the number
+ * of documents with labels[d] == l that store an entry in column c of V (a
+ * document belongs to a topic when that entry is nonzero).  labels: m
+ * int32 in [0, n_labels) (others are skipped), host or device;
+ * 1 <= n_labels <= 256.  Synchronizes.  Errors: INVALID_ARG, STATE (no V). */
+nmf_status nmf_topic_counts(nmf_handle* h, const int32_t* labels, int32_t n_labels, int64_t* counts);
+
 /* Read a tuning parameter into *value.  Errors: INVALID_ARG. */
 nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value);
 

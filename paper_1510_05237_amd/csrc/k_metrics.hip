@@ -316,6 +316,18 @@ __global__ __launch_bounds__(256) void k_sumsq(const T* x, int64_t count, double
   if (threadIdx.x == 0) partials[blockIdx.x] = tot[0];
 }
 
+// Documents per (topic, label) for the clustering accuracy of Eq. (acc):
+// a document belongs to every topic with a stored entry in its row of V.
+// Thread = document; integer atomics, so the counts are exact.
+__global__ void k_topic_counts(const int32_t* row_ptr, const uint8_t* topic, const int32_t* labels, int64_t rows,
+                               int32_t n_labels, uint32_t* counts) {
+  const int64_t d = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (d >= rows) return;
+  const int32_t lab = labels[d];
+  if (lab < 0 || lab >= n_labels) return;
+  for (int32_t e = row_ptr[d]; e < row_ptr[d + 1]; ++e) atomicAdd(&counts[topic[e] * n_labels + lab], 1u);
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t count) {
   const int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t st = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -412,6 +424,13 @@ hipError_t sum_squares(nmf_handle* h, const T* x, int64_t count, double* out) {
   hipLaunchKernelGGL((k_sumsq<T>), dim3(kMetricBlocks), dim3(256), 0, h->stream, x, count, h->met.loss_parts);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, h->stream, h->met.loss_parts, kMetricBlocks, nullptr,
                      nullptr, 0, nullptr, out);
+  return hipGetLastError();
+}
+
+hipError_t topic_counts(nmf_handle* h, const Factor& F, const int32_t* labels, int32_t n_labels, uint32_t* counts) {
+  const unsigned blocks = static_cast<unsigned>((F.rows + 255) / 256);
+  hipLaunchKernelGGL(k_topic_counts, dim3(blocks), dim3(256), 0, h->stream, F.row_ptr, F.topic, labels, F.rows,
+                     n_labels, counts);
   return hipGetLastError();
 }
 

@@ -851,6 +851,30 @@ nmf_status nmf_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v) {
   return h->elt == 8 ? do_enforce<double>(h, mode, t_u, t_v) : do_enforce<float>(h, mode, t_u, t_v);
 }
 
+nmf_status nmf_topic_counts(nmf_handle* h, const int32_t* labels, int32_t n_labels, int64_t* counts) {
+  if (h == nullptr || labels == nullptr || counts == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  if (n_labels < 1 || n_labels > kBins) return fail(h, NMF_ERR_INVALID_ARG, "n_labels must be in 1..256");
+  if (!h->have_v) return fail(h, NMF_ERR_STATE, "no V yet");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  // scratch: the labels in the m x k pre-selection area of the loss, the
+  // counts in the select's histogram (k x 256 words, zero between selects)
+  const int32_t* lab = labels;
+  if (!is_device_ptr(labels)) {
+    s = copy_sync(h, h->lossB, labels, static_cast<size_t>(h->m) * sizeof(int32_t));
+    if (s != NMF_OK) return s;
+    lab = static_cast<const int32_t*>(h->lossB);
+  }
+  const size_t n = static_cast<size_t>(h->k) * n_labels;
+  HIPCHK(h, topic_counts(h, h->V, lab, n_labels, h->sel.hist));
+  std::vector<uint32_t> c(n);
+  HIPCHK(h, hipMemcpyAsync(c.data(), h->sel.hist, n * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, fill_i32(h->stream, reinterpret_cast<int32_t*>(h->sel.hist), 0, static_cast<int64_t>(n)));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (size_t i = 0; i < n; ++i) counts[i] = c[i];
+  return NMF_OK;
+}
+
 nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value) {
   if (h == nullptr || value == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
   switch (param) {

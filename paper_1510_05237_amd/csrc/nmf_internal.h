@@ -251,5 +251,7 @@ template <typename T>
 hipError_t grad_combine(nmf_handle* h, const T* F, const T* B, const double* G,
                         const double* g_scale, int64_t rows, T* out);
 hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t count);
+// counts[c * n_labels + l] += documents with label l storing an entry in topic c
+hipError_t topic_counts(nmf_handle* h, const Factor& F, const int32_t* labels, int32_t n_labels, uint32_t* counts);
 
 }  // namespace nmfk

@@ -102,6 +102,7 @@ SIGNATURES = {
     "nmf_batch_tune": (_I32, [_P, _I32, _P]),
     "nmf_get_param": (_I32, [_P, _I32, _P]),
     "nmf_enforce": (_I32, [_P, _I32, _I64, _I64]),
+    "nmf_topic_counts": (_I32, [_P, _P, _I32, _P]),
     "nmf_batch_errors": (_I32, [_P, _P, _P]),
     "nmf_batch_problem": (_P, [_P, _I32]),
     "nmf_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -253,6 +254,13 @@ def nmf_set_param(h: int, param: int, value: int):
 
 def nmf_enforce(h: int, mode: int, t_u: int, t_v: int):
     _check(load_library().nmf_enforce(h, mode, t_u, t_v), h)
+
+
+def nmf_topic_counts(h: int, labels, n_labels: int, k: int) -> np.ndarray:
+    lab = labels if not isinstance(labels, np.ndarray) else np.ascontiguousarray(labels, np.int32)
+    out = np.zeros(k * n_labels, np.int64)
+    _check(load_library().nmf_topic_counts(h, _ptr(lab), n_labels, _ptr(out)), h)
+    return out.reshape(k, n_labels)
 
 
 def nmf_get_param(h: int, param: int) -> int:
@@ -434,6 +442,16 @@ class NMF:
 
     def get_param(self, param: int) -> int:
         return nmf_get_param(self.h, param)
+
+    def topic_counts(self, labels, n_labels: int) -> np.ndarray:
+        """k x n_labels: documents of each label with an entry in each column of V."""
+        return nmf_topic_counts(self.h, labels, n_labels, self.k)
+
+    def topic_accuracy(self, labels, n_journals: int) -> np.ndarray:
+        """Eq. (acc) of every topic for documents labelled by journal."""
+        from .accuracy import accuracy_from_counts
+
+        return accuracy_from_counts(self.topic_counts(labels, n_journals), n_journals)
 
     def enforce(self, t_u: int, t_v: int, mode: str = "column"):
         """Apply the top-t rule once to the current U and V."""

@@ -8,6 +8,7 @@ from .corpus import (  # noqa: F401
     Corpus,
     WORKLOADS,
     make_corpus,
+    make_labeled_corpus,
     make_init,
     make_workload,
     zipf_terms,

@@ -217,6 +217,51 @@ def make_corpus(n: int, m: int, *, seed: int, alpha: float, dtype: str = "f64",
                   meta=dict(seed=seed, alpha=alpha, nnz=nnz, per_doc=per_doc))
 
 
+def make_labeled_corpus(n: int, m: int, n_j: int, per_doc: int, *, seed: int, alpha: float = 1.1,
+                        share: float = 0.3, dtype: str = "f64"):
+    """A corpus with planted document labels ("journals"), for the clustering
+    accuracy of Eq. (acc): (Corpus, labels int32[m]).
+
+    Documents are dealt to the n_j journals evenly (seeded shuffle).  Each
+    journal ranks the vocabulary by its own seeded permutation, and so does a
+    background shared by all; every draw of a document's terms comes from its
+    journal's Zipf ranking, or with probability ``share`` from the
+    background's.  A document keeps its first ``per_doc`` distinct terms;
+    values are lognormal counts scaled by the smoothed IDF as in
+    ``make_corpus``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    labels = rng.permutation(np.arange(m) % n_j).astype(np.int32)
+    w = np.arange(1, n + 1, dtype=np.float64) ** (-float(alpha))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    perms = np.stack([rng.permutation(n) for _ in range(n_j + 1)]).astype(np.int64)  # row 0: background
+    width = 2 * per_doc + 64
+    parts = []
+    for j0 in range(0, m, _PER_DOC_CHUNK):
+        c = min(_PER_DOC_CHUNK, m - j0)
+        ranks = np.minimum(np.searchsorted(cdf, rng.random((c, width)), side="right"), n - 1)
+        src = np.where(rng.random((c, width)) < share, 0, 1 + labels[j0:j0 + c, None].astype(np.int64))
+        terms = _first_distinct(perms[src, ranks], per_doc)
+        if np.any(terms[:, -1] < 0):
+            raise ValueError("per_doc too large for the vocabulary and draw width")
+        docs = np.arange(j0, j0 + c, dtype=np.int64)[:, None]
+        parts.append((terms * m + docs).ravel())
+    keys = np.concatenate(parts)
+    keys.sort()
+    rows = keys // m
+    cols = (keys - rows * m).astype(np.int32)
+    counts_per_row = np.bincount(rows, minlength=n).astype(np.int64)
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts_per_row, out=indptr[1:])
+    counts = rng.lognormal(0.0, 1.0, size=cols.size)
+    idf = np.log((1.0 + m) / (1.0 + counts_per_row.astype(np.float64))) + 1.0
+    data = counts * np.repeat(idf, counts_per_row)
+    data = data.astype(np.float32) if dtype == "f32" else data
+    corpus = Corpus(n, m, indptr, cols, data, dtype,
+                    meta=dict(seed=seed, alpha=alpha, per_doc=per_doc, n_j=n_j, share=share))
+    return corpus, labels
+
+
 def make_init(n: int, m: int, k: int, *, seed: int, dtype: str = "f64"):
     """U0 = U[0,1)^{n x k}, then V0 = U[0,1)^{m x k}, from PCG64(seed + 1000)."""
     rng = np.random.Generator(np.random.PCG64(seed + 1000))

@@ -77,3 +77,35 @@ def test_enforce_then_continue_column_mode():
     U, V = prob.factors()
     assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9
     prob.close()
+
+
+def test_topic_counts_and_accuracy():
+    """Eq. (acc) on a corpus with planted journal labels: the GPU's per-topic
+    journal counts equal a count over its own V, and the accuracy equals the
+    oracle's on the oracle's factors (FP64: identical supports)."""
+    NMF, NMFError = _lib()
+    import torch
+
+    from paper_1510_05237_amd import accuracy_from_counts
+
+    c, labels = synth.make_labeled_corpus(3000, 1500, 4, 40, seed=83, dtype="f64")
+    u0, _ = synth.make_init(3000, 1500, 4, seed=83, dtype="f64")
+    _say("fp64 planted labels 3000x1500, 4 journals, k=4, 8 iterations, Eq. (acc)")
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=150, t_v=200, dtype="f64")
+    prob.step(8)
+    counts = prob.topic_counts(labels, 4)
+    _, V = prob.factors()
+    want = np.stack([np.bincount(labels[V[:, t] != 0], minlength=4) for t in range(4)])
+    np.testing.assert_array_equal(counts, want)
+    counts_dev = prob.topic_counts(torch.from_numpy(labels).to("cuda:0"), 4)
+    np.testing.assert_array_equal(counts_dev, want)
+    acc = accuracy_from_counts(counts, 4)
+    st = oracle.als(c.scipy(), u0, 150, 200, 8)
+    acc_or = [oracle.topic_accuracy(labels[st.V[:, t] != 0], 4) for t in range(4)]
+    np.testing.assert_allclose(acc, acc_or, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(prob.topic_accuracy(labels, 4), acc)
+    with pytest.raises(NMFError):
+        prob.topic_counts(labels, 0)
+    with pytest.raises(NMFError):
+        prob.topic_counts(labels, 257)
+    prob.close()
