@@ -24,3 +24,4 @@ from .als import (  # noqa: F401
     topt_whole,
 )
 from .accuracy import topic_accuracy, alpha_beta  # noqa: F401
+from .sequential import deflated_half_step, sequential_als  # noqa: F401

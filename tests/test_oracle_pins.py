@@ -400,3 +400,74 @@ def test_accuracy_extremes():
     assert oracle.topic_accuracy([], 5) == 1.0
     # two journals, 4 docs split 3/1: S = 3, alpha = 2, beta = 6 -> 0.25
     assert oracle.topic_accuracy([0, 0, 0, 1], 2) == pytest.approx(0.25)
+
+
+# ---------------------------------------------------------------- sequential ALS (Algorithm 3)
+
+
+def test_sequential_one_block_is_algorithm_2():
+    """With a single block Algorithm 3 is its START step, Algorithm 2 itself."""
+    c = synth.make_corpus(300, 220, seed=12, alpha=1.1, nnz=5000)
+    A = c.scipy()
+    U0, _ = synth.make_init(300, 220, 4, seed=12)
+    seq = oracle.sequential_als(A, U0, 40, 30, k2=4, eta=1, iters=5)
+    ref = oracle.als(A, U0, 40, 30, 5)
+    np.testing.assert_array_equal(seq.U, ref.U)
+    np.testing.assert_array_equal(seq.V, ref.V)
+    np.testing.assert_allclose(seq.E, ref.E, rtol=1e-14)
+    np.testing.assert_allclose(seq.R, ref.R, rtol=1e-14)
+
+
+@pytest.mark.parametrize("k1,k2", [(2, 1), (3, 2), (1, 3)])
+def test_sequential_deflation_is_least_squares(k1, k2):
+    """The deflated solve equals the least-squares fit of U2 V2^T to the
+    residual A - U1 V1^T (numpy's SVD-based lstsq), for both half-steps."""
+    rng = np.random.default_rng(20 + k1 * 3 + k2)
+    n, m = 9, 7
+    A = sp.csr_matrix(rng.uniform(0.0, 2.0, (n, m)) * (rng.random((n, m)) < 0.6))
+    U1, V1 = rng.uniform(0.1, 1.0, (n, k1)), rng.uniform(0.1, 1.0, (m, k1))
+    U2, V2 = rng.uniform(0.1, 1.0, (n, k2)), rng.uniform(0.1, 1.0, (m, k2))
+    Rsd = A.toarray() - U1 @ V1.T
+    _, dv = oracle.deflated_half_step(sp.csr_matrix(A.T), U2, U1, V1, 10**6, mode=oracle.MODE_NONE)
+    np.testing.assert_allclose(dv["X_pre"], np.linalg.lstsq(U2, Rsd, rcond=None)[0].T, rtol=1e-10, atol=1e-12)
+    _, du = oracle.deflated_half_step(A, V2, V1, U1, 10**6, mode=oracle.MODE_NONE)
+    np.testing.assert_allclose(du["X_pre"], np.linalg.lstsq(V2, Rsd.T, rcond=None)[0].T, rtol=1e-10, atol=1e-12)
+
+
+def test_sequential_exact_factors_leave_nothing_to_deflate():
+    """A = U* V*^T with disjoint supports.  The first block (Algorithm 2 from
+    a noisy U*) recovers A exactly; the second block then fits a zero
+    residual, so E stays at rounding level and the first block's columns
+    are untouched."""
+    A, Us, Vs, rb, db, rng = _disjoint_blocks(2)
+    k = Us.shape[1]
+    t_u, t_v = min(len(b) for b in rb), min(len(b) for b in db)
+    U0 = Us + 1e-2 * rng.uniform(0.0, 1.0, Us.shape)
+    st = oracle.sequential_als(A, U0, t_u, t_v, k2=k, eta=2, iters=2)
+    assert st.E[1] <= 1e-12
+    assert max(st.E[2:]) <= 1e-10
+    first = oracle.sequential_als(A, U0, t_u, t_v, k2=k, eta=1, iters=2)
+    np.testing.assert_array_equal(st.U[:, :k], first.U)
+    np.testing.assert_array_equal(st.V[:, :k], first.V)
+
+
+def test_sequential_invariants():
+    """Blocks already found never change; every column keeps at most t
+    positive entries; each block's first iteration restarts from U0."""
+    c = synth.make_corpus(400, 300, seed=13, alpha=1.1, nnz=8000)
+    A = c.scipy()
+    U0, _ = synth.make_init(400, 300, 1, seed=13)
+    t_u, t_v = 25, 20
+    st = oracle.sequential_als(A, U0, t_u, t_v, k2=1, eta=4, iters=3, keep_steps=True)
+    assert len(st.E) == 12
+    for i, s in enumerate(st.steps):
+        b = s["block"]
+        if i % 3 == 0:
+            np.testing.assert_array_equal(s["U_in"][:, b], U0[:, 0])
+        if i > 0 and b > 0:
+            prev = st.steps[i - 1]
+            np.testing.assert_array_equal(s["U"][:, :b], prev["U"][:, :b])
+            np.testing.assert_array_equal(s["V"][:, :b], prev["V"][:, :b])
+        np.testing.assert_array_equal(s["U"][:, b + 1:], 0.0)
+    assert np.all(st.U >= 0) and np.all(st.V >= 0)
+    assert np.all((st.U > 0).sum(0) <= t_u) and np.all((st.V > 0).sum(0) <= t_v)
