@@ -225,6 +225,23 @@ enum {
  * Errors: INVALID_ARG for an unknown parameter or a value out of range. */
 nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value);
 
+/* Sequential ALS (Algorithm 3, Section 4): find the k topics k2 at a time.
+ * Block b (b = 0 .. k/k2 - 1) solves columns [b k2, (b + 1) k2) of U and V
+ * for `iters` iterations while the earlier columns stay fixed, with the
+ * deflated least-squares solves of Eqs. (seq-V)/(seq-U):
+ *   V2 = (A^T U2 - V1 (U1^T U2)) (U2^T U2)^-1,  U2 = (A V2 - U1 (V1^T V2)) (V2^T V2)^-1,
+ * each clamped at zero and cut to the t_v / t_u largest entries of every
+ * column (the handle's per-column rule; NMF_MODE_NONE: no cut).  Every block
+ * starts from the same initial guess: the first k2 columns of U when the
+ * call begins (for a fresh handle, of U0; the other columns of U0 are not
+ * used).  Block 0 is Algorithm 2 on those k2 topics.  U and V keep all k
+ * columns (later blocks' columns are zero until solved); each iteration
+ * records E and R (Section 3.1) of the full factors in the history, R
+ * against U as it stood when the iteration began.  k2 must divide k.
+ * Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (NMF_MODE_WHOLE),
+ * NOT_SPD (a block's Gram matrix; sticky, reported at the next sync). */
+nmf_status nmf_sequential(nmf_handle* h, int32_t k2, int32_t iters);
+
 /* Apply the top-t rule once to the current U (t_u) and V (t_v): mode
  * NMF_MODE_COLUMN per column (Section 4), NMF_MODE_WHOLE over the whole
  * factor (Section 2), with the tie-breaks of the iteration; their Gram

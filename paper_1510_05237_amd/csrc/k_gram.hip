@@ -441,6 +441,55 @@ hipError_t gram_dense(nmf_handle* h, const T* F, int64_t rows, double* G) {
   return launch<T>(h, g, rows);
 }
 
+// G = F^T F only (no inverse, no storage mark).
+template <typename T>
+hipError_t gram_plain(nmf_handle* h, const Factor& F, double* G) {
+  GramArgs g{};
+  g.F = F.dense;
+  g.ld = F.ld;
+  g.rows_dev = F.counts + 1;
+  g.k = h->k;
+  g.partials = h->gram_partials;
+  g.G = G;
+  g.W = nullptr;
+  g.status = h->status;
+  return launch<T>(h, g, F.rows);
+}
+
+namespace {
+__global__ void k_copy_block(const double* G, int32_t k, int32_t k1, int32_t k2, double* Gb) {
+  for (int i = threadIdx.x; i < k2 * k2; i += blockDim.x) {
+    const int a = i / k2, b = i - a * k2;
+    Gb[i] = G[static_cast<int64_t>(k1 + a) * k + (k1 + b)];
+  }
+}
+}  // namespace
+
+// W22 = inverse of the [k1, k1 + k2) diagonal block of the k x k matrix G,
+// by the same float64 Gauss-Jordan kernel as the full inverse (dead topics
+// of the block get identity rows; a non-positive pivot is NMF_ERR_NOT_SPD).
+// Gb: k2 x k2 scratch; dead: one int of scratch.
+hipError_t block_inverse(nmf_handle* h, const double* G, int k1, int k2, double* Gb, double* W22, int32_t* dead) {
+  hipLaunchKernelGGL(k_copy_block, dim3(1), dim3(256), 0, h->stream, G, h->k, k1, k2, Gb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  GramArgs g{};
+  g.G = Gb;
+  g.W = W22;
+  g.k = k2;
+  g.dead = dead;
+  g.status = h->status;
+  if (k2 <= 32)
+    hipLaunchKernelGGL(k_gram_factor<32>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+  else if (k2 <= 64)
+    hipLaunchKernelGGL(k_gram_factor<64>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+  else
+    hipLaunchKernelGGL(k_gram_factor<128>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+  return hipGetLastError();
+}
+
+template hipError_t gram_plain<float>(nmf_handle*, const Factor&, double*);
+template hipError_t gram_plain<double>(nmf_handle*, const Factor&, double*);
 template hipError_t gram<float>(nmf_handle*, const Factor&, const Gram&);
 template hipError_t gram<double>(nmf_handle*, const Factor&, const Gram&);
 template hipError_t gram_dense<float>(nmf_handle*, const float*, int64_t, double*);

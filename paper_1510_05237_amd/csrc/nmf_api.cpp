@@ -380,8 +380,20 @@ nmf_status u_half(nmf_handle* h, bool keep_c) {
 }
 
 template <typename T>
+nmf_status refresh_w(nmf_handle* h) {
+  if (!h->w_stale) return NMF_OK;
+  HIPCHK(h, gram<T>(h, h->U[h->cur_u], h->gU));
+  h->w_stale = false;
+  return NMF_OK;
+}
+
+template <typename T>
 nmf_status do_steps(nmf_handle* h, int32_t iters) {
   const bool rec = !(h->cfg.flags & NMF_FLAG_NO_METRICS);
+  if (iters > 0) {
+    nmf_status s = refresh_w<T>(h);
+    if (s != NMF_OK) return s;
+  }
   for (int32_t i = 0; i < iters; ++i) {
     nmf_status s = v_half<T>(h);
     if (s != NMF_OK) return s;
@@ -539,6 +551,76 @@ nmf_status do_error(nmf_handle* h, double* E) {
   return NMF_OK;
 }
 
+// Sequential ALS (Algorithm 3): blocks of k2 topics, `iters` iterations per
+// block, each block starting from the initial guess U0 = the first k2
+// columns of U when the call begins.  The handle's factors keep their full
+// width k = eta k2 (later blocks' columns zero); every iteration records E
+// and R in the history like an iteration of Algorithm 2.
+template <typename T>
+nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  const int k = h->k;
+  const int eta = k / k2;
+  const bool rec = !(h->cfg.flags & NMF_FLAG_NO_METRICS);
+  T* upre = static_cast<T*>(h->upre);
+  T* vpre = static_cast<T*>(h->vpre);
+  T* C = static_cast<T*>(h->cbuf);
+  T* U0b = static_cast<T*>(h->lossC);                // n x k2: the initial guess of every block
+  double* Gb = h->lossG;                             // k2 x k2 block of a Gram matrix
+  double* W22 = h->lossG + static_cast<size_t>(k2) * k2;  // its inverse
+  HIPCHK(h, densify<T>(h, h->U[h->cur_u], upre));
+  HIPCHK(h, seq_save<T>(h, upre, U0b, h->n, k2));
+  for (int b = 0; b < eta; ++b) {
+    const int k1 = b * k2;
+    // U = [finished blocks | U0 | 0]
+    Factor& Uc = h->U[h->cur_u];
+    HIPCHK(h, densify<T>(h, Uc, upre));
+    HIPCHK(h, seq_setup<T>(h, upre, U0b, h->n, k1, k2));
+    HIPCHK(h, mark_nonzero<T>(h, upre, h->n));
+    HIPCHK(h, repack<T>(h, upre, h->n, Uc, sparse_row_of(h, Uc)));
+    HIPCHK(h, gram_plain<T>(h, Uc, h->gU.G));
+    for (int32_t it = 0; it < iters; ++it) {
+      Factor& Uo = h->U[h->cur_u];
+      const int nxt = 1 - h->cur_u;
+      Factor& Un = h->U[nxt];
+      // V half: V2 = (A^T U2 - V1 U1^T U2) (U2^T U2)^-1
+      PROF(h, -1);
+      HIPCHK(h, spmm<T>(h, h->planAt, Uo, nullptr, vpre, nullptr, true, nullptr, h->sparse_row[0]));
+      HIPCHK(h, block_inverse(h, h->gU.G, k1, k2, Gb, W22, h->scratch_i));
+      HIPCHK(h, seq_solve<T>(h, vpre, vpre, h->m, h->V, h->gU.G, W22, k1, k2));
+      PROF(h, NMF_STAGE_SPMM_V);
+      HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
+      PROF(h, NMF_STAGE_SELECT_V);
+      HIPCHK(h, repack<T>(h, vpre, h->m, h->V, sparse_row_of(h, h->V)));
+      PROF(h, NMF_STAGE_REPACK_V);
+      HIPCHK(h, gram_plain<T>(h, h->V, h->gV.G));
+      HIPCHK(h, seq_max(h, Uo, h->V));
+      PROF(h, NMF_STAGE_GRAM_V);
+      // U half: U2 = (A V2 - U1 V1^T V2) (V2^T V2)^-1
+      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr, h->sparse_row[1]));
+      HIPCHK(h, block_inverse(h, h->gV.G, k1, k2, Gb, W22, h->scratch_i));
+      HIPCHK(h, seq_solve<T>(h, C, upre, h->n, Uo, h->gV.G, W22, k1, k2));
+      PROF(h, NMF_STAGE_SPMM_U);
+      HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
+      PROF(h, NMF_STAGE_SELECT_U);
+      HIPCHK(h, repack<T>(h, upre, h->n, Un, sparse_row_of(h, Un)));
+      PROF(h, NMF_STAGE_REPACK_U);
+      HIPCHK(h, gram_plain<T>(h, Un, h->gU.G));
+      HIPCHK(h, seq_max(h, Un, h->V));
+      PROF(h, NMF_STAGE_GRAM_U);
+      HIPCHK(h, metrics<T>(h, Un, Uo, C, rec));
+      PROF(h, NMF_STAGE_METRICS);
+      h->cur_u = nxt;
+      ++h->iters_done;
+      h->have_v = h->have_pre_v = h->have_pre_u = true;
+      h->metrics_valid = rec;
+    }
+  }
+  h->w_stale = true;  // gU.W / gV.W were not kept up to date
+  return NMF_OK;
+}
+
 // The top-t rule applied once to the current U and V (their dense forms go
 // through the select and the repack of an iteration), then their Gram
 // matrices and inverses are rebuilt.
@@ -637,7 +719,8 @@ nmf_status nmf_half_step(nmf_handle* h, int32_t which) {
   if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
   if (which != 0 && which != 1) return fail(h, NMF_ERR_INVALID_ARG, "which must be 0 or 1");
   if (which == 1 && !h->have_v) return fail(h, NMF_ERR_STATE, "no V yet");
-  nmf_status s;
+  nmf_status s = h->elt == 8 ? refresh_w<double>(h) : refresh_w<float>(h);
+  if (s != NMF_OK) return s;
   if (which == 0) {
     s = h->elt == 8 ? v_half<double>(h) : v_half<float>(h);
   } else {
@@ -841,6 +924,15 @@ nmf_status reload_meta(nmf_handle* h, int which) {
     HIPCHK(h, repack<float>(h, static_cast<float*>(stage), F.rows, F, sparse_row_of(h, F)));
   }
   return sync_status(h);
+}
+
+nmf_status nmf_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
+  if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  if (k2 < 1 || h->k % k2 != 0) return fail(h, NMF_ERR_INVALID_ARG, "k2 must divide k");
+  if (iters < 1) return fail(h, NMF_ERR_INVALID_ARG, "iters < 1");
+  if (h->cfg.mode != NMF_MODE_COLUMN && h->cfg.mode != NMF_MODE_NONE)
+    return fail(h, NMF_ERR_UNSUPPORTED, "sequential ALS runs in NMF_MODE_COLUMN or NMF_MODE_NONE");
+  return h->elt == 8 ? do_sequential<double>(h, k2, iters) : do_sequential<float>(h, k2, iters);
 }
 
 nmf_status nmf_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v) {

@@ -198,6 +198,7 @@ struct nmf_handle {
   // host-side state
   int64_t iters_done = 0;
   bool have_v = false;
+  bool w_stale = false;  // gU.W is not the inverse of U's Gram (after a sequential run)
   bool have_pre_v = false, have_pre_u = false;
   bool metrics_valid = false;  // the newest history record describes the current U, V
   int sparse_row[2] = {1, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
@@ -251,6 +252,19 @@ template <typename T>
 hipError_t grad_combine(nmf_handle* h, const T* F, const T* B, const double* G,
                         const double* g_scale, int64_t rows, T* out);
 hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t count);
+
+// Sequential ALS (k_seq.hip, k_gram.hip).
+template <typename T>
+hipError_t gram_plain(nmf_handle* h, const Factor& F, double* G);
+hipError_t block_inverse(nmf_handle* h, const double* G, int k1, int k2, double* Gb, double* W22, int32_t* dead);
+template <typename T>
+hipError_t seq_solve(nmf_handle* h, const T* B, T* X, int64_t rows, const Factor& F_old, const double* G,
+                     const double* W22, int k1, int k2);
+template <typename T>
+hipError_t seq_setup(nmf_handle* h, T* X, const T* U0b, int64_t rows, int k1, int k2);
+template <typename T>
+hipError_t seq_save(nmf_handle* h, const T* X, T* U0b, int64_t rows, int k2);
+hipError_t seq_max(nmf_handle* h, const Factor& a, const Factor& b);
 // counts[c * n_labels + l] += documents with label l storing an entry in topic c
 hipError_t topic_counts(nmf_handle* h, const Factor& F, const int32_t* labels, int32_t n_labels, uint32_t* counts);
 

@@ -102,6 +102,7 @@ SIGNATURES = {
     "nmf_batch_tune": (_I32, [_P, _I32, _P]),
     "nmf_get_param": (_I32, [_P, _I32, _P]),
     "nmf_enforce": (_I32, [_P, _I32, _I64, _I64]),
+    "nmf_sequential": (_I32, [_P, _I32, _I32]),
     "nmf_topic_counts": (_I32, [_P, _P, _I32, _P]),
     "nmf_batch_errors": (_I32, [_P, _P, _P]),
     "nmf_batch_problem": (_P, [_P, _I32]),
@@ -250,6 +251,10 @@ NMF_PARAM_WAVES_U = 5
 
 def nmf_set_param(h: int, param: int, value: int):
     _check(load_library().nmf_set_param(h, param, value), h)
+
+
+def nmf_sequential(h: int, k2: int, iters: int):
+    _check(load_library().nmf_sequential(h, k2, iters), h)
 
 
 def nmf_enforce(h: int, mode: int, t_u: int, t_v: int):
@@ -452,6 +457,10 @@ class NMF:
         from .accuracy import accuracy_from_counts
 
         return accuracy_from_counts(self.topic_counts(labels, n_journals), n_journals)
+
+    def sequential(self, k2: int, iters: int):
+        """Algorithm 3: k / k2 blocks of k2 topics, ``iters`` iterations each."""
+        nmf_sequential(self.h, k2, iters)
 
     def enforce(self, t_u: int, t_v: int, mode: str = "column"):
         """Apply the top-t rule once to the current U and V."""
