@@ -251,6 +251,44 @@ def sweep_accuracy(iters: int = 50):
     return {"workload": f"planted_{n}x{m}_{n_j}_journals", "nnz": c.nnz, "k": k, "iters": iters, "rows": rows}
 
 
+def compare_rules(total_iters: int = 100):
+    """Time of 100 ALS iterations for a 5-topic factorization of a
+    PubMed-sized stand-in (20 112 x 7 510, 0.4 % density): the top-t rule over
+    the whole factor (t = 500 entries), per column (t = 100), and sequential
+    ALS (Algorithm 3) with one topic per block, 20 iterations per block (the
+    comparison of the paper's Section 4 timing table, on synthetic data).
+    Wall time around the enqueued iterations, HIP-synchronized."""
+    import torch
+
+    import synth
+    from paper_1510_05237_amd import NMF
+
+    n, m, k = 20112, 7510, 5
+    c = synth.make_corpus(n, m, seed=7, alpha=1.1, nnz=int(round(0.004 * n * m)), dtype="f32")
+    u0, _ = synth.make_init(n, m, k, seed=7, dtype="f32")
+    dev = torch.device("cuda:0")
+    args = [torch.from_numpy(x).to(dev) for x in (c.indptr, c.indices, c.data, u0)]
+    out = {}
+    for name, mode, t_u, t_v in (("whole", "whole", 500, 500), ("column", "column", 100, 100),
+                                 ("sequential", "column", 100, 100)):
+        times = []
+        for rep in range(3):
+            h = NMF(n, m, *args, t_u=t_u, t_v=t_v, dtype="f32", device=dev, mode=mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "sequential":
+                h.sequential(1, total_iters // k)
+            else:
+                h.step(total_iters)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            E = h.error()
+            h.close()
+        out[name] = dict(ms=round(min(times), 3), E=E)
+        log(f"rules: {name} {out[name]}")
+    return {"workload": f"pubmed_like_{n}x{m}", "nnz": c.nnz, "k": k, "iters": total_iters, "rules": out}
+
+
 def copy_calibration(gib: float = 1.0, reps: int = 5):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     import torch
@@ -280,6 +318,8 @@ def main():
                     help="print the max-NNZ sweep (enforced sparsity against dense ALS) and exit")
     ap.add_argument("--sweep-accuracy", action="store_true",
                     help="print the clustering-accuracy sweep (Eq. (acc) against t) and exit")
+    ap.add_argument("--compare-rules", action="store_true",
+                    help="print the whole-matrix / per-column / sequential timing comparison and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched comparison (for profiling it); prints its JSON object")
     args = ap.parse_args()
@@ -290,6 +330,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.compare_rules:
+        print(json.dumps({"rules_comparison": compare_rules()}), flush=True)
         return
     if args.sweep_accuracy:
         print(json.dumps({"accuracy_sweep": sweep_accuracy()}), flush=True)
