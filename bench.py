@@ -289,6 +289,65 @@ def compare_rules(total_iters: int = 100):
     return {"workload": f"pubmed_like_{n}x{m}", "nnz": c.nnz, "k": k, "iters": total_iters, "rules": out}
 
 
+def compare_autograd(reps: int = 20):
+    """The autograd loss on the 100k x 200k matrix with sparse U, V (t = 1000
+    and 2000 per column): NMFLoss forward + backward against the same two
+    ABI calls made directly (nmf_loss_fwd, nmf_loss_bwd), same outputs."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1510_05237_amd import NMF, NMFLoss
+    from paper_1510_05237_amd.nmf import nmf_loss_bwd, nmf_loss_fwd
+
+    c, _, _, p = synth.make_workload("plain_f32_100kx200k", with_init=False)
+    k = p["k"]
+    rng = np.random.Generator(np.random.PCG64(4))
+    U = synth.sparse_factor_init(c.n, k, p["t_u"], rng=rng, dtype="f32")
+    V = synth.sparse_factor_init(c.m, k, p["t_v"], rng=rng, dtype="f32")
+    dev = torch.device("cuda:0")
+    prob = NMF(c.n, c.m, torch.from_numpy(c.indptr).to(dev), torch.from_numpy(c.indices).to(dev),
+               torch.from_numpy(c.data).to(dev), torch.from_numpy(U).to(dev), t_u=p["t_u"], t_v=p["t_v"],
+               dtype="f32", device=dev)
+    Ut = torch.tensor(U, device=dev, requires_grad=True)
+    Vt = torch.tensor(V, device=dev, requires_grad=True)
+
+    def autograd_step():
+        Ut.grad = None
+        Vt.grad = None
+        L = NMFLoss.apply(prob, Ut, Vt)
+        L.backward()
+        return L
+
+    Ud, Vd = Ut.detach(), Vt.detach()
+    Ld = torch.empty((), dtype=torch.float64, device=dev)
+    one = torch.ones((), dtype=torch.float64, device=dev)
+    gU, gV = torch.empty_like(Ud), torch.empty_like(Vd)
+
+    def direct_step():
+        nmf_loss_fwd(prob.h, Ud, Vd, Ld)
+        nmf_loss_bwd(prob.h, Ud, Vd, one, gU, gV)
+        return Ld
+
+    res = {}
+    for name, fn in (("autograd", autograd_step), ("direct", direct_step)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = round((time.perf_counter() - t0) * 1e3 / reps, 4)
+    L = autograd_step()
+    direct_step()
+    torch.cuda.synchronize()
+    same = bool(float(L.detach()) == float(Ld) and torch.equal(Ut.grad, gU) and torch.equal(Vt.grad, gV))
+    prob.close()
+    return {"workload": "plain_f32_100kx200k sparse U,V (t_u=1000, t_v=2000, seed 4)", "k": k,
+            "ms_fwd_bwd": res, "identical_outputs": same, "loss": float(L.detach())}
+
+
 def copy_calibration(gib: float = 1.0, reps: int = 5):
     """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
     import torch
@@ -320,6 +379,8 @@ def main():
                     help="print the clustering-accuracy sweep (Eq. (acc) against t) and exit")
     ap.add_argument("--compare-rules", action="store_true",
                     help="print the whole-matrix / per-column / sequential timing comparison and exit")
+    ap.add_argument("--compare-autograd", action="store_true",
+                    help="print the autograd-loss timing against direct ABI calls and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched comparison (for profiling it); prints its JSON object")
     args = ap.parse_args()
@@ -330,6 +391,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.compare_autograd:
+        print(json.dumps({"autograd_comparison": compare_autograd()}), flush=True)
         return
     if args.compare_rules:
         print(json.dumps({"rules_comparison": compare_rules()}), flush=True)

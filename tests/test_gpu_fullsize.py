@@ -59,3 +59,81 @@ def test_fp32_100kx200k_half_steps():
     _say(f"  E gpu {E:.8f} oracle {Eo:.8f}")
     assert abs(E - Eo) <= 1e-6 * Eo
     prob.close()
+
+
+def test_fp32_100kx200k_loss_and_gradient():
+    """The autograd loss on the full 100k x 200k matrix with sparse U, V
+    (t = 1000 and 2000 rows per column, values U(0,1), seed 4): L and both
+    gradients against the FP64 oracle to 1e-4, and central differences of the
+    row-restricted FP64 loss (exactly quadratic in each entry) at 64 entries,
+    32 of U and 32 of V, half of them inside the support."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_05237_amd import NMF, NMFLoss
+
+    c, _, _, p = synth.make_workload("plain_f32_100kx200k", with_init=False)
+    k = p["k"]
+    rng = np.random.Generator(np.random.PCG64(4))
+    U = synth.sparse_factor_init(c.n, k, p["t_u"], rng=rng, dtype="f32")
+    V = synth.sparse_factor_init(c.m, k, p["t_v"], rng=rng, dtype="f32")
+    dev = torch.device("cuda:0")
+    _say(f"fp32 autograd loss {c.n}x{c.m} nnz={c.nnz} k={k}, sparse U ({np.count_nonzero(U)}) and V ({np.count_nonzero(V)})")
+    prob = NMF(c.n, c.m, torch.from_numpy(c.indptr).to(dev), torch.from_numpy(c.indices).to(dev),
+               torch.from_numpy(c.data).to(dev), torch.from_numpy(U).to(dev), t_u=p["t_u"], t_v=p["t_v"],
+               dtype="f32", device=dev)
+    Ut = torch.tensor(U, device=dev, requires_grad=True)
+    Vt = torch.tensor(V, device=dev, requires_grad=True)
+    L = NMFLoss.apply(prob, Ut, Vt)
+    L.backward()
+    A = c.scipy()
+    L_or = oracle.loss(A, U, V)
+    gU_or, gV_or = oracle.loss_grad(A, U, V)
+    gU, gV = Ut.grad.cpu().numpy(), Vt.grad.cpu().numpy()
+    _say(f"  L gpu {float(L.detach()):.6e} oracle {L_or:.6e}; grad rel U {rel_fro(gU, gU_or):.2e} V {rel_fro(gV, gV_or):.2e}")
+    assert float(L.detach()) == pytest.approx(L_or, rel=1e-4)
+    assert rel_fro(gU, gU_or) <= 1e-4 and rel_fro(gV, gV_or) <= 1e-4
+    U64, V64 = U.astype(np.float64), V.astype(np.float64)
+    GU, GV = U64.T @ U64, V64.T @ V64
+    At = A.T.tocsr()
+    h = 0.25
+
+    def pick(M, seed):
+        """16 entries inside the support and 16 outside it."""
+        rr = np.random.default_rng(seed)
+        ins = np.argwhere(M != 0)
+        outs = []
+        while len(outs) < 16:
+            x = (int(rr.integers(0, M.shape[0])), int(rr.integers(0, M.shape[1])))
+            if M[x] == 0:
+                outs.append(x)
+        return [tuple(x) for x in ins[rr.choice(len(ins), 16, replace=False)]] + outs
+
+    for (i, j) in pick(U, 6):
+        a = A.getrow(i)
+        aV = np.asarray(a @ V64).ravel()
+        aa = float(a.multiply(a).sum())
+
+        def Lrow(u):
+            return aa - 2.0 * u @ aV + u @ GV @ u
+
+        up, um = U64[i].copy(), U64[i].copy()
+        up[j] += h
+        um[j] -= h
+        fd = (Lrow(up) - Lrow(um)) / (2 * h)
+        assert gU[i, j] == pytest.approx(fd, rel=1e-4, abs=1e-4 * np.abs(gU_or).max())
+    for (i, j) in pick(V, 7):
+        a = At.getrow(i)
+        aU = np.asarray(a @ U64).ravel()
+        aa = float(a.multiply(a).sum())
+
+        def Lcol(v):
+            return aa - 2.0 * v @ aU + v @ GU @ v
+
+        vp, vm = V64[i].copy(), V64[i].copy()
+        vp[j] += h
+        vm[j] -= h
+        fd = (Lcol(vp) - Lcol(vm)) / (2 * h)
+        assert gV[i, j] == pytest.approx(fd, rel=1e-4, abs=1e-4 * np.abs(gV_or).max())
+    prob.close()
