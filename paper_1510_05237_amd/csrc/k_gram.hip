@@ -256,25 +256,30 @@ __global__ __launch_bounds__(256) void k_gram_mfma_b(const GramArgs* as, const B
 }
 
 
-// One block: the storage high-water mark, then W = G^-1 in float64 by
-// Gauss-Jordan elimination on the symmetric positive definite G.  Without
-// pivoting its j-th pivot is the j-th Schur complement diagonal, i.e. the
-// square of the Cholesky diagonal L_jj, so a pivot that is not positive
+// One block: the storage high-water mark, then W = G^-1 in float64 by the
+// symmetric sweep operator on the positive definite G.  Sweeping pivot p
+// maps a to b with
+//   b_pp = -1 / a_pp,  b_ip = a_ip / a_pp,  b_pj = a_pj / a_pp,
+//   b_ij = a_ij - a_ip a_pj / a_pp          (i, j != p),
+// which keeps the matrix symmetric; sweeping every pivot in order leaves
+// -G^-1.  Its p-th pivot is the p-th Schur complement diagonal, i.e. the
+// square of the Cholesky diagonal L_pp, so a pivot that is not positive
 // (NOT_SPD) occurs exactly where the Cholesky factorization of G fails.
 // Dead topics (G_cc = 0) get identity rows and columns first, which the
-// elimination leaves unchanged.
+// sweep leaves as -1 on the diagonal (W_cc = 1).
 //
-// The KM x KM matrix lives in registers: thread t of 1024 owns row
-// i = t / TPR and the columns l = t % TPR + TPR * q.  Step j needs the pivot,
-// column j and row j as they were after step j - 1; their owners publish
-// them in a double-buffered LDS copy, so each step costs one barrier.
+// The KM x KM matrix lives in registers: thread t of 1024 owns column
+// c = t % KM and the R = KM^2 / 1024 rows (at least one) of its row block
+// t / KM.  By
+// symmetry every update of step p needs only row p (a_pj and a_ip = a_pi):
+// its owners publish it in a double-buffered LDS copy, one barrier a step.
 constexpr int kFactorThreads = 1024;
 
 template <int KM>
 __device__ __forceinline__ void k_gram_factor_body(const GramArgs& g, int blk, int nblk) {
-  constexpr int TPR = kFactorThreads / KM;  // threads per row
-  constexpr int NQ = KM / TPR;              // entries per thread
-  __shared__ double rowb[2][KM], colb[2][KM];
+  constexpr int NB = kFactorThreads / KM;  // row blocks
+  constexpr int R = KM / NB;               // rows per thread
+  __shared__ double rowp[2][KM];
   __shared__ int s_dead[KM];
   __shared__ int s_nd;
   if (*g.status != 0) return;
@@ -295,71 +300,56 @@ __device__ __forceinline__ void k_gram_factor_body(const GramArgs& g, int blk, i
   }
   __syncthreads();
   if (tid == 0) *g.dead = s_nd;
-  const int i = tid / TPR;
-  const int ph = tid % TPR;
-  double e[NQ];
+  const int c = tid % KM;
+  const int r0 = (tid / KM) * R;
+  double e[R];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int l = ph + TPR * q;
+  for (int q = 0; q < R; ++q) {
+    const int i = r0 + q;
     double v = 0.0;
-    if (i < k && l < k) v = (s_dead[i] || s_dead[l]) ? (i == l ? 1.0 : 0.0) : g.G[i * k + l];
+    if (i < k && c < k) v = (s_dead[i] || s_dead[c]) ? (i == c ? 1.0 : 0.0) : g.G[i * k + c];
     e[q] = v;
   }
-  // publish row 0 and column 0
-  if (i == 0) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) rowb[0][ph + TPR * q] = e[q];
-  }
-  if (ph == 0) colb[0][i] = e[0];
-  __syncthreads();
   bool ok = true;
-  for (int j = 0; j < k; ++j) {
-    const int b = j & 1;
-    const double p = rowb[b][j];
-    ok = ok && p > 0.0;
-    const double ip = 1.0 / p;
-    // row j: a_jl * ip; other rows: a_il - a_ij * (a_jl * ip); column j:
-    // ip on the pivot, -a_ij * ip elsewhere
-    const bool prow = i == j;
-    const double aij = prow ? 0.0 : colb[b][i];
+  for (int p = 0; p < k; ++p) {
+    const int b = p & 1;
+    if (p / R == r0 / R) {
+      const int qp = p - r0;
+      double v = 0.0;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double gl = rowb[b][ph + TPR * q] * ip;
-      e[q] = prow ? gl : fma(-aij, gl, e[q]);
-    }
-    if (ph == j % TPR) {
-      const double v = prow ? ip : -aij * ip;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (q == j / TPR) e[q] = v;
-    }
-    // publish row j + 1 and column j + 1 for the next step
-    const int jn = j + 1;
-    if (jn < k) {
-      if (i == jn) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) rowb[b ^ 1][ph + TPR * q] = e[q];
-      }
-      if (ph == jn % TPR) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          if (q == jn / TPR) v = e[q];
-        colb[b ^ 1][i] = v;
-      }
+      for (int q = 0; q < R; ++q)
+        if (q == qp) v = e[q];
+      rowp[b][c] = v;
     }
     __syncthreads();
+    const double d = rowp[b][p];
+    ok = ok && d > 0.0;
+    const double ip = 1.0 / d;
+    const double apc = rowp[b][c] * ip;  // b_pc for c != p
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = r0 + q;
+      const double aip = rowp[b][i];
+      double v;
+      if (i == p)
+        v = c == p ? -ip : apc;
+      else if (c == p)
+        v = aip * ip;
+      else
+        v = fma(-aip, apc, e[q]);
+      e[q] = v;
+    }
   }
   if (!ok) {
     if (tid == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
     for (int x = tid; x < k * k; x += kFactorThreads) g.W[x] = 0.0;
     return;
   }
-  if (i < k) {
+  if (c < k) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int l = ph + TPR * q;
-      if (l < k) g.W[i * k + l] = e[q];
+    for (int q = 0; q < R; ++q) {
+      const int i = r0 + q;
+      if (i < k) g.W[i * k + c] = -e[q];
     }
   }
 }

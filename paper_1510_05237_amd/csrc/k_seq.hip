@@ -39,8 +39,11 @@ __global__ __launch_bounds__(256) void k_seq_solve(const T* Bin, T* Xout, int64_
     y[q] = in_blk[q] ? static_cast<double>(Bin[r * k + c]) : 0.0;
     keep[q] = T(0);
   }
-  // the finished topics of this row: deflate, and keep their values
-  const int32_t e0 = row_ptr[r], e1 = row_ptr[r + 1];
+  // the finished topics of this row: deflate, and keep their values (in the
+  // first block there are none, and the solved factor may not exist yet:
+  // its storage is not read)
+  const int32_t e0 = k1 > 0 ? row_ptr[r] : 0;
+  const int32_t e1 = k1 > 0 ? row_ptr[r + 1] : 0;
   for (int32_t e = e0; e < e1; ++e) {
     const int t = topic[e];
     if (t >= k1) continue;

@@ -107,3 +107,24 @@ def test_sequential_arguments():
         prob.sequential(2, 2)
     assert ei.value.status == -3
     prob.close()
+
+
+def test_sequential_on_recycled_memory():
+    """Regression: the first block must not read the solved factor's storage
+    (V does not exist before the first V half).  The workspace is carved from
+    memory that held other data just before."""
+    NMF, _ = _lib()
+    import torch
+
+    junk = torch.full((64 << 20,), -1, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    del junk
+    c = synth.make_corpus(700, 500, seed=94, alpha=1.1, nnz=9000, dtype="f64")
+    u0, _ = synth.make_init(700, 500, 4, seed=94, dtype="f64")
+    _say("fp64 700x500 k=4 sequential k2=1 on a workspace carved from recycled memory")
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=40, t_v=30, dtype="f64")
+    prob.sequential(1, 2)
+    U, V = prob.factors()
+    st = oracle.sequential_als(c.scipy(), u0[:, :1], 40, 30, k2=1, eta=4, iters=2)
+    assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9
+    prob.close()
