@@ -456,7 +456,7 @@ __global__ void k_copy_block(const double* G, int32_t k, int32_t k1, int32_t k2,
 }  // namespace
 
 // W22 = inverse of the [k1, k1 + k2) diagonal block of the k x k matrix G,
-// by the same float64 Gauss-Jordan kernel as the full inverse (dead topics
+// by the same float64 sweep kernel as the full inverse (dead topics
 // of the block get identity rows; a non-positive pivot is NMF_ERR_NOT_SPD).
 // Gb: k2 x k2 scratch; dead: one int of scratch.
 hipError_t block_inverse(nmf_handle* h, const double* G, int k1, int k2, double* Gb, double* W22, int32_t* dead) {
