@@ -38,6 +38,8 @@ namespace {
 constexpr int kRowsPerBlock = 64;  // rows of X per hist/collect block
 constexpr int kPadBins = kBins + 1;
 constexpr int kFinish = 64;  // candidates ranked directly by one wave
+constexpr int kHistRows = 8;                       // rows in flight per wave in k_hist
+constexpr int kCollectRows = kRowsPerBlock / 4;    // k_collect: every row of a wave's share at once
 
 struct SelArgs {
   const void* X;
@@ -75,17 +77,17 @@ __device__ __forceinline__ void k_hist_body(const SelArgs& a, int blk, int nblk)
   const int64_t r_begin = static_cast<int64_t>(blk) * a.hist_rows;
   int64_t r_end = r_begin + a.hist_rows;
   if (r_end > a.rows) r_end = a.rows;
-  // four rows per wave per step keep four loads in flight
-  for (int64_t r = r_begin + wv; r < r_end; r += 16) {
+  // kHistRows rows per wave per step keep that many loads in flight
+  for (int64_t r = r_begin + wv; r < r_end; r += 4 * kHistRows) {
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
       if (c < k) {
-        typename KO::K key[4];
+        typename KO::K key[kHistRows];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) key[u] = r + 4 * u < r_end ? KO::key(X[(r + 4 * u) * k + c]) : 0;
+        for (int u = 0; u < kHistRows; ++u) key[u] = r + 4 * u < r_end ? KO::key(X[(r + 4 * u) * k + c]) : 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kHistRows; ++u)
           if (key[u] != 0) atomicAdd(&h[(WHOLE ? 0 : c * kPadBins) + top_digit<T>(key[u])], 1u);
       }
     }
@@ -167,17 +169,18 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
   const int64_t r_begin = static_cast<int64_t>(blk) * kRowsPerBlock;
   int64_t r_end = r_begin + kRowsPerBlock;
   if (r_end > a.rows) r_end = a.rows;
-  for (int64_t r4 = r_begin + wv; r4 < r_end; r4 += 16) {
-   typename KO::K keys[4][KPL];
+  // each wave takes every fourth row of the block, all of them in flight at once
+  for (int64_t r4 = r_begin + wv; r4 < r_end; r4 += 4 * kCollectRows) {
+   typename KO::K keys[kCollectRows][KPL];
 #pragma unroll
-   for (int u = 0; u < 4; ++u)
+   for (int u = 0; u < kCollectRows; ++u)
 #pragma unroll
      for (int q = 0; q < KPL; ++q) {
        const int c = lane + 64 * q;
        keys[u][q] = (c < k && r4 + 4 * u < r_end) ? KO::key(X[(r4 + 4 * u) * k + c]) : 0;
      }
 #pragma unroll
-   for (int u = 0; u < 4; ++u) {
+   for (int u = 0; u < kCollectRows; ++u) {
     const int64_t r = r4 + 4 * u;
     if (r >= r_end) break;
     uint64_t keep_bits[KPL];
