@@ -160,29 +160,32 @@ __device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, 
   const int nparts = a.nparts;
   __shared__ double sh[12];
   __shared__ double tot[3];
-  __shared__ double pv[kMetricBlocks * 3];
+  __shared__ double totq[3];
   if (*a.status != 0) return;
   const int k = a.k;
-  for (int i = threadIdx.x; i < nparts * 3; i += 256) pv[i] = a.partials[(i / 3) * 4 + (i % 3)];
+  // partials: thread t adds blocks t, t + 256, ... in order, then a fixed tree
+  double d = 0.0, n = 0.0, x = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    d += a.partials[b * 4 + 0];
+    n += a.partials[b * 4 + 1];
+    x += a.partials[b * 4 + 2];
+  }
+  block_sum3(d, n, x, sh, tot);
+  __syncthreads();
   double q = 0.0;
   if (a.record && a.GU != nullptr)
     for (int i = threadIdx.x; i < k * k; i += 256) q = fma(a.GU[i], a.GV[i], q);
-  block_sum3(q, 0.0, 0.0, sh, tot);
+  block_sum3(q, 0.0, 0.0, sh, totq);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double D = 0, N = 0, X = 0;
-  for (int b = 0; b < nparts; ++b) {
-    D += pv[b * 3 + 0];
-    N += pv[b * 3 + 1];
-    X += pv[b * 3 + 2];
-  }
+  const double D = tot[0], N = tot[1], X = tot[2];
   const int64_t it = *a.it;
   double* rec = a.ring + (it % kHistRing) * H_FIELDS;
   double E = __builtin_nan(""), R = __builtin_nan("");
   if (a.record) {
     R = sqrt(D) / sqrt(N);
     const double nA2 = *a.nA2;
-    const double e2 = nA2 - 2.0 * X + tot[0];
+    const double e2 = nA2 - 2.0 * X + totq[0];
     E = sqrt(e2 > 0.0 ? e2 : 0.0) / sqrt(nA2);
     if (!isfinite(R) || !isfinite(E)) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
   }
@@ -224,16 +227,15 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* partials, int 
                                                     double* out) {
   __shared__ double sh[12];
   __shared__ double tot[3];
-  __shared__ double pv[kMetricBlocks];
-  for (int i = threadIdx.x; i < nparts; i += 256) pv[i] = partials[i];
+  double x = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) x += partials[b];
   double q = 0.0;
   if (GU != nullptr)
     for (int i = threadIdx.x; i < k * k; i += 256) q = fma(GU[i], GV[i], q);
-  block_sum3(q, 0.0, 0.0, sh, tot);
+  block_sum3(q, x, 0.0, sh, tot);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  double X = 0.0;
-  for (int b = 0; b < nparts; ++b) X += pv[b];
+  const double X = tot[1];
   *out = GU != nullptr ? *nA2 - 2.0 * X + tot[0] : X;
 }
 

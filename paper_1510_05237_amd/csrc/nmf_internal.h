@@ -23,7 +23,7 @@ inline int spmm_row_group(int k) { return k > 64 ? 4 : 8; }
 constexpr int kBins = 256;       // radix digit width of the top-t select (8 bits)
 constexpr int kHistRing = 4096;  // iterations kept in the device history ring
 constexpr int kGramBlocks = 240; // Gram partial blocks (fixed: deterministic sums)
-constexpr int kMetricBlocks = 240;
+constexpr int kMetricBlocks = 1024;
 constexpr int kCntStride = 32;  // ints between per-column counters (one 128-byte line each)
 
 // History record fields (float64 each).
