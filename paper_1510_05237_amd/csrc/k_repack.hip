@@ -22,8 +22,9 @@ namespace nmfk {
 
 namespace {
 
-constexpr int kRowsPerThread = 2;
+constexpr int kRowsPerThread = 1;
 constexpr int kScanRows = 256 * kRowsPerThread;  // rows per block
+constexpr int kBuildInFlight = 8;  // nonempty rows whose value loads are in flight together
 
 struct RepackArgs {
   const void* X;
@@ -158,12 +159,11 @@ __device__ __forceinline__ void k_build_body(const RepackArgs& a, int blk, int n
   FactorEnt<T>* __restrict__ ents = static_cast<FactorEnt<T>*>(a.F.packed);
   for (int g = wv * 64; g < kScanRows; g += 256) {
     uint64_t todo = __ballot(s_slot[g + lane] >= 0);
-    // four nonempty rows per step: their value loads are in flight together
     while (todo) {
-      int ib[4];
+      int ib[kBuildInFlight];
       int nb = 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kBuildInFlight; ++u) {
         ib[u] = -1;
         if (todo) {
           ib[u] = g + __ffsll(static_cast<long long>(todo)) - 1;
@@ -171,16 +171,16 @@ __device__ __forceinline__ void k_build_body(const RepackArgs& a, int blk, int n
           ++nb;
         }
       }
-      T xv[4][KPL];
+      T xv[kBuildInFlight][KPL];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < kBuildInFlight; ++u)
 #pragma unroll
         for (int q = 0; q < KPL; ++q) {
           const int c = lane + 64 * q;
           xv[u][q] = (ib[u] >= 0 && c < k) ? X[(rb0 + ib[u]) * k + c] : T(0);
         }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kBuildInFlight; ++u) {
         if (ib[u] < 0) continue;
         const int i = ib[u];
         const int s = s_slot[i];

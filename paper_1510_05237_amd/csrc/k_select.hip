@@ -40,6 +40,7 @@ constexpr int kPadBins = kBins + 1;
 constexpr int kFinish = 64;  // candidates ranked directly by one wave
 constexpr int kHistRows = 8;                       // rows in flight per wave in k_hist
 constexpr int kCollectRows = kRowsPerBlock / 4;    // k_collect: every row of a wave's share at once
+static_assert(kRowsPerBlock == 4 * kCollectRows, "k_collect: each of the 4 waves reads kCollectRows rows");
 
 struct SelArgs {
   const void* X;
@@ -145,42 +146,51 @@ __global__ __launch_bounds__(256) void k_pick_b(const SelArgs* as, const BlockMa
 }
 
 
+// Candidates are staged per (wave, column): a lane owns its column's slots
+// in its wave's region (at most kCollectRows, one per row the wave reads), so
+// staging needs no atomics; the block then takes one global offset per
+// column (one for the single list of the whole-matrix form) and copies its
+// regions out in wave order.
 template <typename T, int KPL, bool WHOLE>
 __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nblk) {
   using KO = KeyOf<T>;
   using C = Cand<T>;
-  __shared__ int32_t lcnt[kMaxK];
+  __shared__ int32_t lcnt[4][kMaxK];  // staged entries per (wave, column)
   __shared__ int32_t lbase[kMaxK];
+  __shared__ int32_t loff[4 * kMaxK];  // whole-matrix form: offset of each (wave, column) region
+  __shared__ int tmp[8];
   extern __shared__ __align__(16) unsigned char smem[];
-  C* stage = reinterpret_cast<C*>(smem);  // [k][kRowsPerBlock]
+  C* stage = reinterpret_cast<C*>(smem);  // [wave][slot < kCollectRows][k]
   if (*a.status != 0) return;
   const int k = a.k;
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
-  for (int i = threadIdx.x; i < k; i += 256) lcnt[i] = 0;
   ColSel s[KPL];
+  int cnt[KPL];
 #pragma unroll
   for (int q = 0; q < KPL; ++q) {
     const int c = lane + 64 * q;
     s[q] = c < k ? a.sel[WHOLE ? 0 : c] : ColSel{0, 0, 1, 0};
+    cnt[q] = 0;
   }
-  __syncthreads();
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const int64_t r_begin = static_cast<int64_t>(blk) * kRowsPerBlock;
   int64_t r_end = r_begin + kRowsPerBlock;
   if (r_end > a.rows) r_end = a.rows;
-  // each wave takes every fourth row of the block, all of them in flight at once
-  for (int64_t r4 = r_begin + wv; r4 < r_end; r4 += 4 * kCollectRows) {
-   typename KO::K keys[kCollectRows][KPL];
+  C* wstage = stage + static_cast<size_t>(wv) * kCollectRows * k;
+  // the wave reads every fourth row of the block (kCollectRows of them), all
+  // loads in flight at once
+  const int64_t r4 = r_begin + wv;
+  typename KO::K keys[kCollectRows][KPL];
 #pragma unroll
-   for (int u = 0; u < kCollectRows; ++u)
+  for (int u = 0; u < kCollectRows; ++u)
 #pragma unroll
-     for (int q = 0; q < KPL; ++q) {
-       const int c = lane + 64 * q;
-       keys[u][q] = (c < k && r4 + 4 * u < r_end) ? KO::key(X[(r4 + 4 * u) * k + c]) : 0;
-     }
+    for (int q = 0; q < KPL; ++q) {
+      const int c = lane + 64 * q;
+      keys[u][q] = (c < k && r4 + 4 * u < r_end) ? KO::key(X[(r4 + 4 * u) * k + c]) : 0;
+    }
 #pragma unroll
-   for (int u = 0; u < kCollectRows; ++u) {
+  for (int u = 0; u < kCollectRows; ++u) {
     const int64_t r = r4 + 4 * u;
     if (r >= r_end) break;
     uint64_t keep_bits[KPL];
@@ -188,22 +198,16 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
       bool keep = false;
-      if (c < k) {
-        const auto key = keys[u][q];
-        if (key != 0) {
-          const int d = top_digit<T>(key);
-          keep = s[q].all || d > s[q].b1;
-          if (!s[q].all && d == s[q].b1) {
-            C cd;
-            cd.key = key;
-            if (WHOLE) {
-              cd.row = static_cast<uint32_t>(r * k + c);
-              stage[atomicAdd(&lcnt[0], 1)] = cd;  // one list, up to 64 * k entries per block
-            } else {
-              cd.row = static_cast<uint32_t>(r);
-              stage[c * kRowsPerBlock + atomicAdd(&lcnt[c], 1)] = cd;
-            }
-          }
+      const auto key = keys[u][q];
+      if (key != 0) {  // zero for lanes past k
+        const int d = top_digit<T>(key);
+        keep = s[q].all || d > s[q].b1;
+        if (!s[q].all && d == s[q].b1) {
+          C cd;
+          cd.key = key;
+          cd.row = WHOLE ? static_cast<uint32_t>(r * k + c) : static_cast<uint32_t>(r);
+          wstage[cnt[q] * k + c] = cd;
+          ++cnt[q];
         }
       }
       keep_bits[q] = __ballot(keep);
@@ -215,25 +219,50 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
       const uint32_t word = (lane & 1) ? static_cast<uint32_t>(b >> 32) : static_cast<uint32_t>(b);
       if (word) atomicOr(&a.mask[r * a.mw + lane], word);
     }
-   }
   }
-  __syncthreads();
-  const int nl = WHOLE ? 1 : k;
-  for (int c = threadIdx.x; c < nl; c += 256) {
-    const int n = lcnt[c];
-    lbase[c] = n ? atomicAdd(&a.cand_cnt[c * kCntStride], n) : 0;
+#pragma unroll
+  for (int q = 0; q < KPL; ++q) {
+    const int c = lane + 64 * q;
+    if (c < k) lcnt[wv][c] = cnt[q];
   }
   __syncthreads();
   C* __restrict__ out = static_cast<C*>(a.candA);
   if (WHOLE) {
-    const int n = lcnt[0];
-    for (int i = threadIdx.x; i < n; i += 256) out[lbase[0] + i] = stage[i];
+    // one list: regions in (wave, column) order after one offset for the block
+    int v = 0;
+    for (int f = 2 * threadIdx.x; f < 2 * threadIdx.x + 2; ++f)
+      if (f < 4 * k) v += lcnt[f / k][f % k];
+    int tot;
+    int o = block_excl_scan_256(v, tmp, &tot);
+    for (int f = 2 * threadIdx.x; f < 2 * threadIdx.x + 2; ++f)
+      if (f < 4 * k) {
+        loff[f] = o;
+        o += lcnt[f / k][f % k];
+      }
+    if (threadIdx.x == 0) lbase[0] = tot ? atomicAdd(&a.cand_cnt[0], tot) : 0;
+    __syncthreads();
+    for (int f = wv; f < 4 * k; f += 4) {
+      const int w = f / k, c = f % k;
+      const int n = lcnt[w][c];
+      for (int i = lane; i < n; i += 64) out[lbase[0] + loff[f] + i] = stage[(static_cast<size_t>(w) * kCollectRows + i) * k + c];
+    }
     return;
   }
+  for (int c = threadIdx.x; c < k; c += 256) {
+    const int n = lcnt[0][c] + lcnt[1][c] + lcnt[2][c] + lcnt[3][c];
+    lbase[c] = n ? atomicAdd(&a.cand_cnt[c * kCntStride], n) : 0;
+  }
+  __syncthreads();
+  // per column, lanes span every (wave, slot) pair
   for (int c = wv; c < k; c += 4) {
-    const int n = lcnt[c];
-    for (int i = lane; i < n; i += 64)
-      out[static_cast<int64_t>(c) * a.stride + lbase[c] + i] = stage[c * kRowsPerBlock + i];
+    const int n0 = lcnt[0][c], n1 = lcnt[1][c], n2 = lcnt[2][c];
+    for (int j = lane; j < 4 * kCollectRows; j += 64) {
+      const int w = j / kCollectRows, i = j - w * kCollectRows;
+      const int before = (w > 0 ? n0 : 0) + (w > 1 ? n1 : 0) + (w > 2 ? n2 : 0);
+      if (i < lcnt[w][c])
+        out[static_cast<int64_t>(c) * a.stride + lbase[c] + before + i] =
+            stage[(static_cast<size_t>(w) * kCollectRows + i) * k + c];
+    }
   }
 }
 template <typename T, int KPL, bool WHOLE>

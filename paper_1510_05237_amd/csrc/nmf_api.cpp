@@ -1110,7 +1110,7 @@ nmf_status batch_fail(nmf_batch* b, nmf_status s, const std::string& msg) {
 size_t batch_table_bound(const nmf_config& c, int64_t nnz) {
   const int64_t ch = nnz / kChunk + 2;
   auto sel = [&](int64_t r) { return 2 * ((r + 63) / 64 + 1) + (c.k + 3) / 4 + c.k; };
-  auto rep = [&](int64_t r) { return 2 * ((r + 511) / 512 + 1); };
+  auto rep = [&](int64_t r) { return 2 * ((r + 255) / 256 + 1); };
   const int64_t gram = kGramBlocks + 130 + 1;
   const int64_t blocks = (c.m + 2 * ch + 1) + ch + (c.n + 2 * ch + 1) + ch + sel(c.m) + sel(c.n) + rep(c.m) +
                          rep(c.n) + 2 * gram + kMetricBlocks + 1;
