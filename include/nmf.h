@@ -192,6 +192,13 @@ enum {
  * device memory is allocated. */
 nmf_status nmf_profile(nmf_handle* h, int32_t enable);
 
+/* As nmf_profile, for the stages whose bit is set in `stages` (bit s =
+ * NMF_STAGE_s; 0 disables).  An event is recorded only where a bracketed
+ * stage begins or ends, so the other stages run back to back, as without
+ * profiling (each recorded event delays the next launch by a few
+ * microseconds).  NMF_ERR_INVALID_ARG for bits at or above NMF_NUM_STAGES. */
+nmf_status nmf_profile_stages(nmf_handle* h, uint32_t stages);
+
 /* Summed event time (milliseconds) and number of launches per stage since
  * profiling was enabled; arrays of n_stages entries (<= NMF_NUM_STAGES).
  * Synchronizes. */

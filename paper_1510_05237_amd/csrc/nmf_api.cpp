@@ -280,24 +280,35 @@ nmf_status prof_fold(nmf_handle* h) {
   return NMF_OK;
 }
 
-// Record an event closing `stage` (-1: an opening mark).
-nmf_status prof_mark(nmf_handle* h, int stage) {
+// A mark where stage `closing` ends and stage `next` begins (-1: none).  An
+// event is recorded only where a bracketed stage (one in prof_mask) ends or
+// begins, so unbracketed stages run back to back; an opening mark directly
+// after the mark that already opened the same stage records nothing.
+nmf_status prof_mark(nmf_handle* h, int closing, int next) {
   if (!h->prof_on) return NMF_OK;
+  const bool close = closing >= 0 && ((h->prof_mask >> closing) & 1u);
+  const bool open = next >= 0 && ((h->prof_mask >> next) & 1u);
+  if (closing < 0 && next == h->prof_open) return NMF_OK;
+  if (!close && !open) {
+    h->prof_open = -2;
+    return NMF_OK;
+  }
   if (h->prof_used == kProfPool) {
     nmf_status s = prof_fold(h);
     if (s != NMF_OK) return s;
   }
-  if (h->prof_used == 0) stage = -1;
   HIPCHK(h, hipEventRecord(h->prof_ev[h->prof_used], h->stream));
-  h->prof_stage[h->prof_used] = stage;
+  // an interval counts only when its first event opened the stage it closes
+  h->prof_stage[h->prof_used] = (close && h->prof_used > 0 && h->prof_open == closing) ? closing : -1;
   ++h->prof_used;
+  h->prof_open = open ? next : -2;
   return NMF_OK;
 }
 
-#define PROF(h, st)                          \
-  do {                                       \
-    nmf_status ps_ = prof_mark((h), (st));   \
-    if (ps_ != NMF_OK) return ps_;           \
+#define PROF(h, st, nx)                            \
+  do {                                             \
+    nmf_status ps_ = prof_mark((h), (st), (nx));   \
+    if (ps_ != NMF_OK) return ps_;                 \
   } while (0)
 
 // Load a dense rows x k factor (host or device) into a stored factor.
@@ -343,38 +354,40 @@ nmf_status refresh_max(nmf_handle* h) {
   return NMF_OK;
 }
 
+// `next`: the stage enqueued after this half (-1: none), for the profiling marks.
 template <typename T>
-nmf_status v_half(nmf_handle* h) {
+nmf_status v_half(nmf_handle* h, int next) {
   Factor& U = h->U[h->cur_u];
   T* vpre = static_cast<T*>(h->vpre);
-  PROF(h, -1);
+  PROF(h, -1, NMF_STAGE_SPMM_V);
   HIPCHK(h, spmm<T>(h, h->planAt, U, h->gU.W, vpre, nullptr, false, nullptr, h->sparse_row[0], h->wide[0], h->waves[0]));
-  PROF(h, NMF_STAGE_SPMM_V);
+  PROF(h, NMF_STAGE_SPMM_V, NMF_STAGE_SELECT_V);
   HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
-  PROF(h, NMF_STAGE_SELECT_V);
+  PROF(h, NMF_STAGE_SELECT_V, NMF_STAGE_REPACK_V);
   HIPCHK(h, repack<T>(h, vpre, h->m, h->V, sparse_row_of(h, h->V)));
-  PROF(h, NMF_STAGE_REPACK_V);
+  PROF(h, NMF_STAGE_REPACK_V, NMF_STAGE_GRAM_V);
   HIPCHK(h, gram<T>(h, h->V, h->gV));
-  PROF(h, NMF_STAGE_GRAM_V);
+  PROF(h, NMF_STAGE_GRAM_V, next);
   h->have_v = true;
   h->have_pre_v = true;
   return NMF_OK;
 }
 
 template <typename T>
-nmf_status u_half(nmf_handle* h, bool keep_c) {
+nmf_status u_half(nmf_handle* h, bool keep_c, int next) {
   const int nxt = 1 - h->cur_u;
   Factor& Un = h->U[nxt];
   T* upre = static_cast<T*>(h->upre);
+  PROF(h, -1, NMF_STAGE_SPMM_U);
   HIPCHK(h, spmm<T>(h, h->planA, h->V, h->gV.W, upre, keep_c ? static_cast<T*>(h->cbuf) : nullptr,
                     false, nullptr, h->sparse_row[1], h->wide[1], h->waves[1]));
-  PROF(h, NMF_STAGE_SPMM_U);
+  PROF(h, NMF_STAGE_SPMM_U, NMF_STAGE_SELECT_U);
   HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
-  PROF(h, NMF_STAGE_SELECT_U);
+  PROF(h, NMF_STAGE_SELECT_U, NMF_STAGE_REPACK_U);
   HIPCHK(h, repack<T>(h, upre, h->n, Un, sparse_row_of(h, Un)));
-  PROF(h, NMF_STAGE_REPACK_U);
+  PROF(h, NMF_STAGE_REPACK_U, NMF_STAGE_GRAM_U);
   HIPCHK(h, gram<T>(h, Un, h->gU));
-  PROF(h, NMF_STAGE_GRAM_U);
+  PROF(h, NMF_STAGE_GRAM_U, next);
   h->have_pre_u = true;
   return NMF_OK;
 }
@@ -394,14 +407,15 @@ nmf_status do_steps(nmf_handle* h, int32_t iters) {
     nmf_status s = refresh_w<T>(h);
     if (s != NMF_OK) return s;
   }
+  h->prof_open = -2;
   for (int32_t i = 0; i < iters; ++i) {
-    nmf_status s = v_half<T>(h);
+    nmf_status s = v_half<T>(h, NMF_STAGE_SPMM_U);
     if (s != NMF_OK) return s;
-    s = u_half<T>(h, rec);
+    s = u_half<T>(h, rec, NMF_STAGE_METRICS);
     if (s != NMF_OK) return s;
     const int nxt = 1 - h->cur_u;
     HIPCHK(h, metrics<T>(h, h->U[nxt], h->U[h->cur_u], rec ? static_cast<T*>(h->cbuf) : nullptr, rec));
-    PROF(h, NMF_STAGE_METRICS);
+    PROF(h, NMF_STAGE_METRICS, i + 1 < iters ? NMF_STAGE_SPMM_V : -1);
     h->cur_u = nxt;
     ++h->iters_done;
     h->metrics_valid = rec;
@@ -563,6 +577,7 @@ nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
   const int k = h->k;
   const int eta = k / k2;
   const bool rec = !(h->cfg.flags & NMF_FLAG_NO_METRICS);
+  h->prof_open = -2;
   T* upre = static_cast<T*>(h->upre);
   T* vpre = static_cast<T*>(h->vpre);
   T* C = static_cast<T*>(h->cbuf);
@@ -585,32 +600,32 @@ nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
       const int nxt = 1 - h->cur_u;
       Factor& Un = h->U[nxt];
       // V half: V2 = (A^T U2 - V1 U1^T U2) (U2^T U2)^-1
-      PROF(h, -1);
+      PROF(h, -1, NMF_STAGE_SPMM_V);
       HIPCHK(h, spmm<T>(h, h->planAt, Uo, nullptr, vpre, nullptr, true, nullptr, h->sparse_row[0]));
       HIPCHK(h, block_inverse(h, h->gU.G, k1, k2, Gb, W22, h->scratch_i));
       HIPCHK(h, seq_solve<T>(h, vpre, vpre, h->m, h->V, h->gU.G, W22, k1, k2));
-      PROF(h, NMF_STAGE_SPMM_V);
+      PROF(h, NMF_STAGE_SPMM_V, NMF_STAGE_SELECT_V);
       HIPCHK(h, select_topt<T>(h, vpre, h->m, h->cfg.t_v, h->cfg.mode, h->V));
-      PROF(h, NMF_STAGE_SELECT_V);
+      PROF(h, NMF_STAGE_SELECT_V, NMF_STAGE_REPACK_V);
       HIPCHK(h, repack<T>(h, vpre, h->m, h->V, sparse_row_of(h, h->V)));
-      PROF(h, NMF_STAGE_REPACK_V);
+      PROF(h, NMF_STAGE_REPACK_V, NMF_STAGE_GRAM_V);
       HIPCHK(h, gram_plain<T>(h, h->V, h->gV.G));
       HIPCHK(h, seq_max(h, Uo, h->V));
-      PROF(h, NMF_STAGE_GRAM_V);
+      PROF(h, NMF_STAGE_GRAM_V, NMF_STAGE_SPMM_U);
       // U half: U2 = (A V2 - U1 V1^T V2) (V2^T V2)^-1
       HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr, h->sparse_row[1]));
       HIPCHK(h, block_inverse(h, h->gV.G, k1, k2, Gb, W22, h->scratch_i));
       HIPCHK(h, seq_solve<T>(h, C, upre, h->n, Uo, h->gV.G, W22, k1, k2));
-      PROF(h, NMF_STAGE_SPMM_U);
+      PROF(h, NMF_STAGE_SPMM_U, NMF_STAGE_SELECT_U);
       HIPCHK(h, select_topt<T>(h, upre, h->n, h->cfg.t_u, h->cfg.mode, Un));
-      PROF(h, NMF_STAGE_SELECT_U);
+      PROF(h, NMF_STAGE_SELECT_U, NMF_STAGE_REPACK_U);
       HIPCHK(h, repack<T>(h, upre, h->n, Un, sparse_row_of(h, Un)));
-      PROF(h, NMF_STAGE_REPACK_U);
+      PROF(h, NMF_STAGE_REPACK_U, NMF_STAGE_GRAM_U);
       HIPCHK(h, gram_plain<T>(h, Un, h->gU.G));
       HIPCHK(h, seq_max(h, Un, h->V));
-      PROF(h, NMF_STAGE_GRAM_U);
+      PROF(h, NMF_STAGE_GRAM_U, NMF_STAGE_METRICS);
       HIPCHK(h, metrics<T>(h, Un, Uo, C, rec));
-      PROF(h, NMF_STAGE_METRICS);
+      PROF(h, NMF_STAGE_METRICS, it + 1 < iters ? NMF_STAGE_SPMM_V : -1);
       h->cur_u = nxt;
       ++h->iters_done;
       h->have_v = h->have_pre_v = h->have_pre_u = true;
@@ -721,10 +736,11 @@ nmf_status nmf_half_step(nmf_handle* h, int32_t which) {
   if (which == 1 && !h->have_v) return fail(h, NMF_ERR_STATE, "no V yet");
   nmf_status s = h->elt == 8 ? refresh_w<double>(h) : refresh_w<float>(h);
   if (s != NMF_OK) return s;
+  h->prof_open = -2;
   if (which == 0) {
-    s = h->elt == 8 ? v_half<double>(h) : v_half<float>(h);
+    s = h->elt == 8 ? v_half<double>(h, -1) : v_half<float>(h, -1);
   } else {
-    s = h->elt == 8 ? u_half<double>(h, false) : u_half<float>(h, false);
+    s = h->elt == 8 ? u_half<double>(h, false, -1) : u_half<float>(h, false, -1);
     if (s == NMF_OK) h->cur_u = 1 - h->cur_u;
   }
   h->metrics_valid = false;
@@ -1014,7 +1030,12 @@ nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value) {
 }
 
 nmf_status nmf_profile(nmf_handle* h, int32_t enable) {
+  return nmf_profile_stages(h, enable != 0 ? (1u << NMF_NUM_STAGES) - 1u : 0u);
+}
+
+nmf_status nmf_profile_stages(nmf_handle* h, uint32_t stages) {
   if (h == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "handle is NULL");
+  if (stages >> NMF_NUM_STAGES) return fail(h, NMF_ERR_INVALID_ARG, "unknown stage bit");
   if (h->prof_ev.empty()) {
     h->prof_ev.resize(kProfPool);
     h->prof_stage.resize(kProfPool, -1);
@@ -1022,7 +1043,9 @@ nmf_status nmf_profile(nmf_handle* h, int32_t enable) {
   }
   nmf_status s = prof_fold(h);
   if (s != NMF_OK) return s;
-  h->prof_on = enable != 0;
+  h->prof_on = stages != 0;
+  h->prof_mask = stages;
+  h->prof_open = -2;
   if (h->prof_on)
     for (int i = 0; i < NMF_NUM_STAGES; ++i) {
       h->prof_ms[i] = 0;

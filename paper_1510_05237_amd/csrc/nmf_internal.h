@@ -206,6 +206,8 @@ struct nmf_handle {
   int waves[2] = {16, 8};                     // NMF_PARAM_WAVES_V / _U: waves per SpMM block
   // stage timing (nmf_profile)
   bool prof_on = false;
+  uint32_t prof_mask = 0;               // stages bracketed while prof_on (bit s = stage s)
+  int prof_open = -2;                   // stage the last mark opened (-2: none)
   std::vector<hipEvent_t> prof_ev;      // pool
   std::vector<int> prof_stage;          // stage of the interval ending at event i
   size_t prof_used = 0;

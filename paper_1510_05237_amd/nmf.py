@@ -91,6 +91,7 @@ SIGNATURES = {
     "nmf_loss_bwd": (_I32, [_P, _P, _P, _P, _P, _P]),
     "nmf_set_param": (_I32, [_P, _I32, _I64]),
     "nmf_profile": (_I32, [_P, _I32]),
+    "nmf_profile_stages": (_I32, [_P, ctypes.c_uint32]),
     "nmf_profile_read": (_I32, [_P, _P, _P, _I32]),
     "nmf_last_error": (ctypes.c_char_p, [_P]),
     "nmf_destroy": (None, [_P]),
@@ -283,6 +284,14 @@ def nmf_profile(h: int, enable: bool):
     _check(load_library().nmf_profile(h, 1 if enable else 0), h)
 
 
+def nmf_profile_stages(h: int, stages):
+    """Bracket only the named stages (names from STAGE_NAMES) with events."""
+    mask = 0
+    for s in stages:
+        mask |= 1 << STAGE_NAMES.index(s)
+    _check(load_library().nmf_profile_stages(h, mask), h)
+
+
 def nmf_profile_read(h: int):
     ms = np.zeros(NMF_NUM_STAGES, np.float64)
     cnt = np.zeros(NMF_NUM_STAGES, np.int64)
@@ -466,8 +475,13 @@ class NMF:
         """Apply the top-t rule once to the current U and V."""
         nmf_enforce(self.h, _MODES[mode], t_u, t_v)
 
-    def profile(self, enable: bool):
-        nmf_profile(self.h, enable)
+    def profile(self, enable: bool, stages=None):
+        """Bracket every stage (or only `stages`, a list of STAGE_NAMES) with
+        HIP events while enabled."""
+        if enable and stages is not None:
+            nmf_profile_stages(self.h, stages)
+        else:
+            nmf_profile(self.h, enable)
 
     def profile_read(self):
         return nmf_profile_read(self.h)
