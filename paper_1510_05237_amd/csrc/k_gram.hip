@@ -363,6 +363,178 @@ __global__ __launch_bounds__(kFactorThreads) void k_gram_factor_b(const GramArgs
 }
 
 
+// Blocked form for k <= 64: the pivots are swept four at a time.  Sweeping a
+// pivot set P at once (B = a_PP, positive definite as a Schur complement of
+// G) maps a to b with
+//   b_PP = -B^-1,  b_Pj = B^-1 a_Pj,  b_iP = a_iP B^-1,
+//   b_ij = a_ij - a_iP B^-1 a_Pj            (i, j not in P),
+// the same matrix as sweeping P's pivots one at a time, and its pivots are
+// the same Schur complement diagonals (checked the same way).  Wave w owns
+// rows 4w..4w+3 of the 64 x 64 register matrix, lane = column.  The wave
+// that owns the next block reads its 4 x 4 diagonal block across lanes,
+// sweeps it in registers (b = -B^-1), forms T = B^-1 a_P. for every column
+// and publishes a_P. and T; by symmetry (a_iP = a_Pi) every other wave's
+// update needs only these, so a block of four pivots takes one barrier.
+constexpr int kPiv = 4;
+
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b)), src));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b >> 32)), src));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// The owner wave of block j: sweep its diagonal block (rows/columns
+// p0..p0+bs-1) into b = -B^-1, then T[q] = (B^-1 a_P.)[q][c] for its lane's
+// column; publishes a_P. (its rows as they stand) and T.  Returns false on a
+// pivot that is not positive.
+__device__ __forceinline__ bool block_pivot(const double (&e)[kPiv], int p0, int bs, double (&b)[kPiv][kPiv],
+                                            double (&t)[kPiv], double (*rs)[kPiv], double (*ts)[kPiv], int c) {
+#pragma unroll
+  for (int q = 0; q < kPiv; ++q)
+#pragma unroll
+    for (int l = 0; l < kPiv; ++l) b[q][l] = lane_read(e[q], p0 + l);
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < kPiv; ++p) {
+    if (p >= bs) break;
+    const double d = b[p][p];
+    ok = ok && d > 0.0;
+    const double ip = 1.0 / d;
+    double rp[kPiv];
+#pragma unroll
+    for (int l = 0; l < kPiv; ++l) rp[l] = b[p][l] * ip;
+#pragma unroll
+    for (int i = 0; i < kPiv; ++i) {
+      if (i == p) continue;
+      const double aip = b[i][p];
+#pragma unroll
+      for (int l = 0; l < kPiv; ++l)
+        if (l != p) b[i][l] = fma(-aip, rp[l], b[i][l]);
+      b[i][p] = aip * ip;
+    }
+#pragma unroll
+    for (int l = 0; l < kPiv; ++l)
+      if (l != p) b[p][l] = rp[l];
+    b[p][p] = -ip;
+  }
+  // rows/columns of the block past bs are zero padding and stay zero
+#pragma unroll
+  for (int q = 0; q < kPiv; ++q) {
+    double v = 0.0;
+#pragma unroll
+    for (int l = 0; l < kPiv; ++l) v = fma(-b[q][l], e[l], v);
+    t[q] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < kPiv; ++q) {
+    rs[c][q] = e[q];
+    ts[c][q] = t[q];
+  }
+  return ok;
+}
+
+__device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, int nblk) {
+  constexpr int KM = 64;
+  static_assert(KM / kPiv * 64 == kFactorThreads, "one wave per block of four rows");
+  __shared__ double rs[2][KM][kPiv];  // rs[.][c][l] = a_{p0+l, c}
+  __shared__ double ts[2][KM][kPiv];  // ts[.][c][q] = (B^-1 a_P.)[q][c]
+  __shared__ int s_dead[KM];
+  __shared__ int s_nd, s_bad;
+  if (*g.status != 0) return;
+  const int k = g.k;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_nd = 0;
+    s_bad = 0;
+    if (g.max_nnz) {
+      const int64_t cur = static_cast<int64_t>(*g.counts_a) + (g.counts_b ? *g.counts_b : 0);
+      if (cur > *g.max_nnz) *g.max_nnz = cur;
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < KM; c += kFactorThreads) {
+    const int d = c < k && g.G[c * k + c] == 0.0;
+    s_dead[c] = d;
+    if (d) atomicAdd(&s_nd, 1);
+  }
+  __syncthreads();
+  if (tid == 0) *g.dead = s_nd;
+  const int c = lane_id();
+  const int wv = tid >> 6;  // owns rows kPiv * wv ...
+  double e[kPiv];
+#pragma unroll
+  for (int q = 0; q < kPiv; ++q) {
+    const int i = kPiv * wv + q;
+    double v = 0.0;
+    if (i < k && c < k) v = (s_dead[i] || s_dead[c]) ? (i == c ? 1.0 : 0.0) : g.G[i * k + c];
+    e[q] = v;
+  }
+  const int nbk = (k + kPiv - 1) / kPiv;
+  double b[kPiv][kPiv], t[kPiv];
+  if (wv == 0 && !block_pivot(e, 0, k < kPiv ? k : kPiv, b, t, rs[0], ts[0], c) && c == 0) s_bad = 1;
+  __syncthreads();
+  for (int j = 0; j < nbk; ++j) {
+    const int buf = j & 1;
+    const int p0 = kPiv * j;
+    const int bs = k - p0 < kPiv ? k - p0 : kPiv;
+    const bool cp = c >= p0 && c < p0 + bs;
+    const int m = (c - p0) & (kPiv - 1);
+    if (wv == j) {
+      // the block's own rows: -B^-1 inside the block, T elsewhere
+#pragma unroll
+      for (int q = 0; q < kPiv; ++q) {
+        if (q >= bs) break;
+        double w = b[q][0];
+#pragma unroll
+        for (int l = 1; l < kPiv; ++l)
+          if (m == l) w = b[q][l];
+        e[q] = cp ? w : t[q];
+      }
+    } else if (wv < nbk) {
+      const double t0 = ts[buf][c][0], t1 = ts[buf][c][1], t2 = ts[buf][c][2], t3 = ts[buf][c][3];
+#pragma unroll
+      for (int q = 0; q < kPiv; ++q) {
+        const int i = kPiv * wv + q;
+        if (cp) {
+          e[q] = ts[buf][i][m];  // a_iP B^-1 = (B^-1 a_Pi)^T by symmetry
+        } else {
+          double v = e[q];
+          v = fma(-rs[buf][i][0], t0, v);
+          v = fma(-rs[buf][i][1], t1, v);
+          v = fma(-rs[buf][i][2], t2, v);
+          v = fma(-rs[buf][i][3], t3, v);
+          e[q] = v;
+        }
+      }
+    }
+    if (wv == j + 1 && j + 1 < nbk) {
+      const int n0 = p0 + kPiv;
+      if (!block_pivot(e, n0, k - n0 < kPiv ? k - n0 : kPiv, b, t, rs[buf ^ 1], ts[buf ^ 1], c) && c == 0) s_bad = 1;
+    }
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (tid == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
+    for (int x = tid; x < k * k; x += kFactorThreads) g.W[x] = 0.0;
+    return;
+  }
+  if (c < k) {
+#pragma unroll
+    for (int q = 0; q < kPiv; ++q) {
+      const int i = kPiv * wv + q;
+      if (i < k) g.W[i * k + c] = -e[q];
+    }
+  }
+}
+__global__ __launch_bounds__(kFactorThreads) void k_gram_block(GramArgs g) { k_gram_block_body(g, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kFactorThreads) void k_gram_block_b(const GramArgs* as, const BlockMap* map) {
+  const BlockMap m = map[blockIdx.x];
+  const GramArgs g = as[m.prob];
+  k_gram_block_body(g, m.blk, m.nblk);
+}
+
+
 template <typename T>
 hipError_t launch(nmf_handle* h, GramArgs& g, int64_t rows_bound) {
   const int k = h->k;
@@ -389,8 +561,7 @@ hipError_t launch(nmf_handle* h, GramArgs& g, int64_t rows_bound) {
   const unsigned rblocks = static_cast<unsigned>((ne + kReduceEntries - 1) / kReduceEntries);
   if ((e = launch_rec(h, k_gram_reduce<T>, k_gram_reduce_b<T>, rblocks, 256, 0, g)) != hipSuccess) return e;
   if (!g.W) return hipSuccess;
-  if (k <= 32) return launch_rec(h, k_gram_factor<32>, k_gram_factor_b<32>, 1, kFactorThreads, 0, g);
-  if (k <= 64) return launch_rec(h, k_gram_factor<64>, k_gram_factor_b<64>, 1, kFactorThreads, 0, g);
+  if (k <= 64) return launch_rec(h, k_gram_block, k_gram_block_b, 1, kFactorThreads, 0, g);
   return launch_rec(h, k_gram_factor<128>, k_gram_factor_b<128>, 1, kFactorThreads, 0, g);
 }
 
@@ -469,10 +640,8 @@ hipError_t block_inverse(nmf_handle* h, const double* G, int k1, int k2, double*
   g.k = k2;
   g.dead = dead;
   g.status = h->status;
-  if (k2 <= 32)
-    hipLaunchKernelGGL(k_gram_factor<32>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
-  else if (k2 <= 64)
-    hipLaunchKernelGGL(k_gram_factor<64>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+  if (k2 <= 64)
+    hipLaunchKernelGGL(k_gram_block, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
   else
     hipLaunchKernelGGL(k_gram_factor<128>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
   return hipGetLastError();
