@@ -35,7 +35,7 @@ namespace nmfk {
 
 namespace {
 
-constexpr int kRowsPerBlock = 64;  // rows of X per hist/collect block
+constexpr int kRowsPerBlock = kSelBlockRows;  // rows of X per hist/collect block
 constexpr int kPadBins = kBins + 1;
 constexpr int kFinish = 64;  // candidates ranked directly by one wave
 constexpr int kHistRows = 8;                       // rows in flight per wave in k_hist
@@ -52,7 +52,8 @@ struct SelArgs {
   int32_t hist_rows;  // rows of X per hist block
   uint32_t* hist;
   ColSel* sel;
-  int32_t* cand_cnt;  // padded: column c at cand_cnt[c * kCntStride]
+  int32_t* cand_cnt;  // column c, sub-list s at cand_cnt[(c * kSelSub + s) * kCntStride]
+  int64_t sub;        // entries per sub-list
   void* candA;
   void* candB;
   int64_t stride;
@@ -148,9 +149,11 @@ __global__ __launch_bounds__(256) void k_pick_b(const SelArgs* as, const BlockMa
 
 // Candidates are staged per (wave, column): a lane owns its column's slots
 // in its wave's region (at most kCollectRows, one per row the wave reads), so
-// staging needs no atomics; the block then takes one global offset per
-// column (one for the single list of the whole-matrix form) and copies its
-// regions out in wave order.
+// staging needs no atomics.  Block b then appends its regions, in wave order,
+// to sub-list b % kSelSub of each column (of the one list in the
+// whole-matrix form) with one atomic per column; spreading the blocks over
+// kSelSub counters keeps them from queueing on one address.  k_refine
+// concatenates the sub-lists.
 template <typename T, int KPL, bool WHOLE>
 __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nblk) {
   using KO = KeyOf<T>;
@@ -239,18 +242,19 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
         loff[f] = o;
         o += lcnt[f / k][f % k];
       }
-    if (threadIdx.x == 0) lbase[0] = tot ? atomicAdd(&a.cand_cnt[0], tot) : 0;
+    if (threadIdx.x == 0) lbase[0] = tot ? atomicAdd(&a.cand_cnt[(blk % kSelSub) * kCntStride], tot) : 0;
     __syncthreads();
+    C* mine = out + (blk % kSelSub) * a.sub * k + lbase[0];
     for (int f = wv; f < 4 * k; f += 4) {
       const int w = f / k, c = f % k;
       const int n = lcnt[w][c];
-      for (int i = lane; i < n; i += 64) out[lbase[0] + loff[f] + i] = stage[(static_cast<size_t>(w) * kCollectRows + i) * k + c];
+      for (int i = lane; i < n; i += 64) mine[loff[f] + i] = stage[(static_cast<size_t>(w) * kCollectRows + i) * k + c];
     }
     return;
   }
   for (int c = threadIdx.x; c < k; c += 256) {
     const int n = lcnt[0][c] + lcnt[1][c] + lcnt[2][c] + lcnt[3][c];
-    lbase[c] = n ? atomicAdd(&a.cand_cnt[c * kCntStride], n) : 0;
+    lbase[c] = n ? atomicAdd(&a.cand_cnt[(c * kSelSub + blk % kSelSub) * kCntStride], n) : 0;
   }
   __syncthreads();
   // per column, lanes span every (wave, slot) pair
@@ -260,7 +264,7 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
       const int w = j / kCollectRows, i = j - w * kCollectRows;
       const int before = (w > 0 ? n0 : 0) + (w > 1 ? n1 : 0) + (w > 2 ? n2 : 0);
       if (i < lcnt[w][c])
-        out[static_cast<int64_t>(c) * a.stride + lbase[c] + before + i] =
+        out[static_cast<int64_t>(c) * a.stride + (blk % kSelSub) * a.sub + lbase[c] + before + i] =
             stage[(static_cast<size_t>(w) * kCollectRows + i) * k + c];
     }
   }
@@ -307,19 +311,53 @@ __device__ __forceinline__ void k_refine_body(const SelArgs& a, int blk, int nbl
   using C = Cand<T>;
   __shared__ uint32_t h[kBins];
   __shared__ int s_bin, s_need, s_n, s_cnt;
-  if (*a.status != 0) return;
+  __shared__ int s_off[kSelSub + 1];
   const int c = blk;
   const int tid = threadIdx.x;
-  const ColSel s = a.sel[c];
-  int* cnt_ptr = &a.cand_cnt[c * kCntStride];
-  if (s.all || s.need <= 0) {
-    if (tid == 0) *cnt_ptr = 0;
-    return;
+  // the sub-list counters: read, then cleared for the next selection (also
+  // after an error, so that no later selection appends past a sub-list)
+  int32_t* cnt = a.cand_cnt + static_cast<int64_t>(c) * kSelSub * kCntStride;
+  if (tid == 0) {
+    int o = 0;
+    for (int q = 0; q < kSelSub; ++q) {
+      s_off[q] = o;
+      o += cnt[q * kCntStride];
+    }
+    s_off[kSelSub] = o;
   }
-  int n = __hip_atomic_load(cnt_ptr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (tid < kSelSub) cnt[tid * kCntStride] = 0;
+  if (*a.status != 0) return;
+  const ColSel s = a.sel[c];
+  if (s.all || s.need <= 0) return;
   int need = s.need;
-  C* src = static_cast<C*>(a.candA) + static_cast<int64_t>(c) * a.stride;
-  C* dst = static_cast<C*>(a.candB) + static_cast<int64_t>(c) * a.stride;
+  int n = s_off[kSelSub];
+  // concatenate the sub-lists (sub-list q holds entries [s_off[q], s_off[q+1])
+  // of the whole list), four entries in flight per thread
+  C* lists = static_cast<C*>(a.candA) + static_cast<int64_t>(c) * a.stride;
+  C* src = static_cast<C*>(a.candB) + static_cast<int64_t>(c) * a.stride;
+  C* dst = lists;
+  {
+    const int64_t sub = a.flat_k > 0 ? a.sub * a.flat_k : a.sub;
+    const int NT = blockDim.x;
+    for (int i0 = tid; i0 < n; i0 += 4 * NT) {
+      C v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * NT;
+        if (i < n) {
+          int q = 0;
+#pragma unroll
+          for (int x = 1; x < kSelSub; ++x) q += i >= s_off[x] ? 1 : 0;
+          v[u] = lists[q * sub + (i - s_off[q])];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (i0 + u * NT < n) src[i0 + u * NT] = v[u];
+    }
+    __syncthreads();
+  }
   int kb = KeyOf<T>::bits - 9;
   int rb = 32;
   while (n > kFinish && (kb > 0 || rb > 0)) {
@@ -408,7 +446,6 @@ __device__ __forceinline__ void k_refine_body(const SelArgs& a, int blk, int nbl
       rank += cand_before<T>(o, me) ? 1 : 0;
     }
     if (tid < n && rank < need) mark_cand(a, me.row, c);
-    if (tid == 0) *cnt_ptr = 0;
   }
 }
 template <typename T>
@@ -462,6 +499,7 @@ hipError_t select_topt(nmf_handle* h, const T* X, int64_t rows, int64_t t, int m
   a.hist = h->sel.hist;
   a.sel = h->sel.sel;
   a.cand_cnt = h->sel.cand_cnt;
+  a.sub = h->sel.cand_sub;
   a.candA = h->sel.candA;
   a.candB = h->sel.candB;
   a.stride = h->sel.cand_stride;

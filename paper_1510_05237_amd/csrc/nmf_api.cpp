@@ -181,10 +181,14 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
   h->lossC = cv.take<char>(n * k * elt);
   h->sel.hist = cv.take<uint32_t>(static_cast<size_t>(k) * kBins);
   h->sel.sel = cv.take<ColSel>(k);
-  h->sel.cand_cnt = cv.take<int32_t>(static_cast<size_t>(k) * kCntStride);
-  h->sel.cand_stride = rmax;
-  h->sel.candA = cv.take<char>(static_cast<size_t>(k) * rmax * cand);
-  h->sel.candB = cv.take<char>(static_cast<size_t>(k) * rmax * cand);
+  // candidate lists: per column kSelSub sub-lists, each with room for all
+  // the candidates of the collect blocks that append to it
+  const int64_t nsel = (rmax + kSelBlockRows - 1) / kSelBlockRows;
+  h->sel.cand_sub = (nsel + kSelSub - 1) / kSelSub * kSelBlockRows;
+  h->sel.cand_stride = kSelSub * h->sel.cand_sub;
+  h->sel.cand_cnt = cv.take<int32_t>(static_cast<size_t>(k) * kSelSub * kCntStride);
+  h->sel.candA = cv.take<char>(static_cast<size_t>(k) * h->sel.cand_stride * cand);
+  h->sel.candB = cv.take<char>(static_cast<size_t>(k) * h->sel.cand_stride * cand);
   h->sel.mask = cv.take<uint32_t>(rmax * mw);
   h->sel.ticket = cv.take<int32_t>(16);
   h->sel.scan_part = cv.take<int32_t>(2 * ((rmax + 255) / 256 + 1));
@@ -509,7 +513,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   // state that must start at zero
   const int k = h->k;
   HIPCHK(h, hipMemset(h->sel.hist, 0, static_cast<size_t>(k) * kBins * 4));
-  HIPCHK(h, hipMemset(h->sel.cand_cnt, 0, static_cast<size_t>(k) * kCntStride * 4));
+  HIPCHK(h, hipMemset(h->sel.cand_cnt, 0, static_cast<size_t>(k) * kSelSub * kCntStride * 4));
   HIPCHK(h, hipMemset(h->sel.mask, 0, static_cast<size_t>(std::max(n, m)) * h->mask_words * 4));
   HIPCHK(h, hipMemset(h->sel.ticket, 0, 16 * 4));
   HIPCHK(h, hipMemset(h->gram_ticket, 0, 16));

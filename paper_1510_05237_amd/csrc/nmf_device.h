@@ -56,10 +56,11 @@ __device__ __forceinline__ bool cand_before(const Cand<T>& a, const Cand<T>& b) 
   return a.key > b.key || (a.key == b.key && a.row < b.row);
 }
 
-// Block-wide exclusive scan of one int per thread (blockDim.x == 256).
-// `tmp` must hold 256/64 = 4 ints of shared memory.  Returns the exclusive
-// prefix; *total receives the block total.
-__device__ __forceinline__ int block_excl_scan_256(int v, int* tmp, int* total) {
+// Block-wide exclusive scan of one int per thread over NW waves (blockDim.x
+// == 64 * NW).  `tmp` must hold NW ints of shared memory.  Returns the
+// exclusive prefix; *total receives the block total.
+template <int NW>
+__device__ __forceinline__ int block_excl_scan(int v, int* tmp, int* total) {
   const int lane = __lane_id();
   const int wv = threadIdx.x >> 6;
   // inclusive scan inside the wave
@@ -73,7 +74,7 @@ __device__ __forceinline__ int block_excl_scan_256(int v, int* tmp, int* total) 
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < NW; ++w) {
     int s = tmp[w];
     if (w < wv) off += s;
     tot += s;
@@ -81,6 +82,12 @@ __device__ __forceinline__ int block_excl_scan_256(int v, int* tmp, int* total) 
   __syncthreads();
   *total = tot;
   return off + x - v;
+}
+__device__ __forceinline__ int block_excl_scan_256(int v, int* tmp, int* total) {
+  return block_excl_scan<4>(v, tmp, total);
+}
+__device__ __forceinline__ int block_excl_scan_1024(int v, int* tmp, int* total) {
+  return block_excl_scan<16>(v, tmp, total);
 }
 
 // Radix-select step on one wave: given the 256-bin histogram of the

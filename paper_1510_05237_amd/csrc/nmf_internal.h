@@ -24,7 +24,9 @@ constexpr int kBins = 256;       // radix digit width of the top-t select (8 bit
 constexpr int kHistRing = 4096;  // iterations kept in the device history ring
 constexpr int kGramBlocks = 240; // Gram partial blocks (fixed: deterministic sums)
 constexpr int kMetricBlocks = 1024;
-constexpr int kCntStride = 32;  // ints between per-column counters (one 128-byte line each)
+constexpr int kSelBlockRows = 64;  // rows of the selected matrix per select collect block
+constexpr int kSelSub = 16;        // candidate sub-lists per column (collect block b appends to b % 16)
+constexpr int kCntStride = 64;     // ints between candidate counters (256 bytes)
 
 // History record fields (float64 each).
 enum { H_E = 0, H_R, H_NNZU, H_NNZV, H_DEADU, H_DEADV, H_FIELDS };
@@ -113,7 +115,8 @@ struct ColSel {
 struct SelectWs {
   uint32_t* hist = nullptr;     // [k][kBins], zero between uses (cleared by refine)
   ColSel* sel = nullptr;        // [k]
-  int32_t* cand_cnt = nullptr;  // [k * kCntStride], zero between uses
+  int32_t* cand_cnt = nullptr;  // [k][kSelSub] counters kCntStride ints apart, zero between uses
+  int64_t cand_sub = 0;         // entries per sub-list (per column)
   void* candA = nullptr;        // [k][rows_max] candidates (row, key)
   void* candB = nullptr;        // [k][rows_max] ping-pong buffer
   int64_t cand_stride = 0;      // entries per column
