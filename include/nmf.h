@@ -69,7 +69,11 @@ enum { NMF_F32 = 0, NMF_F64 = 1 };
 
 /* nmf_config.flags */
 enum {
-  NMF_FLAG_NO_METRICS = 1 /* skip the per-iteration E and R (history keeps nnz) */
+  NMF_FLAG_NO_METRICS = 1, /* skip the per-iteration E and R (history keeps nnz) */
+  NMF_FLAG_NO_HOT = 2      /* keep every term in the V-half sparse stream (float32:
+                              by default the densest terms' nonzeros are stored as
+                              a dense block multiplied on the matrix cores; the
+                              results agree to float32 rounding) */
 };
 
 typedef struct {

@@ -149,6 +149,11 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
   h->planAt.rowptr = cv.take<int64_t>(m + 1);
   h->planAt.col = cv.take<int32_t>(nnz);
   h->planAt.val = cv.take<char>(nnz * elt);
+  if (c.dtype == NMF_F32) {
+    const int hot_max = static_cast<int>(std::min<int64_t>(kMaxHot, (n + 15) / 16 * 16));
+    h->planAt.hot_col = cv.take<int32_t>(kMaxHot);
+    h->planAt.hot = cv.take<char>(m * hot_max * elt);
+  }
   for (int o = 0; o < 2; ++o) {
     Plan& p = o == 0 ? h->planA : h->planAt;
     const PlanSizes& s = o == 0 ? pa : pt;
@@ -466,20 +471,46 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   bool any_pos = false;
   if (!values_ok(val, nnz, &any_pos)) return fail(h, NMF_ERR_INVALID_INPUT, "A has a negative or non-finite value");
   if (!any_pos) return fail(h, NMF_ERR_INVALID_INPUT, "||A|| = 0");
-  // transpose (stable counting sort: rows ascending within each column)
+  // hot terms (float32): rows of A with at least kHotDensity * m nonzeros,
+  // most nonzeros first (ties: lower row), at most kMaxHot; their entries
+  // leave the V-half stream for a dense docs x hot block
+  std::vector<int32_t> hot;
+  if (sizeof(T) == 4 && h->k <= 64 && !(h->cfg.flags & NMF_FLAG_NO_HOT)) {
+    const int64_t need = std::max<int64_t>(kHotMinNnz, static_cast<int64_t>(std::ceil(kHotDensity * m)));
+    for (int64_t i = 0; i < n; ++i)
+      if (rp[i + 1] - rp[i] >= need) hot.push_back(static_cast<int32_t>(i));
+    std::stable_sort(hot.begin(), hot.end(),
+                     [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    if (hot.size() > static_cast<size_t>(kMaxHot)) hot.resize(kMaxHot);
+  }
+  const int n_hot = static_cast<int>(hot.size());
+  const int hot_ld = (n_hot + 15) / 16 * 16;
+  std::vector<int32_t> hot_of(n_hot ? n : 0, -1);
+  for (int x = 0; x < n_hot; ++x) hot_of[hot[x]] = x;
+  std::vector<T> hot_block(static_cast<size_t>(n_hot ? m : 0) * hot_ld, T(0));
+  // transpose of the rest (stable counting sort: rows ascending within each column)
   std::vector<int64_t> cp(m + 1, 0);
-  for (int64_t p = 0; p < nnz; ++p) ++cp[col[p] + 1];
+  for (int64_t i = 0; i < n; ++i)
+    if (!n_hot || hot_of[i] < 0)
+      for (int64_t p = rp[i]; p < rp[i + 1]; ++p) ++cp[col[p] + 1];
   for (int64_t j = 0; j < m; ++j) cp[j + 1] += cp[j];
-  std::vector<int32_t> crow(nnz);
-  std::vector<T> cval(nnz);
+  const int64_t nnz_t = cp[m];
+  std::vector<int32_t> crow(nnz_t);
+  std::vector<T> cval(nnz_t);
   {
     std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < n; ++i) {
+      const int x = n_hot ? hot_of[i] : -1;
       for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+        if (x >= 0) {
+          hot_block[static_cast<size_t>(col[p]) * hot_ld + x] = val[p];
+          continue;
+        }
         const int64_t q = cur[col[p]]++;
         crow[q] = static_cast<int32_t>(i);
         cval[q] = val[p];
       }
+    }
   }
   // rows per light item = the epilogue row group of the SpMM instantiation
   const int group = spmm_row_group(h->k);
@@ -508,8 +539,14 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   HIPCHK(h, hipMemcpy(h->planAt.rowptr, cp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.val, val, nnz * sizeof(T), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz_t * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz_t * sizeof(T), hipMemcpyHostToDevice));
+  h->planAt.n_hot = n_hot;
+  h->planAt.hot_ld = hot_ld;
+  if (n_hot) {
+    HIPCHK(h, hipMemcpy(h->planAt.hot_col, hot.data(), n_hot * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->planAt.hot, hot_block.data(), hot_block.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
   // state that must start at zero
   const int k = h->k;
   HIPCHK(h, hipMemset(h->sel.hist, 0, static_cast<size_t>(k) * kBins * 4));
@@ -1140,8 +1177,8 @@ size_t batch_table_bound(const nmf_config& c, int64_t nnz) {
   auto rep = [&](int64_t r) { return 2 * ((r + 255) / 256 + 1); };
   const int64_t gram = kGramBlocks + 130 + 1;
   const int64_t blocks = (c.m + 2 * ch + 1) + ch + (c.n + 2 * ch + 1) + ch + sel(c.m) + sel(c.n) + rep(c.m) +
-                         rep(c.n) + 2 * gram + kMetricBlocks + 1;
-  const int64_t launches = 40;
+                         rep(c.n) + 2 * gram + kMetricBlocks + 1 + (c.m + 63) / 64 + 1;
+  const int64_t launches = 48;
   return 2 * (static_cast<size_t>(blocks) * sizeof(BlockMap) + launches * (512 + 512));
 }
 

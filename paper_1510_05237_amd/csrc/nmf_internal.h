@@ -14,6 +14,9 @@
 namespace nmfk {
 
 constexpr int kMaxK = 128;       // topics supported (2 per lane at most)
+constexpr int kMaxHot = 128;     // most hot columns split off the V-half stream (float32)
+constexpr double kHotDensity = 0.125;  // a hot column holds at least this share of the rows
+constexpr int64_t kHotMinNnz = 16;     // ... and at least this many nonzeros
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kChunk = 2048;     // nonzeros per SpMM work item; longer rows are split
 
@@ -58,6 +61,15 @@ struct Plan {
   int32_t* heavy_nchunks = nullptr;  // [n_heavy]
   int32_t* heavy_part0 = nullptr;    // [n_heavy]
   void* partials = nullptr;          // [n_parts][k] T
+  // Hot rows of the gathered factor (float32 only): the columns of the
+  // streamed orientation that hold the most nonzeros are kept out of the CSR
+  // above and stored as a dense block, hot[r * hot_ld + h] = entry of row r
+  // in hot column h (hot_ld a multiple of 16, zero-padded), multiplied on the
+  // matrix cores.
+  int32_t n_hot = 0;
+  int32_t hot_ld = 0;
+  int32_t* hot_col = nullptr;  // [kMaxHot]: factor row of hot column h
+  void* hot = nullptr;         // [rows][hot_ld] T
 };
 
 // A factor as stored (row-compressed sparse) plus the gather cache the SpMM
@@ -257,6 +269,13 @@ template <typename T>
 hipError_t grad_combine(nmf_handle* h, const T* F, const T* B, const double* G,
                         const double* g_scale, int64_t rows, T* out);
 hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t count);
+// V half with a hot block (k_hot.hip): X holds the raw sums of the rest of
+// the stream; adds the hot block's product, then solves and clamps with W
+// (W null: leaves the raw sums).  float32, k <= 64.
+hipError_t hot_finish(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X,
+                      const double* W);
+// An empty launch in the hot block's place (products without one).
+hipError_t hot_placeholder(nmf_handle* h);
 
 // Sequential ALS (k_seq.hip, k_gram.hip).
 template <typename T>

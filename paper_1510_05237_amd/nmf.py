@@ -38,6 +38,7 @@ NMF_MODE_WHOLE = 2
 NMF_F32 = 0
 NMF_F64 = 1
 NMF_FLAG_NO_METRICS = 1
+NMF_FLAG_NO_HOT = 2
 
 _STATUS_NAMES = {
     0: "NMF_OK", -1: "NMF_ERR_INVALID_ARG", -2: "NMF_ERR_INVALID_INPUT", -3: "NMF_ERR_UNSUPPORTED",

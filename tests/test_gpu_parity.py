@@ -465,3 +465,49 @@ def test_profile_stage_marks():
     assert load_library().nmf_profile_stages(a.h, 1 << 9) != 0  # no such stage
     a.close()
     ref.close()
+
+
+@pytest.mark.parametrize("k", [16, 50])
+def test_hot_block_split(k):
+    """float32, k <= 64: the densest terms' nonzeros are multiplied as a
+    dense block on the matrix cores instead of streamed.  V_pre of a V half,
+    plain iterations and the loss gradient agree with the unsplit path
+    (NMF_FLAG_NO_HOT) to float32 rounding, and V_pre with the oracle."""
+    import torch
+    from paper_1510_05237_amd import NMF_FLAG_NO_HOT, NMFLoss
+
+    n, m = 2500, 3000
+    c = synth.make_corpus(n, m, seed=43, alpha=1.1, per_doc=60, dtype="f32")
+    df = np.diff(c.indptr)
+    n_hot = int((df >= max(16, int(np.ceil(0.125 * m)))).sum())
+    assert n_hot >= 16, n_hot
+    u0, _ = synth.make_init(n, m, k, seed=43, dtype="f32")
+    _say(f"hot block split f32 {n}x{m} nnz={c.nnz} k={k}: {n_hot} hot terms "
+         f"({df[df >= max(16, int(np.ceil(0.125 * m)))].sum() / c.nnz:.0%} of nnz)")
+    a = _problem(c, u0, k, 60, 80, "f32")
+    b = _problem(c, u0, k, 60, 80, "f32", flags=NMF_FLAG_NO_HOT)
+    for p in (a, b):
+        p.half_step(0)
+    va, vb = a.pre(0), b.pre(0)
+    _, d = oracle.half_step(sp.csr_matrix(c.scipy().T), u0.astype(np.float64), 80)
+    assert rel_fro(va, vb) < 1e-5
+    assert rel_fro(va, oracle.clamp(d["X_pre"])) < 1e-4
+    for p in (a, b):
+        p.half_step(1)
+        p.step(2)
+    Ea, _, _, _ = a.history()
+    Eb, _, _, _ = b.history()
+    np.testing.assert_allclose(Ea, Eb, rtol=1e-4)
+    # the loss gradient through the hot block (dense U input)
+    rng = np.random.Generator(np.random.PCG64(5))
+    U = synth.sparse_factor_init(n, k, 60, rng=rng, dtype="f32")
+    V = synth.sparse_factor_init(m, k, 80, rng=rng, dtype="f32")
+    grads = []
+    for p in (a, b):
+        Ut = torch.tensor(U, device="cuda:0", requires_grad=True)
+        Vt = torch.tensor(V, device="cuda:0", requires_grad=True)
+        NMFLoss.apply(p, Ut, Vt).backward()
+        grads.append((Ut.grad.cpu().numpy(), Vt.grad.cpu().numpy()))
+    assert rel_fro(grads[0][0], grads[1][0]) < 1e-5 and rel_fro(grads[0][1], grads[1][1]) < 1e-5
+    a.close()
+    b.close()
