@@ -3,24 +3,26 @@
 // The terms that occur in the most documents (rows of A with at least
 // kHotDensity * m nonzeros, at most kMaxHot of them) are kept out of the
 // V-half sparse stream: their entries are stored as a dense docs x hot
-// block.  For those columns A^T U is a dense product (the block is 12 % to
-// 85 % full), so it runs on the matrix cores instead of as per-nonzero
-// gathers of U rows.  k_spmm first leaves the raw sums of the rest of each
+// block.  For those columns A^T U is close to a dense product (with Zipf
+// term frequencies the 128 densest terms fill about a third of their block),
+// so it runs on the matrix cores instead of as per-nonzero gathers of U rows.  k_spmm first leaves the raw sums of the rest of each
 // document's stream in X; this kernel adds the hot block's product and, in
 // the solving form, applies the epilogue of Algorithm 2 step 1:
 //   X_r = max(0, (cold_r + hot_r) W),  W = (U^T U)^-1 (float64).
 //
-// Layout of the product: a wave owns 16 documents and all 64 topic slots
-// (four 16-topic tiles), one 16x16x4 MFMA per tile and four hot columns.
-// Lane l (m = l % 16, q = l / 16) loads hot columns 16 g + 4 q .. + 3 of
-// document r0 + m as one float4 and feeds them to four MFMAs as the A
-// operand's column q; the B operand of the same MFMA, row q, is U's row of
-// the same hot column, staged in LDS as ub[g][q][topic][s] so that a lane
-// reads its four values with one 16-byte load.  Tile tt then holds the sums
-// for document r0 + 4 q + i, topic 16 tt + m in element i.  The solve is a
-// second product on the matrix cores, in float64: the 16 documents' raw sums
-// (through a per-wave LDS tile) times W, 16x16x4 float64 MFMAs with the same
-// operand layout; their result holds document r0 + q + 4 i in element i.
+// Layout: a wave owns 16 documents and all 64 topic slots.  The hot product
+// is computed transposed, (U_H^T)(A_H^T), as four 16-topic x 16-document
+// tiles, one 16x16x4 MFMA per tile and four hot columns: lane l (m = l % 16,
+// q = l / 16) loads hot columns 16 g + 4 q .. + 3 of document r0 + m as one
+// float4 (the B operand's column m, rows q, one per MFMA) and reads U's rows
+// of the same hot columns from LDS, staged as ub[g][q][topic][s] so that one
+// 16-byte load gives its four A operands.  Element i of tile tt then holds
+// document r0 + m, topic 16 tt + 4 q + i.  The float64 solve (raw W) is a
+// second product on the matrix cores whose contraction order is free: step
+// (tt, i) takes, in lane (m, q), the raw sum the lane holds for topic
+// rr = 16 tt + 4 q + i as its A operand and W[rr][16 t2 + m] as its B
+// operand, so the raw sums never leave registers; the float64 result holds
+// document r0 + q + 4 i, topic 16 t2 + m in element i.
 #include <algorithm>
 
 #include "nmf_device.h"
@@ -52,7 +54,7 @@ struct HotArgs {
 
 size_t hot_lds_bytes(int hot_ld, int k, bool solve) {
   size_t b = static_cast<size_t>(hot_ld) * kHotTopics * sizeof(float);
-  if (solve) b += static_cast<size_t>((k * k + 1) & ~1) * sizeof(double) + kHotWaves * kHotTopics * 16 * sizeof(float);
+  if (solve) b += static_cast<size_t>(k) * k * sizeof(double);
   return b;
 }
 
@@ -63,24 +65,51 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
   const int H = a.hot_ld;
   float* ub = reinterpret_cast<float*>(smem);  // [H / 16][4][64][4]
   double* sW = reinterpret_cast<double*>(smem + static_cast<size_t>(H) * kHotTopics * sizeof(float));
-  // per-wave raw tile [topic][16 docs], 16-byte aligned
-  float* rt = reinterpret_cast<float*>(sW + ((k * k + 1) & ~1)) + (threadIdx.x >> 6) * kHotTopics * 16;
-  for (int i = threadIdx.x; i < H * kHotTopics; i += blockDim.x) {
-    const int hc = i / kHotTopics, c = i - hc * kHotTopics;
-    float v = 0.f;
-    if (hc < a.n_hot && c < k) {
+  // where each hot column's U row starts in F (-1: an empty row), then
+  // every staged value with independent loads, several in flight per thread
+  __shared__ int64_t s_off[kMaxHot];
+  for (int hc = threadIdx.x; hc < H; hc += blockDim.x) {
+    int64_t off = -1;
+    if (hc < a.n_hot) {
       const int r = a.hot_col[hc];
-      if (a.slot != nullptr) {
-        const int s = a.slot[r];
-        if (s >= 0) v = a.F[static_cast<int64_t>(s) * a.ld + c];
-      } else {
-        v = a.F[static_cast<int64_t>(r) * a.ld + c];
-      }
+      const int s = a.slot != nullptr ? a.slot[r] : r;
+      if (s >= 0) off = static_cast<int64_t>(s) * a.ld;
     }
-    ub[(((hc >> 4) * 4 + ((hc >> 2) & 3)) * kHotTopics + c) * 4 + (hc & 3)] = v;
+    s_off[hc] = off;
   }
-  if (a.W != nullptr)
-    for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
+  __syncthreads();
+  constexpr int kStage = kMaxHot * kHotTopics / (64 * kHotWaves);  // values per thread at most
+  float sv[kStage];
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int i = threadIdx.x + u * 64 * kHotWaves;
+    const int hc = i / kHotTopics, c = i - hc * kHotTopics;
+    sv[u] = 0.f;
+    if (hc < H && c < k) {
+      const int64_t off = s_off[hc];
+      if (off >= 0) sv[u] = a.F[off + c];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kStage; ++u) {
+    const int i = threadIdx.x + u * 64 * kHotWaves;
+    const int hc = i / kHotTopics, c = i - hc * kHotTopics;
+    if (hc < H) ub[(((hc >> 4) * 4 + ((hc >> 2) & 3)) * kHotTopics + c) * 4 + (hc & 3)] = sv[u];
+  }
+  if (a.W != nullptr) {
+    constexpr int kWStage = kHotTopics * kHotTopics / (64 * kHotWaves);
+    double wv[kWStage];
+#pragma unroll
+    for (int u = 0; u < kWStage; ++u) {
+      const int i = threadIdx.x + u * 64 * kHotWaves;
+      wv[u] = i < k * k ? a.W[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kWStage; ++u) {
+      const int i = threadIdx.x + u * 64 * kHotWaves;
+      if (i < k * k) sW[i] = wv[u];
+    }
+  }
   __syncthreads();
   const int lane = lane_id();
   const int m = lane & 15, q = lane >> 4;
@@ -99,15 +128,18 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     for (int g = 0; g < HG; ++g)
       arow4[g] = (16 * g < H && ra < a.rows) ? *reinterpret_cast<const hot_f4*>(arow + 16 * g)
                                              : hot_f4{0.f, 0.f, 0.f, 0.f};
+    // cold[tt][i]: raw sum of document r0 + m, topic 16 tt + 4 q + i (the
+    // layout of the transposed product below)
     float cold[4][4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int64_t r = r0 + 4 * q + i;
-        const int c = 16 * tt + m;
-        cold[tt][i] = (r < a.rows && c < k) ? a.X[r * k + c] : 0.f;
+        const int c = 16 * tt + 4 * q + i;
+        cold[tt][i] = (ra < a.rows && c < k) ? a.X[ra * k + c] : 0.f;
       }
+    // transposed product: tile tt = (U_H^T)(topics 16 tt ..) x (A_H^T)(.., docs),
+    // element i of lane (m, q) = document r0 + m, topic 16 tt + 4 q + i
     hot_f4 acc[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) acc[tt] = hot_f4{0.f, 0.f, 0.f, 0.f};
@@ -115,47 +147,57 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     for (int g = 0; g < HG; ++g) {
       if (16 * g >= H) break;
       const hot_f4 av = arow4[g];
+      hot_f4 bv[4];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        const hot_f4 bv = *reinterpret_cast<const hot_f4*>(&ub[((g * 4 + q) * kHotTopics + 16 * tt + m) * 4]);
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[tt], 0, 0, 0);
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[tt], 0, 0, 0);
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[tt], 0, 0, 0);
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[tt], 0, 0, 0);
-      }
+      for (int tt = 0; tt < 4; ++tt)
+        bv[tt] = *reinterpret_cast<const hot_f4*>(&ub[((g * 4 + q) * kHotTopics + 16 * tt + m) * 4]);
+      // consecutive MFMAs go to different tiles, so none waits on the one before
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].x, av.x, acc[tt], 0, 0, 0);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].y, av.y, acc[tt], 0, 0, 0);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].z, av.z, acc[tt], 0, 0, 0);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].w, av.w, acc[tt], 0, 0, 0);
     }
+    float raw[4][4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) raw[tt][i] = cold[tt][i] + acc[tt][i];
     if (a.W == nullptr) {
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int64_t r = r0 + 4 * q + i;
-          const int c = 16 * tt + m;
-          if (r < a.rows && c < k) a.X[r * k + c] = cold[tt][i] + acc[tt][i];
+          const int c = 16 * tt + 4 * q + i;
+          if (ra < a.rows && c < k) a.X[ra * k + c] = raw[tt][i];
         }
       continue;
     }
-    // raw sums of the 16 documents, topic-major, then the float64 solve on
-    // the matrix cores: out (16 docs x 64 topics) = raw (16 x k) W (k x 64),
-    // one 16x16x4 MFMA per topic tile and four rows of W; lane l feeds
-    // raw[doc m][rr = 4 s + q] and W[4 s + q][16 tt + m]
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) rt[(16 * tt + m) * 16 + 4 * q + i] = cold[tt][i] + acc[tt][i];
+    // the float64 solve on the matrix cores: out (16 docs x 64 topics) =
+    // raw (16 x k) W (k x 64).  The step (tt, i) takes, in lane (m, q), the
+    // raw sum the lane already holds, raw[doc m][rr = 16 tt + 4 q + i], as
+    // the A operand's column q and W[rr][16 tt' + m] as the B operand's row
+    // q; steps whose four rr are all past k are skipped.
     hot_d4 o[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) o[tt] = hot_d4{0.0, 0.0, 0.0, 0.0};
-    for (int s4 = 0; s4 < k; s4 += 4) {
-      const int rr = s4 + q;
-      const double av = rr < k ? static_cast<double>(rt[rr * 16 + m]) : 0.0;
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        const int c = 16 * tt + m;
-        const double bv = (rr < k && c < k) ? sW[rr * k + c] : 0.0;
-        o[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, o[tt], 0, 0, 0);
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (16 * tt + i >= k) break;
+        const int rr = 16 * tt + 4 * q + i;
+        const double av = static_cast<double>(raw[tt][i]);
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2) {
+          const int c = 16 * t2 + m;
+          const double bv = (rr < k && c < k) ? sW[rr * k + c] : 0.0;
+          o[t2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, o[t2], 0, 0, 0);
+        }
       }
-    }
     // o[tt][i]: document r0 + q + 4 i, topic 16 tt + m (the float64 form
     // interleaves the rows)
 #pragma unroll

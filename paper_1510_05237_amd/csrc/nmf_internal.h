@@ -15,7 +15,7 @@ namespace nmfk {
 
 constexpr int kMaxK = 128;       // topics supported (2 per lane at most)
 constexpr int kMaxHot = 128;     // most hot columns split off the V-half stream (float32)
-constexpr double kHotDensity = 0.125;  // a hot column holds at least this share of the rows
+constexpr double kHotDensity = 0.0625;  // a hot column holds at least this share of the rows
 constexpr int64_t kHotMinNnz = 16;     // ... and at least this many nonzeros
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kChunk = 2048;     // nonzeros per SpMM work item; longer rows are split

@@ -479,11 +479,11 @@ def test_hot_block_split(k):
     n, m = 2500, 3000
     c = synth.make_corpus(n, m, seed=43, alpha=1.1, per_doc=60, dtype="f32")
     df = np.diff(c.indptr)
-    n_hot = int((df >= max(16, int(np.ceil(0.125 * m)))).sum())
+    n_hot = int((df >= max(16, int(np.ceil(0.0625 * m)))).sum())
     assert n_hot >= 16, n_hot
     u0, _ = synth.make_init(n, m, k, seed=43, dtype="f32")
     _say(f"hot block split f32 {n}x{m} nnz={c.nnz} k={k}: {n_hot} hot terms "
-         f"({df[df >= max(16, int(np.ceil(0.125 * m)))].sum() / c.nnz:.0%} of nnz)")
+         f"({df[df >= max(16, int(np.ceil(0.0625 * m)))].sum() / c.nnz:.0%} of nnz)")
     a = _problem(c, u0, k, 60, 80, "f32")
     b = _problem(c, u0, k, 60, 80, "f32", flags=NMF_FLAG_NO_HOT)
     for p in (a, b):
