@@ -34,7 +34,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_traffic_100kx200k.json")
-SPMM_SRC = os.path.join(ROOT, "paper_1510_05237_amd", "csrc", "k_spmm.hip")
+# the product stages' kernels: the sparse stream and the V half's hot block
+SPMM_SRCS = [os.path.join(ROOT, "paper_1510_05237_amd", "csrc", f) for f in ("k_spmm.hip", "k_hot.hip")]
 
 
 def log(msg: str):
@@ -54,20 +55,23 @@ def spmm_algorithmic_bytes(rows_out: int, rows_f: int, nnz_a: int, nnz_f: float,
     return float(a + f + out)
 
 
-def file_sha(path: str) -> str:
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def kernels_sha() -> str:
+    h = hashlib.sha256()
+    for path in SPMM_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(stage: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None when
-    absent or taken on a different version of the SpMM kernel."""
+    absent or taken on a different version of the product kernels."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != file_sha(SPMM_SRC):
+    if t.get("kernel_sha") != kernels_sha():
         return None
     s = t.get("stages", {}).get(stage)
     if not s:
@@ -504,7 +508,8 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": f"k_spmm ({'V half: A^T U' if dom == 'spmm_v' else 'U half: A V'})",
+        "kernel": ("V-half product stage: k_spmm stream + k_spmm_heavy + k_hot dense block (A^T U, float64 solve)"
+                   if dom == "spmm_v" else "U-half product stage: k_spmm + k_spmm_heavy (A V, float64 solve)"),
         "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"],
         "launch_ms": round(kern[dom]["ms"], 4),
     }
