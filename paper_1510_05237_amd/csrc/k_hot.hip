@@ -34,6 +34,20 @@ namespace {
 typedef float hot_f4 __attribute__((ext_vector_type(4)));
 typedef double hot_d4 __attribute__((ext_vector_type(4)));
 
+// Range-checked buffer loads (the hardware returns zero past the resource's
+// size), so that the tile's loads carry no branches and the MFMAs can start as
+// soon as their own operands have arrived.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t hot_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                           0x00020000);
+}
+__device__ __forceinline__ hot_f4 hot_load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(hot_f4, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ float hot_load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+
 constexpr int kHotWaves = 8;
 constexpr int kHotTopics = 64;  // topic slots per wave (k <= 64)
 
@@ -117,26 +131,29 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
   const int64_t nw = static_cast<int64_t>(nblk) * bw;
   const int64_t tiles = (a.rows + 15) / 16;
   constexpr int HG = kMaxHot / 16;
+  const __amdgpu_buffer_rsrc_t hr = hot_rsrc(a.hot, static_cast<uint32_t>(a.rows * H * 4));
+  const __amdgpu_buffer_rsrc_t xr = hot_rsrc(a.X, static_cast<uint32_t>(a.rows * k * 4));
   for (int64_t t = static_cast<int64_t>(blk) * bw + (threadIdx.x >> 6); t < tiles; t += nw) {
     const int64_t r0 = 16 * t;
     const int64_t ra = r0 + m;
     // every load of the tile in flight at once: the documents' hot columns
-    // and the raw sums the stream left in X
-    const float* __restrict__ arow = a.hot + ra * H + 4 * q;
+    // (rows past the end read as zero) and the raw sums the stream left in X
+    // (topics past k are zeroed after the load)
+    const uint32_t abase = static_cast<uint32_t>(ra * H + 4 * q) * 4u;
     hot_f4 arow4[HG];
 #pragma unroll
     for (int g = 0; g < HG; ++g)
-      arow4[g] = (16 * g < H && ra < a.rows) ? *reinterpret_cast<const hot_f4*>(arow + 16 * g)
-                                             : hot_f4{0.f, 0.f, 0.f, 0.f};
+      arow4[g] = 16 * g < H ? hot_load4(hr, abase + 64u * g) : hot_f4{0.f, 0.f, 0.f, 0.f};
     // cold[tt][i]: raw sum of document r0 + m, topic 16 tt + 4 q + i (the
     // layout of the transposed product below)
+    const uint32_t xbase = static_cast<uint32_t>(ra * k + 4 * q) * 4u;
     float cold[4][4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int c = 16 * tt + 4 * q + i;
-        cold[tt][i] = (ra < a.rows && c < k) ? a.X[ra * k + c] : 0.f;
+        const float v = hot_load1(xr, xbase + static_cast<uint32_t>(16 * tt + i) * 4u);
+        cold[tt][i] = 16 * tt + 4 * q + i < k ? v : 0.f;
       }
     // transposed product: tile tt = (U_H^T)(topics 16 tt ..) x (A_H^T)(.., docs),
     // element i of lane (m, q) = document r0 + m, topic 16 tt + 4 q + i
@@ -226,7 +243,10 @@ hipError_t hot_placeholder(nmf_handle* h) {
 
 hipError_t hot_finish(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X,
                       const double* W) {
-  if (p.n_hot <= 0 || h->k > kHotTopics || p.hot_ld > kMaxHot) return hipErrorInvalidValue;
+  // the tile loads address the block and X with 32-bit byte offsets
+  if (p.n_hot <= 0 || h->k > kHotTopics || p.hot_ld > kMaxHot ||
+      (p.rows + 16) * p.hot_ld * 4 >= (int64_t{1} << 32) || (p.rows + 16) * h->k * 4 >= (int64_t{1} << 32))
+    return hipErrorInvalidValue;
   HotArgs a{};
   a.hot = static_cast<const float*>(p.hot);
   a.hot_col = p.hot_col;

@@ -475,7 +475,8 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   // most nonzeros first (ties: lower row), at most kMaxHot; their entries
   // leave the V-half stream for a dense docs x hot block
   std::vector<int32_t> hot;
-  if (sizeof(T) == 4 && h->k <= 64 && !(h->cfg.flags & NMF_FLAG_NO_HOT)) {
+  if (sizeof(T) == 4 && h->k <= 64 && !(h->cfg.flags & NMF_FLAG_NO_HOT) &&
+      (m + 16) * kMaxHot * 4 < (int64_t{1} << 32)) {
     const int64_t need = std::max<int64_t>(kHotMinNnz, static_cast<int64_t>(std::ceil(kHotDensity * m)));
     for (int64_t i = 0; i < n; ++i)
       if (rp[i + 1] - rp[i] >= need) hot.push_back(static_cast<int32_t>(i));
