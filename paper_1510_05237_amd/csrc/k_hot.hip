@@ -59,6 +59,7 @@ struct HotArgs {
   const int32_t* slot;  // compact index of each U row (-1: empty), or null for a dense input
   const float* F;       // compact dense U rows, or the dense input
   int32_t ld;           // row pitch of F
+  uint32_t F_bytes;     // bytes of F (staging loads are range-checked against it)
   int64_t rows;         // documents
   int32_t k;
   const double* W;  // k x k, or null: X receives the raw sums
@@ -79,30 +80,30 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
   const int H = a.hot_ld;
   float* ub = reinterpret_cast<float*>(smem);  // [H / 16][4][64][4]
   double* sW = reinterpret_cast<double*>(smem + static_cast<size_t>(H) * kHotTopics * sizeof(float));
-  // where each hot column's U row starts in F (-1: an empty row), then
-  // every staged value with independent loads, several in flight per thread
+  // where each hot column's U row starts in F (-1: an empty row, staged as
+  // zeros), then every staged value with independent range-checked loads,
+  // several in flight per thread
   __shared__ int64_t s_off[kMaxHot];
   for (int hc = threadIdx.x; hc < H; hc += blockDim.x) {
     int64_t off = -1;
     if (hc < a.n_hot) {
       const int r = a.hot_col[hc];
       const int s = a.slot != nullptr ? a.slot[r] : r;
-      if (s >= 0) off = static_cast<int64_t>(s) * a.ld;
+      if (s >= 0) off = static_cast<int64_t>(s) * a.ld * 4;
     }
     s_off[hc] = off;
   }
   __syncthreads();
+  const __amdgpu_buffer_rsrc_t fr = hot_rsrc(a.F, a.F_bytes);
   constexpr int kStage = kMaxHot * kHotTopics / (64 * kHotWaves);  // values per thread at most
   float sv[kStage];
 #pragma unroll
   for (int u = 0; u < kStage; ++u) {
     const int i = threadIdx.x + u * 64 * kHotWaves;
-    const int hc = i / kHotTopics, c = i - hc * kHotTopics;
-    sv[u] = 0.f;
-    if (hc < H && c < k) {
-      const int64_t off = s_off[hc];
-      if (off >= 0) sv[u] = a.F[off + c];
-    }
+    const int hc = (i / kHotTopics) < H ? i / kHotTopics : 0, c = i % kHotTopics;
+    const int64_t off = s_off[hc];
+    const float v = hot_load1(fr, static_cast<uint32_t>(off < 0 ? 0 : off) + 4u * static_cast<uint32_t>(c));
+    sv[u] = (off >= 0 && c < k) ? v : 0.f;
   }
 #pragma unroll
   for (int u = 0; u < kStage; ++u) {
@@ -112,11 +113,12 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
   }
   if (a.W != nullptr) {
     constexpr int kWStage = kHotTopics * kHotTopics / (64 * kHotWaves);
+    const __amdgpu_buffer_rsrc_t wr = hot_rsrc(a.W, static_cast<uint32_t>(k * k * 8));
     double wv[kWStage];
 #pragma unroll
     for (int u = 0; u < kWStage; ++u) {
       const int i = threadIdx.x + u * 64 * kHotWaves;
-      wv[u] = i < k * k ? a.W[i] : 0.0;
+      wv[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(wr, 8 * i, 0, 0));
     }
 #pragma unroll
     for (int u = 0; u < kWStage; ++u) {
@@ -255,6 +257,7 @@ hipError_t hot_finish(nmf_handle* h, const Plan& p, const Factor& F, const float
   a.slot = dense_in ? nullptr : F.slot;
   a.F = dense_in ? dense_in : static_cast<const float*>(F.dense);
   a.ld = dense_in ? h->k : F.ld;
+  a.F_bytes = static_cast<uint32_t>(dense_in ? h->n * h->k * 4 : F.rows * F.ld * 4);
   a.rows = p.rows;
   a.k = h->k;
   a.W = W;
