@@ -213,18 +213,21 @@ nmf_status nmf_profile_read(nmf_handle* h, double* ms, int64_t* count, int32_t n
 enum {
   NMF_PARAM_SPARSE_ROW_V = 0, /* V half: U rows with <= this many entries are
                                  gathered entry by entry, denser rows whole
-                                 (0..128; default 1)                        */
+                                 (0..128; default 1, or 2 with a hot block:
+                                 see NMF_FLAG_NO_HOT)                       */
   NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V (default 3) */
   NMF_PARAM_WIDE_V = 2,       /* V half SpMM step form: 0 = 64 nonzeros per
                                  step with loads only on the lanes that need
-                                 them (default; suits factors whose gathered
-                                 rows are mostly dense), 1 = 128 nonzeros per
-                                 step with every load issued on all lanes
-                                 (suits very sparse gathered rows)          */
+                                 them (default without a hot block; suits
+                                 factors whose gathered rows are mostly
+                                 dense), 1 = 128 nonzeros per step with every
+                                 load issued on all lanes (suits very sparse
+                                 gathered rows; default with a hot block)   */
   NMF_PARAM_WIDE_U = 3,       /* U half: the same (default 1)               */
   NMF_PARAM_WAVES_V = 4,      /* V half SpMM: waves per block, 1/2/4/8/16
-                                 (default 16; fewer when the k x k inverse
-                                 and the wave buffers exceed the LDS)       */
+                                 (default 16, 8 with a hot block; fewer when
+                                 the k x k inverse and the wave buffers
+                                 exceed the LDS)                            */
   NMF_PARAM_WAVES_U = 5,      /* U half: the same (default 8)               */
   NMF_NUM_PARAMS = 6
 };

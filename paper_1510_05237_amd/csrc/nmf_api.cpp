@@ -543,6 +543,13 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz_t * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz_t * sizeof(T), hipMemcpyHostToDevice));
   h->planAt.n_hot = n_hot;
+  if (n_hot) {
+    // the stream without the hot terms gathers sparser rows of U (set before
+    // any factor's gather metadata is built)
+    h->sparse_row[0] = 2;
+    h->wide[0] = true;
+    h->waves[0] = 8;
+  }
   h->planAt.hot_ld = hot_ld;
   if (n_hot) {
     HIPCHK(h, hipMemcpy(h->planAt.hot_col, hot.data(), n_hot * sizeof(int32_t), hipMemcpyHostToDevice));
