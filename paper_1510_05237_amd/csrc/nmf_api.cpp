@@ -149,7 +149,9 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
   h->planAt.rowptr = cv.take<int64_t>(m + 1);
   h->planAt.col = cv.take<int32_t>(nnz);
   h->planAt.val = cv.take<char>(nnz * elt);
-  if (c.dtype == NMF_F32) {
+  // room for the V half's hot block when one can exist (float32, k <= 64,
+  // the flag not set, its byte offsets within 32 bits): see do_create
+  if (c.dtype == NMF_F32 && k <= 64 && !(c.flags & NMF_FLAG_NO_HOT) && (m + 16) * kMaxHot * 4 < (int64_t{1} << 32)) {
     const int hot_max = static_cast<int>(std::min<int64_t>(kMaxHot, (n + 15) / 16 * 16));
     h->planAt.hot_col = cv.take<int32_t>(kMaxHot);
     h->planAt.hot = cv.take<char>(m * hot_max * elt);
@@ -542,6 +544,8 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   HIPCHK(h, hipMemcpy(h->planA.val, val, nnz * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz_t * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz_t * sizeof(T), hipMemcpyHostToDevice));
+  if (n_hot && (h->planAt.hot == nullptr || h->planAt.hot_col == nullptr))
+    return fail(h, NMF_ERR_WORKSPACE, "internal: no room for the hot block");
   h->planAt.n_hot = n_hot;
   if (n_hot) {
     // the stream without the hot terms gathers sparser rows of U (set before
