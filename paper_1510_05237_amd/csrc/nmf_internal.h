@@ -18,7 +18,7 @@ constexpr int kMaxHot = 128;     // most hot columns split off the V-half stream
 constexpr double kHotDensity = 0.0625;  // a hot column holds at least this share of the rows
 constexpr int64_t kHotMinNnz = 16;     // ... and at least this many nonzeros
 constexpr int kWave = 64;        // CDNA wavefront width
-constexpr int kChunk = 2048;     // nonzeros per SpMM work item; longer rows are split
+constexpr int kChunk = 1024;     // nonzeros per SpMM work item; longer rows are split
 
 // Most output rows a light SpMM work item carries (the rows of one epilogue
 // batch): 8 with one topic per lane, 4 with two.

@@ -119,7 +119,7 @@ def test_fp32_two_topics_per_lane_k80():
 
 
 def test_fp32_heavy_rows_split():
-    """Term rows longer than one work chunk (4096 nonzeros) are split and
+    """Term rows longer than one work chunk (1024 nonzeros) are split and
     recombined in chunk order."""
     c = synth.make_corpus(2000, 12000, seed=33, alpha=1.1, per_doc=30, dtype="f32")
     lens = np.diff(c.indptr)
