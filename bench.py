@@ -390,8 +390,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the ALS hot path on a single MI355X "
-              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the ALS iteration on a single MI355X "
+              "(there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
