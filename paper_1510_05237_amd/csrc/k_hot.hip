@@ -73,6 +73,8 @@ size_t hot_lds_bytes(int hot_ld, int k, bool solve) {
   return b;
 }
 
+// NT: 16-topic tiles in use (ceil(k / 16)); the product and the solve skip the rest.
+template <int NT>
 __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (*a.status != 0) return;
@@ -151,7 +153,7 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     const uint32_t xbase = static_cast<uint32_t>(ra * k + 4 * q) * 4u;
     float cold[4][4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float v = hot_load1(xr, xbase + static_cast<uint32_t>(16 * tt + i) * 4u);
@@ -161,33 +163,33 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     // element i of lane (m, q) = document r0 + m, topic 16 tt + 4 q + i
     hot_f4 acc[4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) acc[tt] = hot_f4{0.f, 0.f, 0.f, 0.f};
+    for (int tt = 0; tt < NT; ++tt) acc[tt] = hot_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int g = 0; g < HG; ++g) {
       if (16 * g >= H) break;
       const hot_f4 av = arow4[g];
       hot_f4 bv[4];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
+      for (int tt = 0; tt < NT; ++tt)
         bv[tt] = *reinterpret_cast<const hot_f4*>(&ub[((g * 4 + q) * kHotTopics + 16 * tt + m) * 4]);
       // consecutive MFMAs go to different tiles, so none waits on the one before
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].x, av.x, acc[tt], 0, 0, 0);
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].x, av.x, acc[tt], 0, 0, 0);
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].y, av.y, acc[tt], 0, 0, 0);
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].y, av.y, acc[tt], 0, 0, 0);
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].z, av.z, acc[tt], 0, 0, 0);
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].z, av.z, acc[tt], 0, 0, 0);
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].w, av.w, acc[tt], 0, 0, 0);
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].w, av.w, acc[tt], 0, 0, 0);
     }
     float raw[4][4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) raw[tt][i] = cold[tt][i] + acc[tt][i];
     if (a.W == nullptr) {
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
+      for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int c = 16 * tt + 4 * q + i;
@@ -202,16 +204,16 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     // q; steps whose four rr are all past k are skipped.
     hot_d4 o[4];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) o[tt] = hot_d4{0.0, 0.0, 0.0, 0.0};
+    for (int tt = 0; tt < NT; ++tt) o[tt] = hot_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (16 * tt + i >= k) break;
         const int rr = 16 * tt + 4 * q + i;
         const double av = static_cast<double>(raw[tt][i]);
 #pragma unroll
-        for (int t2 = 0; t2 < 4; ++t2) {
+        for (int t2 = 0; t2 < NT; ++t2) {
           const int c = 16 * t2 + m;
           const double bv = (rr < k && c < k) ? sW[rr * k + c] : 0.0;
           o[t2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, o[t2], 0, 0, 0);
@@ -220,7 +222,7 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     // o[tt][i]: document r0 + q + 4 i, topic 16 tt + m (the float64 form
     // interleaves the rows)
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t r = r0 + q + 4 * i;
@@ -229,18 +231,20 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
       }
   }
 }
-__global__ __launch_bounds__(64 * kHotWaves) void k_hot(HotArgs a) { k_hot_body(a, blockIdx.x, gridDim.x); }
+template <int NT>
+__global__ __launch_bounds__(64 * kHotWaves) void k_hot(HotArgs a) { k_hot_body<NT>(a, blockIdx.x, gridDim.x); }
+template <int NT>
 __global__ __launch_bounds__(64 * kHotWaves) void k_hot_b(const HotArgs* as, const BlockMap* map) {
   const BlockMap mp = map[blockIdx.x];
   const HotArgs a = as[mp.prob];
-  k_hot_body(a, mp.blk, mp.nblk);
+  k_hot_body<NT>(a, mp.blk, mp.nblk);
 }
 
 }  // namespace
 
 hipError_t hot_placeholder(nmf_handle* h) {
   HotArgs a{};
-  return launch_rec(h, k_hot, k_hot_b, 0, 64 * kHotWaves, 0, a);
+  return launch_rec(h, k_hot<4>, k_hot_b<4>, 0, 64 * kHotWaves, 0, a);
 }
 
 hipError_t hot_finish(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X,
@@ -266,7 +270,13 @@ hipError_t hot_finish(nmf_handle* h, const Plan& p, const Factor& F, const float
   const int64_t tiles = (p.rows + 15) / 16;
   const unsigned blocks =
       static_cast<unsigned>(std::min<int64_t>((tiles + kHotWaves - 1) / kHotWaves, 2 * h->num_cus));
-  return launch_rec(h, k_hot, k_hot_b, blocks, 64 * kHotWaves, hot_lds_bytes(p.hot_ld, h->k, W != nullptr), a);
+  const size_t lds = hot_lds_bytes(p.hot_ld, h->k, W != nullptr);
+  switch ((h->k + 15) / 16) {
+    case 1: return launch_rec(h, k_hot<1>, k_hot_b<1>, blocks, 64 * kHotWaves, lds, a);
+    case 2: return launch_rec(h, k_hot<2>, k_hot_b<2>, blocks, 64 * kHotWaves, lds, a);
+    case 3: return launch_rec(h, k_hot<3>, k_hot_b<3>, blocks, 64 * kHotWaves, lds, a);
+    default: return launch_rec(h, k_hot<4>, k_hot_b<4>, blocks, 64 * kHotWaves, lds, a);
+  }
 }
 
 }  // namespace nmfk
