@@ -163,38 +163,68 @@ __device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, 
   __shared__ double totq[3];
   if (*a.status != 0) return;
   const int k = a.k;
-  // partials: thread t adds blocks t, t + 256, ... in order, then a fixed tree
+  // every load in flight at once: thread 0's scalars, the partials (thread t
+  // adds blocks t, t + 256, ... in order, then a fixed tree) and G_U, G_V
+  int64_t it = 0;
+  double nA2 = 0.0;
+  int32_t cnt[4] = {0, 0, 0, 0};
+  if (threadIdx.x == 0) {
+    it = *a.it;
+    nA2 = *a.nA2;
+    cnt[0] = *a.nnz_u;
+    cnt[1] = *a.nnz_v;
+    cnt[2] = *a.dead_u;
+    cnt[3] = *a.dead_v;
+  }
+  constexpr int kPer = (kMetricBlocks + 255) / 256;
+  double pd[kPer][3];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int b = threadIdx.x + 256 * j;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) pd[j][f] = b < nparts ? a.partials[b * 4 + f] : 0.0;
+  }
   double d = 0.0, n = 0.0, x = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += 256) {
-    d += a.partials[b * 4 + 0];
-    n += a.partials[b * 4 + 1];
-    x += a.partials[b * 4 + 2];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    d += pd[j][0];
+    n += pd[j][1];
+    x += pd[j][2];
   }
   block_sum3(d, n, x, sh, tot);
   __syncthreads();
   double q = 0.0;
-  if (a.record && a.GU != nullptr)
-    for (int i = threadIdx.x; i < k * k; i += 256) q = fma(a.GU[i], a.GV[i], q);
+  if (a.record && a.GU != nullptr) {
+    for (int i0 = threadIdx.x; i0 < k * k; i0 += 8 * 256) {
+      double gu[8], gv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + 256 * u;
+        gu[u] = i < k * k ? a.GU[i] : 0.0;
+        gv[u] = i < k * k ? a.GV[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q = fma(gu[u], gv[u], q);
+    }
+  }
   block_sum3(q, 0.0, 0.0, sh, totq);
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double D = tot[0], N = tot[1], X = tot[2];
-  const int64_t it = *a.it;
   double* rec = a.ring + (it % kHistRing) * H_FIELDS;
   double E = __builtin_nan(""), R = __builtin_nan("");
   if (a.record) {
     R = sqrt(D) / sqrt(N);
-    const double nA2 = *a.nA2;
     const double e2 = nA2 - 2.0 * X + totq[0];
     E = sqrt(e2 > 0.0 ? e2 : 0.0) / sqrt(nA2);
     if (!isfinite(R) || !isfinite(E)) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
   }
   rec[H_E] = E;
   rec[H_R] = R;
-  rec[H_NNZU] = static_cast<double>(*a.nnz_u);
-  rec[H_NNZV] = static_cast<double>(*a.nnz_v);
-  rec[H_DEADU] = static_cast<double>(*a.dead_u);
-  rec[H_DEADV] = static_cast<double>(*a.dead_v);
+  rec[H_NNZU] = static_cast<double>(cnt[0]);
+  rec[H_NNZV] = static_cast<double>(cnt[1]);
+  rec[H_DEADU] = static_cast<double>(cnt[2]);
+  rec[H_DEADV] = static_cast<double>(cnt[3]);
   *a.it = it + 1;
 }
 __global__ __launch_bounds__(256) void k_metrics_final(MetArgs a) { k_metrics_final_body(a, blockIdx.x, gridDim.x); }
