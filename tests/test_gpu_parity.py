@@ -482,6 +482,9 @@ def test_hot_block_split(k):
     n_hot = int((df >= max(16, int(np.ceil(0.0625 * m)))).sum())
     assert n_hot >= 16, n_hot
     u0, _ = synth.make_init(n, m, k, seed=43, dtype="f32")
+    # the three densest terms get empty rows of U: hot columns whose factor
+    # row is not stored
+    u0[np.argsort(-df, kind="stable")[:3]] = 0.0
     _say(f"hot block split f32 {n}x{m} nnz={c.nnz} k={k}: {n_hot} hot terms "
          f"({df[df >= max(16, int(np.ceil(0.0625 * m)))].sum() / c.nnz:.0%} of nnz)")
     a = _problem(c, u0, k, 60, 80, "f32")
