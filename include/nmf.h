@@ -225,7 +225,7 @@ enum {
                                  gathered rows; default with a hot block)   */
   NMF_PARAM_WIDE_U = 3,       /* U half: the same (default 1)               */
   NMF_PARAM_WAVES_V = 4,      /* V half SpMM: waves per block, 1/2/4/8/16
-                                 (default 16, 8 with a hot block; fewer when
+                                 (default 16, 4 with a hot block; fewer when
                                  the k x k inverse and the wave buffers
                                  exceed the LDS)                            */
   NMF_PARAM_WAVES_U = 5,      /* U half: the same (default 8)               */

@@ -552,7 +552,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
     // any factor's gather metadata is built)
     h->sparse_row[0] = 2;
     h->wide[0] = true;
-    h->waves[0] = 8;
+    h->waves[0] = 4;
   }
   h->planAt.hot_ld = hot_ld;
   if (n_hot) {
