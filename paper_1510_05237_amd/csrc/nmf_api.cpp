@@ -1522,8 +1522,8 @@ nmf_status nmf_batch_tune(nmf_batch* b, int32_t iters, int32_t* chosen) {
   nmf_status s = common_slot(b, &slot);
   if (s != NMF_OK) return s;
   // SpMM forms tried for each half: {wide step, entry-by-entry threshold, waves per block}
-  static const int kCands[][3] = {{0, 1, 16}, {0, 1, 8}, {0, 3, 8}, {0, 0, 16},
-                                  {1, 3, 8},  {1, 1, 8}, {1, 3, 16}, {1, 0, 8}};
+  static const int kCands[][3] = {{0, 1, 16}, {0, 1, 8}, {0, 3, 8}, {0, 0, 16}, {1, 3, 8},
+                                  {1, 1, 8},  {1, 3, 16}, {1, 0, 8}, {1, 2, 4}, {0, 2, 4}};
   const int n_cands = static_cast<int>(sizeof(kCands) / sizeof(kCands[0]));
   auto apply = [&](int half, const int* c) -> nmf_status {
     const int32_t params[3] = {half == 0 ? NMF_PARAM_WIDE_V : NMF_PARAM_WIDE_U,
