@@ -2,14 +2,17 @@
 """Benchmark of the enforced-sparsity ALS hot path on one MI355X.
 
 One step = one ALS iteration of Algorithm 2 with per-column top-t (V half:
-A^T U, FP64 solve, clamp, top-t_v, sparse repack, Gram + Cholesky; U half
+A^T U, FP64 solve, clamp, top-t_v, sparse repack, Gram + FP64 inverse; U half
 mirrored; then R and E), on the 100k terms x 200k docs / 20M-nnz FP32
 workload with k = 50, t_u = 1000, t_v = 2000.  Inputs are synthetic (Zipf
 terms, lognormal TF-IDF values) and resident in HBM before timing starts.
 
-Prints one JSON line: iterations/s, plus the SpMM roofline (algorithmic
-bytes per launch / event-timed launch duration), the FP64 CPU oracle timed
-on a bounded sample of the same workload, and the batched comparison: 256
+Prints one JSON line: iterations/s (timed with only the dominant product
+stage bracketed by HIP events), plus that stage's roofline (algorithmic bytes
+per launch / event-timed stage duration, with the HBM bytes of the counter
+runs when they match the kernel sources), a per-stage breakdown from a
+separate pass with every stage bracketed, the FP64 CPU oracle timed on a
+bounded sample of the same workload, and the batched comparison: 256
 independent corpora of uneven size (n in [500, 50k], m in [300, 20k],
 density 0.1-2 %, k in 5..64) solved per problem, per problem under a HIP
 graph, and with one launch per stage for all of them under a HIP graph.
