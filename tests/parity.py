@@ -1,13 +1,19 @@
 """Comparison helpers for the GPU-vs-oracle parity tests (test code only).
 
-A factor from the GPU and one from the oracle are compared in two parts:
-* values: relative Frobenius error over the entries both keep, normalised
-  by the oracle factor's norm;
+A factor from the GPU and one from the oracle are compared in three parts:
+* values, whole factor: relative Frobenius error over the entries both keep,
+  normalised by the oracle factor's norm;
+* values, per column and per entry: for every column c the relative error
+  ||x_gpu,c - x_or,c|| / ||x_or,c|| over the entries both keep, and for every
+  entry both keep |x_gpu - x_or| <= tol * max(|x_or|, theta_c), i.e. an
+  element-wise relative bound whose floor is the column's threshold theta_c
+  (the smallest value the oracle keeps in that column).  A column or a few
+  entries far off can no longer hide behind the norm of the rest;
 * supports: every entry kept by one side only is a mismatch.  It is a
   near-tie when its pre-selection value lies within ``tol * theta_c`` of the
-  oracle's threshold theta_c of that column (the smallest value the oracle
-  keeps there; for the whole-matrix rule, the smallest it keeps anywhere);
-  otherwise it is a non-tie mismatch.
+  oracle's threshold theta_c of that column (for the whole-matrix rule, the
+  smallest value the oracle keeps anywhere); otherwise it is a non-tie
+  mismatch.
 """
 
 from __future__ import annotations
@@ -19,13 +25,21 @@ import numpy as np
 
 @dataclass
 class FactorDiff:
-    rel: float
+    rel: float          # whole-factor relative Frobenius error (entries both keep)
     mismatches: int
     near_ties: int
     non_ties: int
+    col_rel: float = 0.0   # worst per-column relative error
+    worst_col: int = -1
+    elem: float = 0.0      # worst |dx| / max(|x_or|, theta_c) over entries both keep
 
     def ok(self, tol: float) -> bool:
-        return self.rel <= tol and self.non_ties == 0
+        return self.rel <= tol and self.col_rel <= tol and self.elem <= tol and self.non_ties == 0
+
+    def __str__(self) -> str:
+        return (f"rel {self.rel:.2e} worst column {self.worst_col} ({self.col_rel:.2e}) "
+                f"worst entry {self.elem:.2e} mismatches {self.mismatches} "
+                f"(near-tie {self.near_ties}, non-tie {self.non_ties})")
 
 
 def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol: float = 1e-4,
@@ -39,9 +53,24 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
     both = kg & ko
     den = np.linalg.norm(X_or)
     rel = float(np.linalg.norm(X_gpu[both] - X_or[both]) / den) if den > 0 else float(np.linalg.norm(X_gpu))
+    theta_all = X_or[ko].min() if ko.any() else 0.0
+    # per column: relative error of the entries both keep, element-wise bound
+    D = np.where(both, X_gpu - X_or, 0.0)
+    col_rel, worst_col, elem = 0.0, -1, 0.0
+    for c in range(X_or.shape[1]):
+        kept = X_or[ko[:, c], c]
+        theta = theta_all if whole else (kept.min() if kept.size else 0.0)
+        dc = D[:, c]
+        nc = np.linalg.norm(X_or[:, c])
+        r = float(np.linalg.norm(dc) / nc) if nc > 0 else float(np.linalg.norm(dc))
+        if worst_col < 0 or r > col_rel:
+            col_rel, worst_col = r, c
+        sel = both[:, c]
+        if sel.any():
+            floor = np.maximum(np.abs(X_or[sel, c]), max(theta, 1e-300))
+            elem = max(elem, float(np.max(np.abs(dc[sel]) / floor)))
     mism = kg != ko
     near = non = 0
-    theta_all = X_or[ko].min() if ko.any() else 0.0
     for c in np.nonzero(mism.any(axis=0))[0]:
         kept = X_or[ko[:, c], c]
         theta = theta_all if whole else (kept.min() if kept.size else 0.0)
@@ -51,7 +80,7 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
                 near += 1
             else:
                 non += 1
-    return FactorDiff(rel, int(mism.sum()), near, non)
+    return FactorDiff(rel, int(mism.sum()), near, non, col_rel, worst_col, elem)
 
 
 def rel_fro(a, b) -> float:
@@ -59,3 +88,24 @@ def rel_fro(a, b) -> float:
     b = np.asarray(b, np.float64)
     d = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / d) if d > 0 else float(np.linalg.norm(a))
+
+
+def col_rel(a, b) -> float:
+    """Worst per-column relative Frobenius error of ``a`` against ``b`` (a
+    column of ``b`` that is entirely zero contributes ``||a_c||``)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if a.ndim == 1:
+        return rel_fro(a, b)
+    worst = 0.0
+    for c in range(b.shape[1]):
+        worst = max(worst, rel_fro(a[:, c], b[:, c]))
+    return worst
+
+
+def check_pre(a, b, tol: float) -> float:
+    """A pre-selection (or raw product) matrix against the oracle's: the whole
+    matrix and every column within ``tol`` relative; returns the worst."""
+    w = max(rel_fro(a, b), col_rel(a, b))
+    assert w <= tol, f"pre-selection matrix off: whole {rel_fro(a, b):.2e}, worst column {col_rel(a, b):.2e}"
+    return w

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests.parity import rel_fro
+from tests.parity import check_pre, col_rel, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -40,16 +40,16 @@ def test_fp32_100kx200k_half_steps():
         vpre = prob.pre(0)
         _, V = prob.factors()
         _, info = oracle.half_step(At, U_in.astype(np.float64), p["t_v"])
-        rv = rel_fro(vpre, oracle.clamp(info["X_pre"]))
+        rv = check_pre(vpre, oracle.clamp(info["X_pre"]), 1e-4)
         np.testing.assert_array_equal(V, oracle.topt_per_column(vpre.astype(np.float64), p["t_v"]).astype(np.float32))
         assert int(np.count_nonzero(V)) == int(np.minimum((vpre > 0).sum(0), p["t_v"]).sum())
         prob.half_step(1)
         upre = prob.pre(1)
         U, _ = prob.factors()
         _, info = oracle.half_step(A, V.astype(np.float64), p["t_u"])
-        ru = rel_fro(upre, oracle.clamp(info["X_pre"]))
+        ru = check_pre(upre, oracle.clamp(info["X_pre"]), 1e-4)
         np.testing.assert_array_equal(U, oracle.topt_per_column(upre.astype(np.float64), p["t_u"]).astype(np.float32))
-        _say(f"  iteration {it}: V_pre rel {rv:.2e}, U_pre rel {ru:.2e}, nnz U {np.count_nonzero(U)} V {np.count_nonzero(V)}")
+        _say(f"  iteration {it}: V_pre worst (whole or column) rel {rv:.2e}, U_pre {ru:.2e}, nnz U {np.count_nonzero(U)} V {np.count_nonzero(V)}")
         assert rv <= 1e-4 and ru <= 1e-4, (it, rv, ru)
     # a full iteration records E; it matches the oracle's E of the GPU's factors
     prob.step(1)
@@ -94,6 +94,7 @@ def test_fp32_100kx200k_loss_and_gradient():
     _say(f"  L gpu {float(L.detach()):.6e} oracle {L_or:.6e}; grad rel U {rel_fro(gU, gU_or):.2e} V {rel_fro(gV, gV_or):.2e}")
     assert float(L.detach()) == pytest.approx(L_or, rel=1e-4)
     assert rel_fro(gU, gU_or) <= 1e-4 and rel_fro(gV, gV_or) <= 1e-4
+    assert col_rel(gU, gU_or) <= 1e-4 and col_rel(gV, gV_or) <= 1e-4, (col_rel(gU, gU_or), col_rel(gV, gV_or))
     U64, V64 = U.astype(np.float64), V.astype(np.float64)
     GU, GV = U64.T @ U64, V64.T @ V64
     At = A.T.tocsr()

@@ -13,7 +13,7 @@ import scipy.sparse as sp
 
 import oracle
 import synth
-from tests.parity import compare_factor, rel_fro
+from tests.parity import check_pre, compare_factor, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -87,18 +87,17 @@ def _teacher_forced(c, u0, k, t_u, t_v, iters, tol=1e-4):
         prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32))
         prob.half_step(0)
         vpre = prob.pre(0)
-        assert rel_fro(vpre, oracle.clamp(s["V_pre"])) <= tol, ("V_pre", i)
+        check_pre(vpre, oracle.clamp(s["V_pre"]), tol)
         _, V = prob.factors()
         dv = compare_factor(V, s["V"], s["V_pre"], tol)
         prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32), v=np.ascontiguousarray(s["V"], np.float32))
         prob.half_step(1)
         upre = prob.pre(1)
-        assert rel_fro(upre, oracle.clamp(s["U_pre"])) <= tol, ("U_pre", i)
+        check_pre(upre, oracle.clamp(s["U_pre"]), tol)
         U, _ = prob.factors()
         du = compare_factor(U, s["U"], s["U_pre"], tol)
         report.append((i, dv, du))
-        _say(f"  iter {i}: V rel {dv.rel:.2e} mism {dv.mismatches} (near-tie {dv.near_ties}) | "
-             f"U rel {du.rel:.2e} mism {du.mismatches} (near-tie {du.near_ties})")
+        _say(f"  iter {i}: V {dv} | U {du}")
         assert dv.ok(tol) and du.ok(tol), (i, dv, du)
     prob.close()
     return report

@@ -9,7 +9,7 @@ import scipy.sparse as sp
 
 import oracle
 import synth
-from tests.parity import compare_factor, rel_fro
+from tests.parity import check_pre, compare_factor, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -69,16 +69,15 @@ def test_whole_fp32_teacher_forced(k):
     for i, s in enumerate(st.steps):
         prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32))
         prob.half_step(0)
-        assert rel_fro(prob.pre(0), oracle.clamp(s["V_pre"])) <= 1e-4, ("V_pre", i)
+        check_pre(prob.pre(0), oracle.clamp(s["V_pre"]), 1e-4)
         _, V = prob.factors()
         dv = compare_factor(V, s["V"], s["V_pre"], 1e-4, whole=True)
         prob.set_factors(np.ascontiguousarray(s["U_in"], np.float32), v=np.ascontiguousarray(s["V"], np.float32))
         prob.half_step(1)
-        assert rel_fro(prob.pre(1), oracle.clamp(s["U_pre"])) <= 1e-4, ("U_pre", i)
+        check_pre(prob.pre(1), oracle.clamp(s["U_pre"]), 1e-4)
         U, _ = prob.factors()
         du = compare_factor(U, s["U"], s["U_pre"], 1e-4, whole=True)
-        _say(f"  iter {i}: V rel {dv.rel:.2e} mism {dv.mismatches} (near-tie {dv.near_ties}) | "
-             f"U rel {du.rel:.2e} mism {du.mismatches} (near-tie {du.near_ties})")
+        _say(f"  iter {i}: V {dv} | U {du}")
         assert dv.ok(1e-4) and du.ok(1e-4), (i, dv, du)
         assert np.count_nonzero(V) == min(t_v, np.count_nonzero(oracle.clamp(s["V_pre"])))
         assert np.count_nonzero(U) == min(t_u, np.count_nonzero(oracle.clamp(s["U_pre"])))

@@ -301,6 +301,57 @@ def test_error_expansion_matches_dense():
     assert oracle.error(A, U, V) == pytest.approx(np.sqrt((D * D).sum() / nA2), rel=1e-12)
 
 
+def test_error_expansion_branch_matches_dense_large():
+    """Past n*m = 4e6 the oracle's E switches to the expansion
+    ||A||^2 - 2<U, AV> + <U^T U, V^T V> (Section 3.1's E, expanded so that no
+    dense n x m matrix is formed).  Drive that branch on a 2100 x 2000 corpus
+    and compare it with the dense definition formed explicitly: a dropped
+    term, a wrong factor or a transposed Gram product moves E by O(1)."""
+    n, m, k = 2100, 2000, 7
+    assert n * m > 4_000_000
+    c = synth.make_corpus(n, m, seed=31, alpha=1.1, nnz=60_000)
+    A = c.scipy()
+    U0, _ = synth.make_init(n, m, k, seed=31)
+    st = oracle.als(A, U0, t_u=150, t_v=120, iters=2)
+    e_branch = oracle.error(A, st.U, st.V)
+    e_branch_c = oracle.error(A, st.U, st.V, C=A @ st.V)
+    D = A.toarray() - st.U @ st.V.T
+    e_dense = float(np.sqrt((D * D).sum()) / np.sqrt((A.data ** 2).sum()))
+    assert 0.1 < e_dense < 1.0
+    assert e_branch == pytest.approx(e_dense, rel=1e-12)
+    assert e_branch_c == pytest.approx(e_dense, rel=1e-12)
+    # the history the iteration records goes through the same branch
+    assert st.E[-1] == pytest.approx(e_dense, rel=1e-12)
+
+
+def test_error_expansion_branch_exact_recovery_large():
+    """Disjoint-support blocks scaled past n*m = 4e6: A = U0 V0^T is recovered
+    in one iteration from U0 (Section 3.1's E is then zero).  Through the
+    expansion E is zero up to cancellation: nA2, 2<U,AV> and <G_U,G_V> agree
+    to about 1e-15 relative, so E <= 1e-7 (sqrt of the rounding floor), while
+    the dense definition reaches 1e-12."""
+    rng = np.random.default_rng(33)
+    n, m, k = 2400, 1800, 4
+    assert n * m > 4_000_000
+    rb = np.array_split(rng.permutation(n), k)
+    db = np.array_split(rng.permutation(m), k)
+    U0 = np.zeros((n, k))
+    V0 = np.zeros((m, k))
+    for cc in range(k):
+        U0[rb[cc], cc] = rng.uniform(0.5, 1.5, rb[cc].size)
+        V0[db[cc], cc] = rng.uniform(0.5, 1.5, db[cc].size)
+    A = sp.csr_matrix(U0 @ V0.T)
+    st = oracle.als(A, U0, max(map(len, rb)), max(map(len, db)), 1)
+    assert st.E[0] <= 1e-7
+    assert oracle.error_direct(A, st.U, st.V) <= 1e-12
+    # a perturbed V moves the expansion exactly as the dense definition
+    Vp = st.V.copy()
+    Vp[db[0], 0] *= 1.01
+    D = A.toarray() - st.U @ Vp.T
+    e_dense = float(np.linalg.norm(D) / np.sqrt((A.data ** 2).sum()))
+    assert oracle.error(A, st.U, Vp) == pytest.approx(e_dense, rel=1e-7)
+
+
 def test_residual_definition_is_relative_to_new_iterate():
     U_old = np.array([[1.0, 0.0], [0.0, 2.0]])
     U_new = np.array([[2.0, 0.0], [0.0, 2.0]])
