@@ -274,6 +274,26 @@ nmf_status nmf_enforce(nmf_handle* h, int32_t mode, int64_t t_u, int64_t t_v);
  * 1 <= n_labels <= 256.  Synchronizes.  Errors: INVALID_ARG, STATE (no V). */
 nmf_status nmf_topic_counts(nmf_handle* h, const int32_t* labels, int32_t n_labels, int64_t* counts);
 
+/* Clustering accuracy of Eq. (acc) (Section 3.2) of every topic of the
+ * current V: acc[c] (k doubles, host) for the documents storing an entry in
+ * column c, labelled by labels[d] in [0, n_labels) as in nmf_topic_counts
+ * (the counts come from the same device kernel).  With S the topic's
+ * same-label document pairs, n_D its documents, n_J = n_labels and
+ * q, r = n_D div n_J, n_D mod n_J:
+ *   acc = (S - alpha) / (beta - alpha),
+ *   alpha = q (n_J (q - 1) / 2 + r)   (pairs of the most even spread),
+ *   beta  = n_D (n_D - 1) / 2         (pairs of a single-label topic),
+ * evaluated exactly in 64-bit integers up to the final division; a topic
+ * with at most one document, or n_J = 1, scores 1.  Synchronizes.
+ * Errors: as nmf_topic_counts. */
+nmf_status nmf_topic_accuracy(nmf_handle* h, const int32_t* labels, int32_t n_labels, double* acc);
+
+/* The arithmetic of nmf_topic_accuracy on counts the caller holds (host,
+ * k x n_labels, row-major, counts[c * n_labels + l] >= 0): acc[c] for
+ * c < k (host).  Needs no handle and no device.  Errors: INVALID_ARG
+ * (NULL pointer, k < 1, n_labels < 1, a negative count). */
+nmf_status nmf_accuracy_from_counts(const int64_t* counts, int32_t k, int32_t n_labels, double* acc);
+
 /* Read a tuning parameter into *value.  Errors: INVALID_ARG. */
 nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value);
 

@@ -1036,6 +1036,43 @@ nmf_status nmf_topic_counts(nmf_handle* h, const int32_t* labels, int32_t n_labe
   return NMF_OK;
 }
 
+nmf_status nmf_accuracy_from_counts(const int64_t* counts, int32_t k, int32_t n_labels, double* acc) {
+  if (counts == nullptr || acc == nullptr || k < 1 || n_labels < 1)
+    return fail(nullptr, NMF_ERR_INVALID_ARG, "NULL pointer, k < 1 or n_labels < 1");
+  for (int64_t i = 0; i < static_cast<int64_t>(k) * n_labels; ++i)
+    if (counts[i] < 0) return fail(nullptr, NMF_ERR_INVALID_ARG, "negative count");
+  const int64_t nj = n_labels;
+  for (int32_t c = 0; c < k; ++c) {
+    const int64_t* row = counts + static_cast<int64_t>(c) * n_labels;
+    int64_t nd = 0, same2 = 0;  // documents, twice the same-label pairs
+    for (int64_t l = 0; l < nj; ++l) {
+      nd += row[l];
+      same2 += row[l] * (row[l] - 1);
+    }
+    if (nd <= 1 || nj <= 1) {
+      acc[c] = 1.0;
+      continue;
+    }
+    // twice alpha and beta, so that everything stays integral
+    const int64_t q = nd / nj, r = nd % nj;
+    const int64_t alpha2 = q * (nj * (q - 1) + 2 * r);
+    const int64_t beta2 = nd * (nd - 1);
+    acc[c] = static_cast<double>(same2 - alpha2) / static_cast<double>(beta2 - alpha2);
+  }
+  return NMF_OK;
+}
+
+nmf_status nmf_topic_accuracy(nmf_handle* h, const int32_t* labels, int32_t n_labels, double* acc) {
+  if (h == nullptr || acc == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  if (n_labels < 1 || n_labels > kBins) return fail(h, NMF_ERR_INVALID_ARG, "n_labels must be in 1..256");
+  std::vector<int64_t> counts(static_cast<size_t>(h->k) * n_labels);
+  nmf_status s = nmf_topic_counts(h, labels, n_labels, counts.data());
+  if (s != NMF_OK) return s;
+  s = nmf_accuracy_from_counts(counts.data(), h->k, n_labels, acc);
+  if (s != NMF_OK) return fail(h, s, g_create_error);
+  return NMF_OK;
+}
+
 nmf_status nmf_get_param(nmf_handle* h, int32_t param, int64_t* value) {
   if (h == nullptr || value == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
   switch (param) {

@@ -106,6 +106,8 @@ SIGNATURES = {
     "nmf_enforce": (_I32, [_P, _I32, _I64, _I64]),
     "nmf_sequential": (_I32, [_P, _I32, _I32]),
     "nmf_topic_counts": (_I32, [_P, _P, _I32, _P]),
+    "nmf_topic_accuracy": (_I32, [_P, _P, _I32, _P]),
+    "nmf_accuracy_from_counts": (_I32, [_P, _I32, _I32, _P]),
     "nmf_batch_errors": (_I32, [_P, _P, _P]),
     "nmf_batch_problem": (_P, [_P, _I32]),
     "nmf_batch_last_error": (ctypes.c_char_p, [_P]),
@@ -268,6 +270,22 @@ def nmf_topic_counts(h: int, labels, n_labels: int, k: int) -> np.ndarray:
     out = np.zeros(k * n_labels, np.int64)
     _check(load_library().nmf_topic_counts(h, _ptr(lab), n_labels, _ptr(out)), h)
     return out.reshape(k, n_labels)
+
+
+def nmf_topic_accuracy(h: int, labels, n_labels: int, k: int) -> np.ndarray:
+    lab = labels if not isinstance(labels, np.ndarray) else np.ascontiguousarray(labels, np.int32)
+    out = np.zeros(k, np.float64)
+    _check(load_library().nmf_topic_accuracy(h, _ptr(lab), n_labels, _ptr(out)), h)
+    return out
+
+
+def accuracy_from_counts(counts, n_labels: int) -> np.ndarray:
+    """Eq. (acc) of every topic from its k x n_labels label counts (the
+    library's nmf_accuracy_from_counts; no device needed)."""
+    cnt = np.ascontiguousarray(np.asarray(counts, dtype=np.int64).reshape(-1, n_labels))
+    out = np.zeros(cnt.shape[0], np.float64)
+    _check(load_library().nmf_accuracy_from_counts(_ptr(cnt), cnt.shape[0], n_labels, _ptr(out)), None)
+    return out
 
 
 def nmf_get_param(h: int, param: int) -> int:
@@ -464,9 +482,7 @@ class NMF:
 
     def topic_accuracy(self, labels, n_journals: int) -> np.ndarray:
         """Eq. (acc) of every topic for documents labelled by journal."""
-        from .accuracy import accuracy_from_counts
-
-        return accuracy_from_counts(self.topic_counts(labels, n_journals), n_journals)
+        return nmf_topic_accuracy(self.h, labels, n_journals, self.k)
 
     def sequential(self, k2: int, iters: int):
         """Algorithm 3: k / k2 blocks of k2 topics, ``iters`` iterations each."""

@@ -1,10 +1,11 @@
-"""The library's Eq. (acc) helper (from per-topic journal counts) against the
-oracle's pinned definition (from label lists), on random and edge cases."""
+"""The library's Eq. (acc) arithmetic (nmf_accuracy_from_counts, host code in
+libnmf.so that needs no device) against the oracle's pinned definition (from
+label lists), on random and edge cases."""
 
 import numpy as np
 
 import oracle
-from paper_1510_05237_amd.accuracy import accuracy_from_counts
+from paper_1510_05237_amd import NMFError, accuracy_from_counts
 
 
 def _labels_to_counts(label_lists, n_j):
@@ -30,3 +31,29 @@ def test_accuracy_edge_cases():
     # the most uneven spread that is not a single journal lies strictly between
     a = accuracy_from_counts(np.array([[9, 1, 0]]), 3)[0]
     assert 0.0 < a < 1.0
+
+
+def test_accuracy_rejects_bad_counts():
+    import pytest
+
+    with pytest.raises(NMFError):
+        accuracy_from_counts(np.array([[3, -1]]), 2)
+    with pytest.raises((NMFError, ValueError)):
+        accuracy_from_counts(np.zeros((1, 0), np.int64), 0)
+
+
+def test_accuracy_large_counts_exact():
+    """Counts near the largest corpus size (2^29 documents) stay exact in the
+    library's 64-bit integer arithmetic."""
+    n_j = 3
+    row = np.array([[2 ** 28, 2 ** 27, 12345]])
+    got = accuracy_from_counts(row, n_j)[0]
+    same = sum(int(x) * (int(x) - 1) // 2 for x in row[0])
+    from fractions import Fraction
+
+    n_d = int(row.sum())
+    q, r = divmod(n_d, n_j)
+    alpha = Fraction(q * (n_j * (q - 1) + 2 * r), 2)
+    beta = Fraction(n_d * (n_d - 1), 2)
+    exact = (Fraction(same) - alpha) / (beta - alpha)
+    assert abs(got - float(exact)) <= 1e-15

@@ -86,8 +86,6 @@ def test_topic_counts_and_accuracy():
     NMF, NMFError = _lib()
     import torch
 
-    from paper_1510_05237_amd import accuracy_from_counts
-
     c, labels = synth.make_labeled_corpus(3000, 1500, 4, 40, seed=83, dtype="f64")
     u0, _ = synth.make_init(3000, 1500, 4, seed=83, dtype="f64")
     _say("fp64 planted labels 3000x1500, 4 journals, k=4, 8 iterations, Eq. (acc)")
@@ -99,11 +97,14 @@ def test_topic_counts_and_accuracy():
     np.testing.assert_array_equal(counts, want)
     counts_dev = prob.topic_counts(torch.from_numpy(labels).to("cuda:0"), 4)
     np.testing.assert_array_equal(counts_dev, want)
-    acc = accuracy_from_counts(counts, 4)
+    # Eq. (acc) behind the ABI (device counts, library arithmetic)
+    acc = prob.topic_accuracy(labels, 4)
     st = oracle.als(c.scipy(), u0, 150, 200, 8)
     acc_or = [oracle.topic_accuracy(labels[st.V[:, t] != 0], 4) for t in range(4)]
     np.testing.assert_allclose(acc, acc_or, rtol=0, atol=1e-12)
-    np.testing.assert_allclose(prob.topic_accuracy(labels, 4), acc)
+    np.testing.assert_allclose(prob.topic_accuracy(torch.from_numpy(labels).to("cuda:0"), 4), acc_or, rtol=0, atol=1e-12)
+    with pytest.raises(NMFError):
+        prob.topic_accuracy(labels, 0)
     with pytest.raises(NMFError):
         prob.topic_counts(labels, 0)
     with pytest.raises(NMFError):
