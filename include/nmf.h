@@ -166,13 +166,18 @@ nmf_status nmf_get_pre(nmf_handle* h, int32_t which, void* dst);
 /* Squared loss L = ||A - U V^T||_F^2 = ||A||^2 - 2 tr(U^T A V) + tr(U^T U V^T V)
  * (the squared objective of Eq. (2)) for caller-given dense U (n x k) and
  * V (m x k), device pointers of the handle's dtype.  *loss_dev is a device
- * float64.  Uses the handle's copy of A.  Asynchronous. */
+ * float64.  Uses the handle's copy of A.  Synchronizes with the handle's
+ * stream before (to read the sticky status: while a numerical error is
+ * pending the products would be skipped) and after (a non-finite product
+ * is reported here).  Errors: INVALID_ARG (NULL or host pointer), the
+ * pending sticky status, NONFINITE, DEVICE. */
 nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* loss_dev);
 
 /* Gradient of that loss scaled by the device scalar *g_scale (float64; pass
  * NULL for 1): gU = g (-2 A V + 2 U V^T V), gV = g (-2 A^T U + 2 V U^T U).
  * Device pointers, dtype of the handle, gU n x k and gV m x k (either may be
- * NULL to skip).  Asynchronous. */
+ * NULL to skip).  Synchronizes before and after, as nmf_loss_fwd.
+ * Errors: as nmf_loss_fwd. */
 nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const double* g_scale,
                         void* gU, void* gV);
 

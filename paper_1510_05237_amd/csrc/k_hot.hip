@@ -187,14 +187,21 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
     for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) raw[tt][i] = cold[tt][i] + acc[tt][i];
+    // a non-finite sum or solution (float32 overflow) raises the sticky
+    // NONFINITE status instead of being clamped to zero
+    bool bad = false;
     if (a.W == nullptr) {
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int c = 16 * tt + 4 * q + i;
-          if (ra < a.rows && c < k) a.X[ra * k + c] = raw[tt][i];
+          if (ra < a.rows && c < k) {
+            bad |= !isfinite(raw[tt][i]);
+            a.X[ra * k + c] = raw[tt][i];
+          }
         }
+      if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
       continue;
     }
     // the float64 solve on the matrix cores: out (16 docs x 64 topics) =
@@ -227,8 +234,13 @@ __device__ __forceinline__ void k_hot_body(const HotArgs& a, int blk, int nblk) 
       for (int i = 0; i < 4; ++i) {
         const int64_t r = r0 + q + 4 * i;
         const int c = 16 * tt + m;
-        if (r < a.rows && c < k) a.X[r * k + c] = static_cast<float>(o[tt][i] > 0.0 ? o[tt][i] : 0.0);
+        if (r < a.rows && c < k) {
+          const float y = static_cast<float>(o[tt][i] > 0.0 ? o[tt][i] : 0.0);
+          bad |= !isfinite(o[tt][i]) || !isfinite(y);
+          a.X[r * k + c] = y;
+        }
       }
+    if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
   }
 }
 template <int NT>

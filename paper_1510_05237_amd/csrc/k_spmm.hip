@@ -429,14 +429,22 @@ __device__ __forceinline__ void epilogue(const SpmmArgs& a, const T* tile, const
   const int lane = lane_id();
   const int k = a.k;
   T* __restrict__ X = static_cast<T*>(a.X);
+  // a non-finite sum or solution (float32 overflow) raises the sticky
+  // NONFINITE status instead of being clamped to zero
+  bool bad = false;
   if (RAW) {
     for (int r = 0; r < nrows; ++r) {
 #pragma unroll
       for (int q = 0; q < KPL; ++q) {
         const int c = lane + 64 * q;
-        if (c < k) X[static_cast<int64_t>(r0 + r) * k + c] = tile[c * RG + r];
+        if (c < k) {
+          const T x = tile[c * RG + r];
+          bad |= !isfinite(x);
+          X[static_cast<int64_t>(r0 + r) * k + c] = x;
+        }
       }
     }
+    if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
     return;
   }
   double out[RG][KPL];
@@ -467,12 +475,15 @@ __device__ __forceinline__ void epilogue(const SpmmArgs& a, const T* tile, const
         if (c < k) {
           const double x = out[r][q];
           const int64_t o = static_cast<int64_t>(r0 + r) * k + c;
-          X[o] = static_cast<T>(x > 0.0 ? x : 0.0);
+          const T y = static_cast<T>(x > 0.0 ? x : 0.0);
+          bad |= !isfinite(x) || !isfinite(y);
+          X[o] = y;
           if (STORE_C) static_cast<T*>(a.C)[o] = tile[c * RG + r];
         }
       }
     }
   }
+  if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
 }
 
 template <typename T, int KPL, int RG>

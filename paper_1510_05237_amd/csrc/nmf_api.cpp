@@ -926,6 +926,12 @@ nmf_status nmf_get_pre(nmf_handle* h, int32_t which, void* dst) {
 nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* loss_dev) {
   if (h == nullptr || U == nullptr || V == nullptr || loss_dev == nullptr)
     return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  // every operand is read or written by kernels: host memory would fault
+  if (!is_device_ptr(U) || !is_device_ptr(V) || !is_device_ptr(loss_dev))
+    return fail(h, NMF_ERR_INVALID_ARG, "U, V and the loss must be device memory");
+  // the products below are skipped while the sticky status is set
+  nmf_status st = sync_status(h);
+  if (st != NMF_OK) return st;
   double* GU = h->lossG;
   double* GV = h->lossG + static_cast<size_t>(h->k) * h->k;
   if (h->elt == 8) {
@@ -939,12 +945,17 @@ nmf_status nmf_loss_fwd(nmf_handle* h, const void* U, const void* V, double* los
     HIPCHK(h, gram_dense<float>(h, static_cast<const float*>(V), h->m, GV));
     HIPCHK(h, loss_dot<float>(h, static_cast<const float*>(U), static_cast<const float*>(h->lossC), GU, GV, loss_dev));
   }
-  return NMF_OK;
+  return sync_status(h);
 }
 
 nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const double* g_scale, void* gU,
                         void* gV) {
   if (h == nullptr || U == nullptr || V == nullptr) return fail(h, NMF_ERR_INVALID_ARG, "NULL argument");
+  if (!is_device_ptr(U) || !is_device_ptr(V) || (g_scale != nullptr && !is_device_ptr(g_scale)) ||
+      (gU != nullptr && !is_device_ptr(gU)) || (gV != nullptr && !is_device_ptr(gV)))
+    return fail(h, NMF_ERR_INVALID_ARG, "U, V, the scale and the gradients must be device memory");
+  nmf_status st = sync_status(h);
+  if (st != NMF_OK) return st;
   double* GU = h->lossG;
   double* GV = h->lossG + static_cast<size_t>(h->k) * h->k;
   if (h->elt == 8) {
@@ -972,7 +983,7 @@ nmf_status nmf_loss_bwd(nmf_handle* h, const void* U, const void* V, const doubl
       HIPCHK(h, grad_combine<T>(h, static_cast<const T*>(V), static_cast<const T*>(h->lossB), GU, g_scale, h->m, static_cast<T*>(gV)));
     }
   }
-  return NMF_OK;
+  return sync_status(h);
 }
 
 // Rebuild a stored factor (0: U, 1: V) from its dense form so that its

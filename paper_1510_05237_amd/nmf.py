@@ -515,6 +515,52 @@ class NMF:
             pass
 
 
+def _loss_operands(problem, U, V):
+    """The loss entry points read U (n x k) and V (m x k) of the problem's
+    dtype on the problem's device; anything else is refused before a kernel
+    sees it."""
+    import torch
+
+    for name, X, rows in (("U", U, problem.n), ("V", V, problem.m)):
+        if not isinstance(X, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if X.dtype != problem.torch_dtype:
+            raise TypeError(f"{name} must have the problem's dtype {problem.torch_dtype}")
+        if X.device != torch.device(problem.device):
+            raise ValueError(f"{name} is on {X.device}, the problem on {problem.device}")
+        if tuple(X.shape) != (rows, problem.k):
+            raise ValueError(f"{name} has shape {tuple(X.shape)}, expected {(rows, problem.k)}")
+
+
+class _on_problem_stream:
+    """Orders the problem's stream after the caller's current stream on
+    entry (the operands may still be in flight there) and the current
+    stream after the problem's stream on exit."""
+
+    def __init__(self, problem):
+        self.problem = problem
+
+    def __enter__(self):
+        import torch
+
+        self.cur = torch.cuda.current_stream(self.problem.device)
+        # a batch member runs on the batch's own stream, which torch does not
+        # know: wait for the caller's stream on the host instead
+        self.own = getattr(self.problem, "stream", None)
+        if self.own is None:
+            self.cur.synchronize()
+        elif self.own != self.cur:
+            self.own.wait_stream(self.cur)
+        return self
+
+    def __exit__(self, *exc):
+        # the loss entry points synchronize their stream before returning;
+        # the event wait keeps the order explicit all the same
+        if self.own is not None and self.own != self.cur:
+            self.cur.wait_stream(self.own)
+        return False
+
+
 class NMFLoss:
     """``NMFLoss.apply(problem, U, V)`` -> L = ||A - U V^T||_F^2 (float64 scalar
     tensor) with the hand-written gradient (-2 A V + 2 U V^T V, and the
@@ -530,12 +576,12 @@ class NMFLoss:
             class _Loss(torch.autograd.Function):
                 @staticmethod
                 def forward(ctx, problem, U, V):
+                    _loss_operands(problem, U, V)
                     U = U.contiguous()
                     V = V.contiguous()
-                    if U.dtype != problem.torch_dtype or V.dtype != problem.torch_dtype:
-                        raise TypeError("U and V must have the problem's dtype")
                     out = torch.empty((), dtype=torch.float64, device=U.device)
-                    nmf_loss_fwd(problem.h, U, V, out)
+                    with _on_problem_stream(problem):
+                        nmf_loss_fwd(problem.h, U, V, out)
                     ctx.problem = problem
                     ctx.save_for_backward(U, V)
                     return out
@@ -544,10 +590,11 @@ class NMFLoss:
                 def backward(ctx, g):
                     U, V = ctx.saved_tensors
                     problem = ctx.problem
-                    g = g.to(torch.float64).contiguous()
+                    g = g.to(device=U.device, dtype=torch.float64).contiguous()
                     gU = torch.empty_like(U) if ctx.needs_input_grad[1] else None
                     gV = torch.empty_like(V) if ctx.needs_input_grad[2] else None
-                    nmf_loss_bwd(problem.h, U, V, g, gU, gV)
+                    with _on_problem_stream(problem):
+                        nmf_loss_bwd(problem.h, U, V, g, gU, gV)
                     return None, gU, gV
 
             cls._fn = _Loss
