@@ -37,8 +37,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_traffic_100kx200k.json")
-# the product stages' kernels: the sparse stream and the V half's hot block
-SPMM_SRCS = [os.path.join(ROOT, "paper_1510_05237_amd", "csrc", f) for f in ("k_spmm.hip", "k_hot.hip")]
+# the product stages' kernels: the fused V half and the U half's stream
+SPMM_SRCS = [os.path.join(ROOT, "paper_1510_05237_amd", "csrc", f) for f in ("k_vhalf.hip", "k_spmm.hip")]
 
 
 def log(msg: str):
@@ -511,7 +511,8 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": ("V-half product stage: k_spmm stream + k_spmm_heavy + k_hot dense block (A^T U, float64 solve)"
+        "kernel": ("V-half product stage: k_vhalf (A^T U: hot block on fp32 MFMA + streamed gathers, "
+                   "float64 MFMA solve, clamp)"
                    if dom == "spmm_v" else "U-half product stage: k_spmm + k_spmm_heavy (A V, float64 solve)"),
         "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"],
         "launch_ms": round(kern[dom]["ms"], 4),

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnmf.so")
 
-SOURCES = ["k_spmm.hip", "k_hot.hip", "k_select.hip", "k_repack.hip", "k_gram.hip", "k_metrics.hip", "k_seq.hip", "nmf_api.cpp"]
+SOURCES = ["k_spmm.hip", "k_vhalf.hip", "k_select.hip", "k_repack.hip", "k_gram.hip", "k_metrics.hip", "k_seq.hip", "nmf_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -654,15 +654,7 @@ hipError_t spmm_stream(nmf_handle* h, const Plan& p, const Factor& F, const doub
   a.status = h->status;
   const bool two = h->k > 64;
   const bool dense = dense_in != nullptr;
-  if constexpr (sizeof(T) == 4) {
-    if (p.n_hot > 0) {
-      // the stream without the hot columns leaves raw sums; hot_finish adds
-      // the hot block's product and solves
-      if (C != nullptr || two) return hipErrorInvalidValue;
-      return dense ? launch<T, 1, 8, true, false, true, false>(h, a, waves)
-                   : launch<T, 1, 8, true, false, false, false>(h, a, waves);
-    }
-  }
+  if (p.n_hot > 0) return hipErrorInvalidValue;  // a hot block belongs to the fused V-half kernel
   if (raw) {
     if (dense)
       return two ? launch<T, 2, 4, true, false, true, false>(h, a, waves) : launch<T, 1, 8, true, false, true, false>(h, a, waves);
@@ -681,17 +673,23 @@ hipError_t spmm_stream(nmf_handle* h, const Plan& p, const Factor& F, const doub
 }  // namespace
 
 // Every product records the same number of launches (the stream, its long
-// rows, then the hot block's launch or an empty one), so that batched
-// problems with and without a hot block line up.
+// rows and an empty one; or the fused V-half kernel and two empty ones), so
+// that the launch sequences of a batch's problems line up.
 template <typename T>
 hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
                 bool raw, const T* dense_in, int sparse_row, bool wide, int waves) {
+  if constexpr (sizeof(T) == 4) {
+    if (h->use_vhalf && &p == &h->planAt) {
+      if (C != nullptr) return hipErrorInvalidValue;
+      hipError_t e = vhalf(h, p, F, dense_in, X, raw ? nullptr : W, waves);
+      if (e != hipSuccess) return e;
+      if ((e = vhalf_placeholder(h)) != hipSuccess) return e;
+      return vhalf_placeholder(h);
+    }
+  }
   hipError_t e = spmm_stream<T>(h, p, F, W, X, C, raw, dense_in, sparse_row, wide, waves);
   if (e != hipSuccess) return e;
-  bool hot = false;
-  if constexpr (sizeof(T) == 4) hot = p.n_hot > 0;
-  if (!hot) return hot_placeholder(h);
-  return hot_finish(h, p, F, reinterpret_cast<const float*>(dense_in), reinterpret_cast<float*>(X), raw ? nullptr : W);
+  return vhalf_placeholder(h);
 }
 
 template hipError_t spmm<float>(nmf_handle*, const Plan&, const Factor&, const double*, float*,

@@ -1,0 +1,425 @@
+// V half-step of Algorithm 2 (step 1) for float32 factors with k <= 64, as
+// one fused kernel:
+//
+//   V_pre[r] = max(0, (sum_{p in doc r} a_p U[term_p]) W),   W = (U^T U)^-1
+//
+// (W null: the raw sums are stored instead, for the loss products).
+//
+// Work unit: a tile of 16 consecutive documents owned by one wave, from
+// their nonzeros to their stored rows of V_pre.
+//
+//  * Hot terms.  The terms that occur in the most documents (their rows of A
+//    were split off into a dense documents x hot block when the handle was
+//    created) are a dense product: after the rest of the tile has streamed,
+//    the wave loads its 16 documents' hot columns as float4 per lane
+//    (holding them during the stream would spill registers at 16 waves per
+//    block) and multiplies them by U's
+//    hot rows, staged once per block in LDS, on the fp32 matrix cores
+//    (v_mfma_f32_16x16x4f32), computing the transposed product
+//    (U_H^T)(A_H^T): element i of tile tt then holds document r0 + m,
+//    topic 16 tt + 4 q + i for lane (m = lane % 16, q = lane / 16).
+//  * Every other nonzero is streamed, 64 per step, lanes = nonzeros: its
+//    term's row metadata gives the byte offset of U's row in the compact
+//    dense copy (empty rows are skipped).  The step's hits are queued in
+//    LDS per document, each document's run padded to a multiple of four
+//    with zero-weight entries, and the queue is read in batches of four
+//    rows: lane (c16 = lane % 16, u = lane / 16) loads topics 4 c16 .. + 3
+//    of the batch's row u as one float4 and accumulates them, so one vector
+//    instruction handles four gathered rows.  When the document changes
+//    (wave-uniform: a batch never spans two documents) the four lane groups'
+//    sums are combined by two xor-shuffles in a fixed order and lane group 0
+//    adds them to the document's row of the wave's LDS accumulator.  No
+//    floating-point atomics: every sum is formed in a fixed order, so two
+//    runs are bitwise identical.
+//  * Epilogue: each lane adds the accumulator's sums of its (document,
+//    topic) slots to the hot product it holds, then the float64 solve runs
+//    on the matrix cores (v_mfma_f64_16x16x4f64) with the raw sums as the A
+//    operand straight from registers and W from LDS (the contraction order
+//    of raw W is free); the result holds document r0 + q + 4 i, topic
+//    16 tt + m in element i; it is clamped at zero, rounded to float32 and
+//    stored.  A non-finite sum or solution raises the sticky NONFINITE
+//    status instead of being clamped.
+#include <algorithm>
+
+#include "nmf_device.h"
+
+namespace nmfk {
+
+namespace {
+
+typedef float vh_f4 __attribute__((ext_vector_type(4)));
+typedef double vh_d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kVhTile = 16;                       // documents per wave tile
+constexpr int kVhTopics = 64;                     // topic slots (k <= 64)
+constexpr int kVhQueue = 64 + 3 * kVhTile;        // a step's hits, every document run padded to a multiple of 4
+constexpr int kVhWavesMax = 16;
+constexpr size_t kVhLds = 160 * 1024;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vh_rsrc(const void* p, uint32_t bytes) {
+  // raw buffer: range-checked by byte offset (zero is returned past the end)
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                           0x00020000);
+}
+__device__ __forceinline__ vh_f4 vh_load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(vh_f4, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ float vh_load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ int vh_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Four consecutive topics of a factor row at a byte offset: one 16-byte load
+// from the compact dense copy (rows 64-byte aligned); four 4-byte loads from
+// a caller's dense input, whose rows are only 4-byte aligned.
+template <bool DENSE_IN>
+__device__ __forceinline__ vh_f4 vh_row4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if (DENSE_IN) return vh_f4{vh_load1(r, off), vh_load1(r, off + 4u), vh_load1(r, off + 8u), vh_load1(r, off + 12u)};
+  return vh_load4(r, off);
+}
+
+struct VhArgs {
+  const int64_t* rowptr;   // [rows + 1]: documents' nonzeros of the non-hot terms
+  const int32_t* col;      // term of each nonzero
+  const float* val;
+  const int2* meta;        // U row metadata {compact dense row, entry count}; null for a dense input
+  const float* F;          // compact dense U rows (pitch ld), or the dense input (pitch k)
+  int32_t ld;
+  uint32_t F_bytes;        // bytes of F (every load of it is range-checked)
+  const float* hot;        // [rows][hot_ld]: hot block (null when n_hot == 0)
+  const int32_t* hot_col;  // [n_hot]: U row of hot column h
+  int32_t hot_ld;          // multiple of 16, <= kMaxHot
+  int32_t n_hot;
+  const int32_t* slot;     // U row -> compact dense row (-1: empty), null for a dense input
+  int64_t rows;            // documents
+  int32_t k;
+  const double* W;         // k x k, or null: X receives the raw sums
+  float* X;                // [rows][k]
+  int32_t* status;
+};
+
+// Per wave: the accumulator (16 documents x 64 topics), then the queue's
+// byte offsets and weights.
+constexpr size_t kVhPerWave = kVhTile * kVhTopics * sizeof(float) + kVhQueue * (sizeof(uint32_t) + sizeof(float));
+
+__host__ __device__ inline size_t vh_block_lds(int hot_ld, int k, bool solve) {
+  size_t b = static_cast<size_t>(hot_ld) * kVhTopics * sizeof(float);
+  if (solve) b += static_cast<size_t>(k) * k * sizeof(double);
+  return (b + 15) / 16 * 16;
+}
+
+// Adds the four lane groups' sums (fixed order) of document d into its row
+// of the accumulator and clears them.  Wave-uniform call.
+__device__ __forceinline__ void vh_flush(vh_f4& acc, float* tile, int d, bool live) {
+  const int lane = lane_id();
+  vh_f4 s;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    float v = acc[x] + __shfl_xor(acc[x], 16, 64);
+    s[x] = v + __shfl_xor(v, 32, 64);
+  }
+  if (lane < 16 && live) {
+    vh_f4* t = reinterpret_cast<vh_f4*>(tile + d * kVhTopics + 4 * lane);
+    *t = *t + s;
+  }
+  acc = vh_f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// The tile's non-hot nonzeros [rb[0], rb[16]) into the accumulator.
+template <bool DENSE_IN>
+__device__ __forceinline__ void vh_stream(const VhArgs& a, const int64_t* rb, float* tile, uint32_t* q_off,
+                                          float* q_a) {
+  const int lane = lane_id();
+  const int c16 = lane & 15, u = lane >> 4;
+  const bool live = 4 * c16 < a.k;
+  const __amdgpu_buffer_rsrc_t Fr = vh_rsrc(a.F, a.F_bytes);
+  const uint32_t ldb = static_cast<uint32_t>(a.ld) * 4u;
+  const uint32_t lo = 16u * static_cast<uint32_t>(c16);
+  vh_f4 acc = {0.f, 0.f, 0.f, 0.f};
+  int cur_d = 0;
+  const int64_t p_end = rb[kVhTile];
+  for (int64_t base = rb[0]; base < p_end; base += 64) {
+    const int64_t p = base + lane;
+    const bool valid = p < p_end;
+    int32_t j = 0;
+    float av = 0.f;
+    if (valid) {
+      j = __builtin_nontemporal_load(&a.col[p]);
+      av = __builtin_nontemporal_load(&a.val[p]);
+    }
+    int d = 0;
+#pragma unroll
+    for (int i = 1; i < kVhTile; ++i) d += p >= rb[i] ? 1 : 0;
+    bool hit = false;
+    uint32_t off = 0;
+    if (DENSE_IN) {
+      hit = valid;
+      off = static_cast<uint32_t>(j) * ldb;
+    } else if (valid) {
+      const int2 m = a.meta[j];
+      hit = m.y > 0;
+      off = static_cast<uint32_t>(m.x) * ldb;
+    }
+    const int64_t left = p_end - base;
+    const int last = left < 64 ? static_cast<int>(left) - 1 : 63;
+    const int d_lo = vh_uniform(d);
+    const int d_hi = vh_uniform(__shfl(d, last, 64));
+    for (int dd = d_lo; dd <= d_hi; ++dd) {
+      const bool mine = hit && d == dd;
+      const uint64_t mb = __ballot(mine);
+      if (mb == 0) continue;
+      if (dd != cur_d) {
+        vh_flush(acc, tile, cur_d, live);
+        cur_d = dd;
+      }
+      const int cnt = __popcll(mb);
+      const int cnt4 = (cnt + 3) & ~3;
+      if (mine) {
+        const int pos = lane_rank(mb);
+        q_off[pos] = off;
+        q_a[pos] = av;
+      }
+      if (lane < cnt4 - cnt) {  // zero-weight padding (row 0 of F, or zeros past its end)
+        q_off[cnt + lane] = 0u;
+        q_a[cnt + lane] = 0.f;
+      }
+      __builtin_amdgcn_wave_barrier();
+      // batches of four rows, up to four batches' loads in flight
+      for (int h = 0; h < cnt4; h += 16) {
+        vh_f4 f[4];
+        float w[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int e = h + 4 * b + u;
+          const bool in = h + 4 * b < cnt4;
+          const uint32_t o = in ? q_off[e] : 0u;
+          w[b] = in ? q_a[e] : 0.f;
+          f[b] = (in && live) ? vh_row4<DENSE_IN>(Fr, o + lo) : vh_f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc += w[b] * f[b];
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  vh_flush(acc, tile, cur_d, live);
+}
+
+template <int NT, bool DENSE_IN>
+__device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (*a.status != 0) return;
+  const int k = a.k;
+  const int H = a.n_hot > 0 ? a.hot_ld : 0;
+  const bool solve = a.W != nullptr;
+  float* ub = reinterpret_cast<float*>(smem);  // [H / 16][4][64][4]
+  double* sW = reinterpret_cast<double*>(smem + static_cast<size_t>(H) * kVhTopics * sizeof(float));
+  unsigned char* waves0 = smem + vh_block_lds(H, k, solve);
+  // stage U's hot rows (zeros for empty rows and topics past k) and W
+  if (H > 0) {
+    const __amdgpu_buffer_rsrc_t fr = vh_rsrc(a.F, a.F_bytes);
+    for (int i = threadIdx.x; i < H * kVhTopics; i += blockDim.x) {
+      const int hc = i / kVhTopics, c = i - hc * kVhTopics;
+      int64_t off = -1;
+      if (hc < a.n_hot) {
+        const int r = a.hot_col[hc];
+        const int s = a.slot != nullptr ? a.slot[r] : r;
+        if (s >= 0) off = static_cast<int64_t>(s) * a.ld * 4;
+      }
+      const float v = vh_load1(fr, static_cast<uint32_t>(off < 0 ? 0 : off) + 4u * static_cast<uint32_t>(c));
+      ub[(((hc >> 4) * 4 + ((hc >> 2) & 3)) * kVhTopics + c) * 4 + (hc & 3)] = (off >= 0 && c < k) ? v : 0.f;
+    }
+  }
+  if (solve)
+    for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int wv = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  float* tile = reinterpret_cast<float*>(waves0 + wv * kVhPerWave);
+  uint32_t* q_off = reinterpret_cast<uint32_t*>(tile + kVhTile * kVhTopics);
+  float* q_a = reinterpret_cast<float*>(q_off + kVhQueue);
+  const int bw = blockDim.x >> 6;
+  const int64_t nw = static_cast<int64_t>(nblk) * bw;
+  const int64_t tiles = (a.rows + kVhTile - 1) / kVhTile;
+  constexpr int HG = kMaxHot / 16;
+  const __amdgpu_buffer_rsrc_t hr = vh_rsrc(a.hot, static_cast<uint32_t>(H > 0 ? a.rows * H * 4 : 0));
+  for (int64_t t = static_cast<int64_t>(blk) * bw + wv; t < tiles; t += nw) {
+    const int64_t r0 = kVhTile * t;
+    const int nrows = static_cast<int>(a.rows - r0 < kVhTile ? a.rows - r0 : kVhTile);
+    // the hot columns of the 16 documents stay in flight during the stream
+    // (rows past the end read as zero)
+    const uint32_t abase = static_cast<uint32_t>((r0 + m) * H + 4 * q) * 4u;
+#pragma unroll
+    for (int i = 0; i < kVhTile * kVhTopics / 64; ++i) tile[lane + 64 * i] = 0.f;
+    int64_t rb[kVhTile + 1];
+#pragma unroll
+    for (int i = 0; i <= kVhTile; ++i) rb[i] = a.rowptr[r0 + (i < nrows ? i : nrows)];
+    __builtin_amdgcn_wave_barrier();
+    vh_stream<DENSE_IN>(a, rb, tile, q_off, q_a);
+    __builtin_amdgcn_wave_barrier();
+    vh_f4 arow4[HG];
+#pragma unroll
+    for (int g = 0; g < HG; ++g)
+      arow4[g] = 16 * g < H ? vh_load4(hr, abase + 64u * g) : vh_f4{0.f, 0.f, 0.f, 0.f};
+    // hot product: tile tt = (U_H^T)(topics 16 tt ..) x (A_H^T)(.., docs)
+    vh_f4 acc[4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[tt] = vh_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int g = 0; g < HG; ++g) {
+      if (16 * g >= H) break;
+      const vh_f4 av = arow4[g];
+      vh_f4 bv[4];
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+        bv[tt] = *reinterpret_cast<const vh_f4*>(&ub[((g * 4 + q) * kVhTopics + 16 * tt + m) * 4]);
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].x, av.x, acc[tt], 0, 0, 0);
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].y, av.y, acc[tt], 0, 0, 0);
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].z, av.z, acc[tt], 0, 0, 0);
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].w, av.w, acc[tt], 0, 0, 0);
+    }
+    // raw sums of document r0 + m, topic 16 tt + 4 q + i: hot product plus
+    // the streamed part from the accumulator
+    float raw[4][4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const vh_f4 cold = *reinterpret_cast<const vh_f4*>(tile + m * kVhTopics + 16 * tt + 4 * q);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) raw[tt][i] = 16 * tt + 4 * q + i < k ? acc[tt][i] + cold[i] : 0.f;
+    }
+    bool bad = false;
+    const int64_t ra = r0 + m;
+    if (!solve) {
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int c = 16 * tt + 4 * q + i;
+          if (ra < a.rows && c < k) {
+            bad |= !isfinite(raw[tt][i]);
+            a.X[ra * k + c] = raw[tt][i];
+          }
+        }
+      if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
+      continue;
+    }
+    // float64 solve on the matrix cores: out (16 docs x 64 topics) =
+    // raw (16 x k) W (k x 64); step (tt, i) takes in lane (m, q) the raw sum
+    // of topic rr = 16 tt + 4 q + i as the A operand's column q and
+    // W[rr][16 t2 + m] as the B operand's row q
+    vh_d4 o[4];
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) o[tt] = vh_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (16 * tt + i >= k) break;
+        const int rr = 16 * tt + 4 * q + i;
+        const double av = static_cast<double>(raw[tt][i]);
+#pragma unroll
+        for (int t2 = 0; t2 < NT; ++t2) {
+          const int c = 16 * t2 + m;
+          const double bv = (rr < k && c < k) ? sW[rr * k + c] : 0.0;
+          o[t2] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, o[t2], 0, 0, 0);
+        }
+      }
+    // o[tt][i]: document r0 + q + 4 i, topic 16 tt + m
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = r0 + q + 4 * i;
+        const int c = 16 * tt + m;
+        if (r < a.rows && c < k) {
+          const float y = static_cast<float>(o[tt][i] > 0.0 ? o[tt][i] : 0.0);
+          bad |= !isfinite(o[tt][i]) || !isfinite(y);
+          a.X[r * k + c] = y;
+        }
+      }
+    if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
+  }
+}
+
+template <int NT, bool DENSE_IN>
+__global__ __launch_bounds__(64 * kVhWavesMax) void k_vhalf(VhArgs a) {
+  vh_body<NT, DENSE_IN>(a, blockIdx.x, gridDim.x);
+}
+template <int NT, bool DENSE_IN>
+__global__ __launch_bounds__(64 * kVhWavesMax) void k_vhalf_b(const VhArgs* as, const BlockMap* map) {
+  const BlockMap mp = map[blockIdx.x];
+  const VhArgs a = as[mp.prob];
+  vh_body<NT, DENSE_IN>(a, mp.blk, mp.nblk);
+}
+
+template <int NT, bool DENSE_IN>
+hipError_t vh_launch(nmf_handle* h, const VhArgs& a, int waves_max) {
+  const size_t blk_lds = vh_block_lds(a.n_hot > 0 ? a.hot_ld : 0, a.k, a.W != nullptr);
+  int waves = std::min(std::max(waves_max, 1), kVhWavesMax);
+  while (waves > 1 && blk_lds + waves * kVhPerWave > kVhLds) waves /= 2;
+  const size_t lds = blk_lds + waves * kVhPerWave;
+  if (lds > kVhLds) return hipErrorInvalidValue;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_vhalf<NT, DENSE_IN>, 64 * waves, lds) != hipSuccess)
+    return hipErrorInvalidValue;
+  if (per_cu < 1) per_cu = 1;
+  const int64_t tiles = (a.rows + kVhTile - 1) / kVhTile;
+  const unsigned blocks =
+      static_cast<unsigned>(std::min<int64_t>((tiles + waves - 1) / waves, static_cast<int64_t>(h->num_cus) * per_cu));
+  return launch_rec(h, k_vhalf<NT, DENSE_IN>, k_vhalf_b<NT, DENSE_IN>, blocks, 64u * waves, lds, a);
+}
+
+template <bool DENSE_IN>
+hipError_t vh_dispatch(nmf_handle* h, const VhArgs& a, int waves) {
+  switch ((a.k + 15) / 16) {
+    case 1: return vh_launch<1, DENSE_IN>(h, a, waves);
+    case 2: return vh_launch<2, DENSE_IN>(h, a, waves);
+    case 3: return vh_launch<3, DENSE_IN>(h, a, waves);
+    default: return vh_launch<4, DENSE_IN>(h, a, waves);
+  }
+}
+
+}  // namespace
+
+hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X, const double* W,
+                 int waves) {
+  // byte offsets into the hot block, F and X are 32-bit
+  if (h->k > kVhTopics || p.hot_ld > kMaxHot || (p.rows + kVhTile) * p.hot_ld * 4 >= (int64_t{1} << 32) ||
+      (p.rows + kVhTile) * h->k * 4 >= (int64_t{1} << 32))
+    return hipErrorInvalidValue;
+  VhArgs a{};
+  a.rowptr = p.rowptr;
+  a.col = p.col;
+  a.val = static_cast<const float*>(p.val);
+  a.meta = dense_in ? nullptr : F.meta;
+  a.F = dense_in ? dense_in : static_cast<const float*>(F.dense);
+  a.ld = dense_in ? h->k : F.ld;
+  a.F_bytes = static_cast<uint32_t>(dense_in ? h->n * h->k * 4 : F.rows * F.ld * 4);
+  a.hot = static_cast<const float*>(p.hot);
+  a.hot_col = p.hot_col;
+  a.hot_ld = p.hot_ld;
+  a.n_hot = p.n_hot;
+  a.slot = dense_in ? nullptr : F.slot;
+  a.rows = p.rows;
+  a.k = h->k;
+  a.W = W;
+  a.X = X;
+  a.status = h->status;
+  return dense_in ? vh_dispatch<true>(h, a, waves) : vh_dispatch<false>(h, a, waves);
+}
+
+// Empty launches in the places of a product's second and third kernels, so
+// that problems of a batch with and without this kernel record equally long
+// launch sequences.
+hipError_t vhalf_placeholder(nmf_handle* h) {
+  VhArgs a{};
+  return launch_rec(h, k_vhalf<4, false>, k_vhalf_b<4, false>, 0, 64, 0, a);
+}
+
+}  // namespace nmfk

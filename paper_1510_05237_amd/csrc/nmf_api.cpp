@@ -326,7 +326,8 @@ nmf_status prof_mark(nmf_handle* h, int closing, int next) {
 // A factor's gather metadata follows the SpMM that gathers it: U is gathered
 // by the V half (threshold sparse_row[0]), V by the U half (sparse_row[1]).
 int sparse_row_of(const nmf_handle* h, const Factor& f) {
-  return &f == &h->V ? h->sparse_row[1] : h->sparse_row[0];
+  if (&f == &h->V) return h->sparse_row[1];
+  return h->use_vhalf ? 0 : h->sparse_row[0];
 }
 
 template <typename T>
@@ -547,13 +548,6 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   if (n_hot && (h->planAt.hot == nullptr || h->planAt.hot_col == nullptr))
     return fail(h, NMF_ERR_WORKSPACE, "internal: no room for the hot block");
   h->planAt.n_hot = n_hot;
-  if (n_hot) {
-    // the stream without the hot terms gathers sparser rows of U (set before
-    // any factor's gather metadata is built)
-    h->sparse_row[0] = 2;
-    h->wide[0] = true;
-    h->waves[0] = 4;
-  }
   h->planAt.hot_ld = hot_ld;
   if (n_hot) {
     HIPCHK(h, hipMemcpy(h->planAt.hot_col, hot.data(), n_hot * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -764,6 +758,11 @@ nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int3
     return fail(nullptr, NMF_ERR_DEVICE, "no HIP device");
   }
   h->hist_cus = h->num_cus;
+  // float32 with k <= 64 (32-bit byte offsets into V_pre): the fused V-half
+  // kernel, whose gathers read every nonempty row of U from its compact
+  // dense copy
+  h->use_vhalf = h->elt == 4 && h->k <= 64 && (h->m + 16) * h->k * 4 < (int64_t{1} << 32);
+  if (h->use_vhalf) h->waves[0] = 16;
   carve(h, h->ws, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
   s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)
                   : do_create<float>(h, a_rowptr, a_col, a_val, u0, v0);

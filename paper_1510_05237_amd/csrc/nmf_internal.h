@@ -216,6 +216,10 @@ struct nmf_handle {
   bool w_stale = false;  // gU.W is not the inverse of U's Gram (after a sequential run)
   bool have_pre_v = false, have_pre_u = false;
   bool metrics_valid = false;  // the newest history record describes the current U, V
+  // float32 with k <= 64: the V half is the fused kernel of k_vhalf.hip
+  // (its own queue replaces the entry-by-entry gathers: NMF_PARAM_SPARSE_ROW_V
+  // and NMF_PARAM_WIDE_V do not apply)
+  bool use_vhalf = false;
   int sparse_row[2] = {1, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
   bool wide[2] = {false, true};               // NMF_PARAM_WIDE_V / _U
   int waves[2] = {16, 8};                     // NMF_PARAM_WAVES_V / _U: waves per SpMM block
@@ -269,13 +273,15 @@ template <typename T>
 hipError_t grad_combine(nmf_handle* h, const T* F, const T* B, const double* G,
                         const double* g_scale, int64_t rows, T* out);
 hipError_t fill_i32(hipStream_t s, int32_t* p, int32_t v, int64_t count);
-// V half with a hot block (k_hot.hip): X holds the raw sums of the rest of
-// the stream; adds the hot block's product, then solves and clamps with W
-// (W null: leaves the raw sums).  float32, k <= 64.
-hipError_t hot_finish(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X,
-                      const double* W);
-// An empty launch in the hot block's place (products without one).
-hipError_t hot_placeholder(nmf_handle* h);
+// V half of float32 problems with k <= 64 (k_vhalf.hip): the whole product
+// A^T U (hot block on the matrix cores, the rest streamed), the float64
+// solve with W and the clamp in one kernel (W null: X receives the raw
+// sums).  U's row metadata must point every nonempty row at its compact
+// dense row (gather threshold 0).
+hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X, const double* W,
+                 int waves);
+// An empty launch record (keeps every product's launch sequence equally long).
+hipError_t vhalf_placeholder(nmf_handle* h);
 
 // Sequential ALS (k_seq.hip, k_gram.hip).
 template <typename T>

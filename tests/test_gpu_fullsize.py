@@ -138,3 +138,58 @@ def test_fp32_100kx200k_loss_and_gradient():
         fd = (Lcol(vp) - Lcol(vm)) / (2 * h)
         assert gV[i, j] == pytest.approx(fd, rel=1e-4, abs=1e-4 * np.abs(gV_or).max())
     prob.close()
+
+
+def test_fp32_100kx200k_free_running_trajectory():
+    """The headline workload (100k x 200k, 20M nnz, k = 50, t_u = 1000,
+    t_v = 2000) run free on the GPU for 30 iterations beside the FP64 oracle
+    run free from the same U0.  Per iteration: E within 1e-4 relative; U and
+    V compared entry by entry and per column (tests/parity.py); every support
+    mismatch counted and split into near-ties (both disputed entries within
+    1e-4 theta_c of the column threshold) and non-ties, and no non-tie is
+    allowed.  After the first near-tie the trajectories may legitimately
+    part, so the GPU is teacher-forced from the oracle's state (U, its
+    predecessor and V) before the next iteration."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_05237_amd import NMF
+    from tests.parity import compare_factor
+
+    c, u0, _, p = synth.make_workload("plain_f32_100kx200k")
+    A = c.scipy()
+    dev = torch.device("cuda:0")
+    iters = 30
+    _say(f"fp32 free-running trajectory {c.n}x{c.m} nnz={c.nnz} k={p['k']}: {iters} iterations against the oracle")
+    prob = NMF(c.n, c.m, torch.from_numpy(c.indptr).to(dev), torch.from_numpy(c.indices).to(dev),
+               torch.from_numpy(c.data).to(dev), torch.from_numpy(u0).to(dev), t_u=p["t_u"], t_v=p["t_v"],
+               dtype="f32", device=dev)
+    st = None
+    forced = 0
+    tot_near = tot_non = 0
+    for it in range(iters):
+        prob.step(1)
+        U, V = prob.factors()
+        E_gpu = prob.error()
+        st = oracle.als(A, u0, p["t_u"], p["t_v"], 1, keep_steps=True, state=st)
+        s = st.steps[-1]
+        st.steps.clear()
+        dv = compare_factor(V, s["V"], s["V_pre"], 1e-4)
+        du = compare_factor(U, s["U"], s["U_pre"], 1e-4)
+        E_or = st.E[-1]
+        tot_near += dv.near_ties + du.near_ties
+        tot_non += dv.non_ties + du.non_ties
+        _say(f"  iteration {it + 1}: E gpu {E_gpu:.8f} oracle {E_or:.8f} | V {dv} | U {du}")
+        assert abs(E_gpu - E_or) <= 1e-4 * E_or, (it, E_gpu, E_or)
+        assert dv.ok(1e-4) and du.ok(1e-4), (it, str(dv), str(du))
+        if dv.mismatches or du.mismatches:
+            # teacher forcing from the oracle's state
+            prob.set_factors(np.ascontiguousarray(s["U"], np.float32),
+                             u_prev=np.ascontiguousarray(s["U_in"], np.float32),
+                             v=np.ascontiguousarray(s["V"], np.float32))
+            forced += 1
+    _say(f"  support mismatches over {iters} iterations: near-tie {tot_near}, non-tie {tot_non}; "
+         f"teacher-forced {forced} times")
+    assert tot_non == 0
+    prob.close()
