@@ -136,6 +136,34 @@ nmf_status nmf_residual(nmf_handle* h, double* R);
 nmf_status nmf_history(nmf_handle* h, double* E, double* R, int64_t* nnz_u, int64_t* nnz_v,
                        int32_t cap, int32_t* len);
 
+/* Fields of the per-iteration record (nmf_history_field). */
+enum {
+  NMF_HIST_E = 0,        /* relative error E (Section 3.1)                          */
+  NMF_HIST_R = 1,        /* relative residual R (Section 3.1)                       */
+  NMF_HIST_NNZ_U = 2,    /* entries stored in U after the iteration                 */
+  NMF_HIST_NNZ_V = 3,    /* entries stored in V                                     */
+  NMF_HIST_DEAD_U = 4,   /* dead topics (all-zero columns) of U                     */
+  NMF_HIST_DEAD_V = 5,   /* dead topics of V                                        */
+  NMF_HIST_COND_U = 6,   /* conditioning of U^T U at the end of the iteration: the
+                            largest G_cc (G^-1)_cc over live topics (1 for
+                            orthogonal columns; a lower bound of the condition
+                            number; NaN after nmf_sequential, which forms only
+                            block inverses)                                         */
+  NMF_HIST_COND_V = 7,   /* the same for V^T V (the matrix the U half solved with)  */
+  NMF_HIST_GATHERED_V = 8, /* factor entries the V-half product gathered since the
+                            previous record: the sum over the streamed nonzeros of A
+                            of the stored entries of the U row each hits (the hot
+                            block's product is dense and not counted)               */
+  NMF_HIST_GATHERED_U = 9, /* the same for the U-half product (rows of V)           */
+  NMF_HIST_NUM_FIELDS = 10
+};
+
+/* One field (NMF_HIST_*) of the per-iteration record, oldest first, for up to
+ * `cap` of the most recent iterations into out (host); *len receives the
+ * number written.  Synchronizes.  Errors: INVALID_ARG (unknown field, NULL
+ * out or len, cap < 0). */
+nmf_status nmf_history_field(nmf_handle* h, int32_t field, double* out, int32_t cap, int32_t* len);
+
 /* Largest nnz(U) + nnz(V) held at the end of any half-step so far, counting
  * U0 (the storage high-water mark of Section 3.2).  Synchronizes. */
 nmf_status nmf_max_nnz(nmf_handle* h, int64_t* max_nnz_uv);

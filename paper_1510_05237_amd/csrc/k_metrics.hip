@@ -62,6 +62,9 @@ struct MetArgs {
   double* partials;
   const double* GU;
   const double* GV;
+  const double* WU;   // inverses of G_U, G_V (conditioning indicator)
+  const double* WV;
+  unsigned long long* gathered;  // [2][kGathSlots], read into the record and cleared
   const double* nA2;
   double* ring;
   int64_t* it;
@@ -225,6 +228,35 @@ __device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, 
   rec[H_NNZV] = static_cast<double>(cnt[1]);
   rec[H_DEADU] = static_cast<double>(cnt[2]);
   rec[H_DEADV] = static_cast<double>(cnt[3]);
+  // conditioning of each Gram matrix: the largest G_cc (G^-1)_cc over live
+  // topics (>= 1; 1 for orthogonal columns; it bounds the condition number
+  // from below and grows without bound as a column approaches the span of
+  // the others)
+  double vif[2] = {__builtin_nan(""), __builtin_nan("")};
+  if (a.GU != nullptr && a.WU != nullptr && a.GV != nullptr && a.WV != nullptr) {
+    for (int f = 0; f < 2; ++f) {
+      const double* G = f == 0 ? a.GU : a.GV;
+      const double* W = f == 0 ? a.WU : a.WV;
+      double v = 1.0;
+      for (int c = 0; c < k; ++c) {
+        const double g = G[c * k + c];
+        if (g > 0.0) v = fmax(v, g * W[c * k + c]);
+      }
+      vif[f] = v;
+    }
+  }
+  rec[H_VIFU] = vif[0];
+  rec[H_VIFV] = vif[1];
+  unsigned long long gs[2] = {0ull, 0ull};
+  if (a.gathered != nullptr) {
+    for (int f = 0; f < 2; ++f)
+      for (int s = 0; s < kGathSlots; ++s) {
+        gs[f] += a.gathered[f * kGathSlots + s];
+        a.gathered[f * kGathSlots + s] = 0ull;
+      }
+  }
+  rec[H_GATHV] = static_cast<double>(gs[0]);
+  rec[H_GATHU] = static_cast<double>(gs[1]);
   *a.it = it + 1;
 }
 __global__ __launch_bounds__(256) void k_metrics_final(MetArgs a) { k_metrics_final_body(a, blockIdx.x, gridDim.x); }
@@ -389,6 +421,9 @@ hipError_t metrics(nmf_handle* h, const Factor& Unew, const Factor& Uold, const 
   a.partials = h->met.partials;
   a.GU = h->gU.G;
   a.GV = h->gV.G;
+  a.WU = h->w_stale ? nullptr : h->gU.W;
+  a.WV = h->w_stale ? nullptr : h->gV.W;
+  a.gathered = h->met.gathered;
   a.nA2 = h->met.nA2;
   a.ring = h->met.ring;
   a.it = h->met.it;

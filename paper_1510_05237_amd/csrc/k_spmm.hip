@@ -90,6 +90,7 @@ struct SpmmArgs {
   void* C;
   int32_t k;
   int32_t* status;
+  unsigned long long* gathered;  // [kGathSlots] entries gathered (null: not counted)
 };
 
 struct WaveLds {
@@ -307,7 +308,7 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
 //    wave mostly waits on the metadata and entry gathers.
 template <typename T, int KPL, int RG, bool DENSE_IN, bool WIDE>
 __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_t p1, const int64_t* rb,
-                                           int nrows, const WaveLds& w) {
+                                           int nrows, const WaveLds& w, uint32_t& gath) {
   constexpr int NS = WIDE ? 2 : 1;
   const int lane = lane_id();
   const int k = a.k;
@@ -368,6 +369,8 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
       }
     }
     if (!DENSE_IN) {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) gath += static_cast<uint32_t>(cnt[s]);
       // sparse factor rows, entry by entry; lanes start at a rotated entry so
       // that one round rarely adds twice to one topic
       bool sparse[NS];
@@ -509,6 +512,7 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
 
   const int bw = blockDim.x >> 6;
   const int nw = nblk * bw;
+  uint32_t gath = 0;  // this lane's gathered entries (fits: at most k per nonzero it loads)
   for (int it = blk * bw + wv; it < a.n_items; it += nw) {
     const WorkItem wi = a.items[it];
     clear_tile<T, KPL, RG>(tile, k);
@@ -521,13 +525,13 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
       int64_t rb[RG + 1];
 #pragma unroll
       for (int i = 0; i <= RG; ++i) rb[i] = a.rowptr[wi.r0 + (i < nrows ? i : nrows)];
-      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, rb[0], rb[nrows], rb, nrows, w);
+      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, rb[0], rb[nrows], rb, nrows, w, gath);
       epilogue<T, KPL, RG, RAW, STORE_C>(a, tile, sW, nrows, wi.r0);
     } else {
       int64_t rb[RG + 1];
 #pragma unroll
       for (int i = 0; i <= RG; ++i) rb[i] = i == 0 ? wi.p0 : wi.p1;
-      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, wi.p0, wi.p1, rb, 1, w);
+      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, wi.p0, wi.p1, rb, 1, w, gath);
       T* part = static_cast<T*>(a.partials);
 #pragma unroll
       for (int q = 0; q < KPL; ++q) {
@@ -535,6 +539,12 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
         if (c < k) part[static_cast<int64_t>(wi.part) * k + c] = tile[c * RG];
       }
     }
+  }
+  if (a.gathered != nullptr) {
+    unsigned long long g = gath;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) g += __shfl_xor(g, d, 64);
+    if (lane == 0 && g != 0) atomicAdd(&a.gathered[(blk * bw + wv) % kGathSlots], g);
   }
 }
 
@@ -652,6 +662,7 @@ hipError_t spmm_stream(nmf_handle* h, const Plan& p, const Factor& F, const doub
   a.C = C;
   a.k = h->k;
   a.status = h->status;
+  a.gathered = dense_in ? nullptr : h->met.gathered + (&p == &h->planA ? kGathSlots : 0);
   const bool two = h->k > 64;
   const bool dense = dense_in != nullptr;
   if (p.n_hot > 0) return hipErrorInvalidValue;  // a hot block belongs to the fused V-half kernel

@@ -96,6 +96,7 @@ struct VhArgs {
   const double* W;         // k x k, or null: X receives the raw sums
   float* X;                // [rows][k]
   int32_t* status;
+  unsigned long long* gathered;  // [kGathSlots]: U entries of the streamed rows (null: not counted)
 };
 
 // Per wave: the accumulator (16 documents x 64 topics), then the queue's
@@ -128,7 +129,7 @@ __device__ __forceinline__ void vh_flush(vh_f4& acc, float* tile, int d, bool li
 // The tile's non-hot nonzeros [rb[0], rb[16]) into the accumulator.
 template <bool DENSE_IN>
 __device__ __forceinline__ void vh_stream(const VhArgs& a, const int64_t* rb, float* tile, uint32_t* q_off,
-                                          float* q_a) {
+                                          float* q_a, uint32_t& gath) {
   const int lane = lane_id();
   const int c16 = lane & 15, u = lane >> 4;
   const bool live = 4 * c16 < a.k;
@@ -159,6 +160,7 @@ __device__ __forceinline__ void vh_stream(const VhArgs& a, const int64_t* rb, fl
       const int2 m = a.meta[j];
       hit = m.y > 0;
       off = static_cast<uint32_t>(m.x) * ldb;
+      gath += static_cast<uint32_t>(m.y);
     }
     const int64_t left = p_end - base;
     const int last = left < 64 ? static_cast<int>(left) - 1 : 63;
@@ -245,6 +247,7 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   const int64_t tiles = (a.rows + kVhTile - 1) / kVhTile;
   constexpr int HG = kMaxHot / 16;
   const __amdgpu_buffer_rsrc_t hr = vh_rsrc(a.hot, static_cast<uint32_t>(H > 0 ? a.rows * H * 4 : 0));
+  uint32_t gath = 0;  // this lane's gathered U entries (at most k per nonzero it loads)
   for (int64_t t = static_cast<int64_t>(blk) * bw + wv; t < tiles; t += nw) {
     const int64_t r0 = kVhTile * t;
     const int nrows = static_cast<int>(a.rows - r0 < kVhTile ? a.rows - r0 : kVhTile);
@@ -257,7 +260,7 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
 #pragma unroll
     for (int i = 0; i <= kVhTile; ++i) rb[i] = a.rowptr[r0 + (i < nrows ? i : nrows)];
     __builtin_amdgcn_wave_barrier();
-    vh_stream<DENSE_IN>(a, rb, tile, q_off, q_a);
+    vh_stream<DENSE_IN>(a, rb, tile, q_off, q_a, gath);
     __builtin_amdgcn_wave_barrier();
     vh_f4 arow4[HG];
 #pragma unroll
@@ -345,6 +348,12 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
       }
     if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
   }
+  if (a.gathered != nullptr) {
+    unsigned long long g = gath;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) g += __shfl_xor(g, d, 64);
+    if (lane == 0 && g != 0) atomicAdd(&a.gathered[(blk * bw + wv) % kGathSlots], g);
+  }
 }
 
 template <int NT, bool DENSE_IN>
@@ -411,6 +420,7 @@ hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* den
   a.W = W;
   a.X = X;
   a.status = h->status;
+  a.gathered = dense_in ? nullptr : h->met.gathered;
   return dense_in ? vh_dispatch<true>(h, a, waves) : vh_dispatch<false>(h, a, waves);
 }
 

@@ -216,6 +216,7 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
   h->met.nA2 = cv.take<double>(1);
   h->met.loss_parts = cv.take<double>(kMetricBlocks);
   h->met.out = cv.take<double>(4);
+  h->met.gathered = cv.take<unsigned long long>(2 * kGathSlots);
   h->status = cv.take<int32_t>(4);
   h->scratch_i = cv.take<int32_t>(4);
   return align_up(cv.off, 256);
@@ -563,6 +564,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   HIPCHK(h, hipMemset(h->met.ticket, 0, 16));
   HIPCHK(h, hipMemset(h->met.it, 0, 8));
   HIPCHK(h, hipMemset(h->met.max_nnz, 0, 8));
+  HIPCHK(h, hipMemset(h->met.gathered, 0, 2 * kGathSlots * sizeof(unsigned long long)));
   HIPCHK(h, hipMemset(h->status, 0, 16));
   HIPCHK(h, hipMemset(h->gU.dead, 0, 16));
   HIPCHK(h, hipMemset(h->gV.dead, 0, 16));
@@ -625,6 +627,7 @@ nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
   const int eta = k / k2;
   const bool rec = !(h->cfg.flags & NMF_FLAG_NO_METRICS);
   h->prof_open = -2;
+  h->w_stale = true;  // only block inverses are formed: the records carry no conditioning
   T* upre = static_cast<T*>(h->upre);
   T* vpre = static_cast<T*>(h->vpre);
   T* C = static_cast<T*>(h->cbuf);
@@ -837,6 +840,22 @@ nmf_status nmf_history(nmf_handle* h, double* E, double* R, int64_t* nnz_u, int6
     if (nnz_u) nnz_u[i] = static_cast<int64_t>(r[H_NNZU]);
     if (nnz_v) nnz_v[i] = static_cast<int64_t>(r[H_NNZV]);
   }
+  *len = static_cast<int32_t>(cnt);
+  return NMF_OK;
+}
+
+nmf_status nmf_history_field(nmf_handle* h, int32_t field, double* out, int32_t cap, int32_t* len) {
+  static_assert(H_FIELDS == NMF_HIST_NUM_FIELDS, "history record layout");
+  if (h == nullptr || out == nullptr || len == nullptr || cap < 0 || field < 0 || field >= H_FIELDS)
+    return fail(h, NMF_ERR_INVALID_ARG, "bad argument");
+  nmf_status s = sync_status(h);
+  if (s != NMF_OK) return s;
+  int64_t it = 0;
+  HIPCHK(h, hipMemcpy(&it, h->met.it, 8, hipMemcpyDeviceToHost));
+  std::vector<double> ring(static_cast<size_t>(kHistRing) * H_FIELDS);
+  HIPCHK(h, hipMemcpy(ring.data(), h->met.ring, ring.size() * 8, hipMemcpyDeviceToHost));
+  const int64_t cnt = std::min<int64_t>(std::min<int64_t>(it, kHistRing), cap);
+  for (int64_t i = 0; i < cnt; ++i) out[i] = ring[((it - cnt + i) % kHistRing) * H_FIELDS + field];
   *len = static_cast<int32_t>(cnt);
   return NMF_OK;
 }

@@ -31,8 +31,9 @@ constexpr int kSelBlockRows = 64;  // rows of the selected matrix per select col
 constexpr int kSelSub = 16;        // candidate sub-lists per column (collect block b appends to b % 16)
 constexpr int kCntStride = 64;     // ints between candidate counters (256 bytes)
 
-// History record fields (float64 each).
-enum { H_E = 0, H_R, H_NNZU, H_NNZV, H_DEADU, H_DEADV, H_FIELDS };
+// History record fields (float64 each), in the order of NMF_HIST_*.
+enum { H_E = 0, H_R, H_NNZU, H_NNZV, H_DEADU, H_DEADV, H_VIFU, H_VIFV, H_GATHV, H_GATHU, H_FIELDS };
+constexpr int kGathSlots = 16;  // spread slots of each gathered-entries counter
 
 // One unit of SpMM work for one wave, over the nonzeros [p0, p1) of the
 // plan's arrays (row-compressed, rows ascending, columns ascending in a row).
@@ -146,6 +147,9 @@ struct Metrics {
   double* nA2 = nullptr;        // ||A||_F^2
   double* loss_parts = nullptr; // [kMetricBlocks]
   double* out = nullptr;        // [4] scalar results of on-demand queries
+  // factor entries the products gathered since the last record: [0] V half,
+  // [1] U half, each spread over kGathSlots words (one atomic add per wave)
+  unsigned long long* gathered = nullptr;  // [2][kGathSlots]
 };
 
 }  // namespace nmfk

@@ -107,6 +107,7 @@ SIGNATURES = {
     "nmf_sequential": (_I32, [_P, _I32, _I32]),
     "nmf_topic_counts": (_I32, [_P, _P, _I32, _P]),
     "nmf_topic_accuracy": (_I32, [_P, _P, _I32, _P]),
+    "nmf_history_field": (_I32, [_P, _I32, _P, _I32, _P]),
     "nmf_accuracy_from_counts": (_I32, [_P, _I32, _I32, _P]),
     "nmf_batch_errors": (_I32, [_P, _P, _P]),
     "nmf_batch_problem": (_P, [_P, _I32]),
@@ -270,6 +271,16 @@ def nmf_topic_counts(h: int, labels, n_labels: int, k: int) -> np.ndarray:
     out = np.zeros(k * n_labels, np.int64)
     _check(load_library().nmf_topic_counts(h, _ptr(lab), n_labels, _ptr(out)), h)
     return out.reshape(k, n_labels)
+
+
+HIST_FIELDS = ("E", "R", "nnz_u", "nnz_v", "dead_u", "dead_v", "cond_u", "cond_v", "gathered_v", "gathered_u")
+
+
+def nmf_history_field(h: int, field: str, cap: int = 4096) -> np.ndarray:
+    out = np.zeros(cap, np.float64)
+    n = ctypes.c_int32()
+    _check(load_library().nmf_history_field(h, HIST_FIELDS.index(field), _ptr(out), cap, ctypes.byref(n)), h)
+    return out[: n.value]
 
 
 def nmf_topic_accuracy(h: int, labels, n_labels: int, k: int) -> np.ndarray:
@@ -475,6 +486,10 @@ class NMF:
 
     def get_param(self, param: int) -> int:
         return nmf_get_param(self.h, param)
+
+    def history_field(self, field: str, cap: int = 4096) -> np.ndarray:
+        """One field of the per-iteration record (see HIST_FIELDS), oldest first."""
+        return nmf_history_field(self.h, field, cap)
 
     def topic_counts(self, labels, n_labels: int) -> np.ndarray:
         """k x n_labels: documents of each label with an entry in each column of V."""

@@ -109,3 +109,21 @@ def check_pre(a, b, tol: float) -> float:
     w = max(rel_fro(a, b), col_rel(a, b))
     assert w <= tol, f"pre-selection matrix off: whole {rel_fro(a, b):.2e}, worst column {col_rel(a, b):.2e}"
     return w
+
+
+def elem_kept(X_gpu, Xpre_or) -> float:
+    """Worst element-wise error of the GPU's kept entries against the oracle's
+    pre-selection values at the same positions (both sides took the step from
+    the same input): max |x_gpu - x_or| / max(|x_or|, theta_c), theta_c the
+    smallest value the GPU keeps in column c."""
+    X_gpu = np.asarray(X_gpu, np.float64)
+    Xp = np.asarray(Xpre_or, np.float64)
+    worst = 0.0
+    for c in range(X_gpu.shape[1]):
+        sel = X_gpu[:, c] != 0
+        if not sel.any():
+            continue
+        theta = X_gpu[sel, c].min()
+        err = np.abs(X_gpu[sel, c] - Xp[sel, c]) / np.maximum(np.abs(Xp[sel, c]), theta)
+        worst = max(worst, float(err.max()))
+    return worst
