@@ -187,6 +187,22 @@ __device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, 
 #pragma unroll
     for (int f = 0; f < 3; ++f) pd[j][f] = b < nparts ? a.partials[b * 4 + f] : 0.0;
   }
+  // conditioning indicator and gathered-entry counts: each diagonal entry
+  // and counter slot is loaded by its own thread (k <= 128 < 256)
+  const bool have_w = a.GU != nullptr && a.WU != nullptr && a.GV != nullptr && a.WV != nullptr;
+  double vl0 = 1.0, vl1 = 1.0;
+  if (have_w && threadIdx.x < k) {
+    const int c = threadIdx.x;
+    const double gu = a.GU[c * k + c], wu = a.WU[c * k + c];
+    const double gv = a.GV[c * k + c], wv = a.WV[c * k + c];
+    if (gu > 0.0) vl0 = gu * wu;
+    if (gv > 0.0) vl1 = gv * wv;
+  }
+  unsigned long long gl = 0ull;
+  if (a.gathered != nullptr && threadIdx.x < 2 * kGathSlots) {
+    gl = a.gathered[threadIdx.x];
+    a.gathered[threadIdx.x] = 0ull;
+  }
   double d = 0.0, n = 0.0, x = 0.0;
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
@@ -211,6 +227,21 @@ __device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, 
     }
   }
   block_sum3(q, 0.0, 0.0, sh, totq);
+  // largest diagonal product per factor (fmax over waves, then blocks of
+  // the wave's lanes); gathered counts: lanes 0-15 (V half), 16-31 (U half)
+  __shared__ double shv[8];
+  __shared__ unsigned long long shg[2];
+  for (int o = 32; o > 0; o >>= 1) {
+    vl0 = fmax(vl0, __shfl_xor(vl0, o, 64));
+    vl1 = fmax(vl1, __shfl_xor(vl1, o, 64));
+  }
+  for (int o = 8; o > 0; o >>= 1) gl += __shfl_xor(gl, o, 64);
+  if (__lane_id() == 0) {
+    shv[(threadIdx.x >> 6) * 2] = vl0;
+    shv[(threadIdx.x >> 6) * 2 + 1] = vl1;
+  }
+  if (threadIdx.x == 0) shg[0] = gl;
+  if (threadIdx.x == kGathSlots) shg[1] = gl;
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double D = tot[0], N = tot[1], X = tot[2];
@@ -233,28 +264,12 @@ __device__ __forceinline__ void k_metrics_final_body(const MetArgs& a, int blk, 
   // from below and grows without bound as a column approaches the span of
   // the others)
   double vif[2] = {__builtin_nan(""), __builtin_nan("")};
-  if (a.GU != nullptr && a.WU != nullptr && a.GV != nullptr && a.WV != nullptr) {
-    for (int f = 0; f < 2; ++f) {
-      const double* G = f == 0 ? a.GU : a.GV;
-      const double* W = f == 0 ? a.WU : a.WV;
-      double v = 1.0;
-      for (int c = 0; c < k; ++c) {
-        const double g = G[c * k + c];
-        if (g > 0.0) v = fmax(v, g * W[c * k + c]);
-      }
-      vif[f] = v;
-    }
-  }
+  if (have_w)
+    for (int f = 0; f < 2; ++f)
+      vif[f] = fmax(fmax(shv[f], shv[2 + f]), fmax(shv[4 + f], shv[6 + f]));
   rec[H_VIFU] = vif[0];
   rec[H_VIFV] = vif[1];
-  unsigned long long gs[2] = {0ull, 0ull};
-  if (a.gathered != nullptr) {
-    for (int f = 0; f < 2; ++f)
-      for (int s = 0; s < kGathSlots; ++s) {
-        gs[f] += a.gathered[f * kGathSlots + s];
-        a.gathered[f * kGathSlots + s] = 0ull;
-      }
-  }
+  const unsigned long long gs[2] = {shg[0], shg[1]};
   rec[H_GATHV] = static_cast<double>(gs[0]);
   rec[H_GATHU] = static_cast<double>(gs[1]);
   *a.it = it + 1;
