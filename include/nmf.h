@@ -109,6 +109,27 @@ nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int3
                       const void* a_val, int64_t nnz, const void* u0, const void* v0,
                       void* workspace, size_t ws_bytes, void* hip_stream, nmf_handle** out);
 
+/* Size of the static workspace behind nmf_create_static, per device. */
+#define NMF_STATIC_WORKSPACE_BYTES (64ull << 20)
+
+/* nmf_create for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * handle, with the library's static device workspace of
+ * NMF_STATIC_WORKSPACE_BYTES (64 MiB; one array per device, held until the
+ * process ends) in place of a caller's workspace.  Arguments, layouts,
+ * ownership of the inputs and behaviour are those of nmf_create.  Allocates
+ * no device memory: no hipMalloc/hipFree/hipHostMalloc and no allocating
+ * library call (host-side set-up uses the C++ heap as nmf_create does).  The
+ * workspace keeps whatever the previous handle left; creation clears what
+ * must start at zero.  One live handle per device owns it: a second call on
+ * the same device before nmf_destroy of the first returns NMF_ERR_STATE
+ * (calls on the one handle from several threads race, as for any handle).
+ * Errors: those of nmf_create, plus WORKSPACE when nmf_workspace_size()
+ * exceeds NMF_STATIC_WORKSPACE_BYTES and STATE as above. */
+nmf_status nmf_create_static(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col,
+                             const void* a_val, int64_t nnz, const void* u0, const void* v0, void* hip_stream,
+                             nmf_handle** out);
+
 /* Enqueue `iters` iterations of Algorithm 2 (V half-step first, from the
  * current U), each followed by R and E of Section 3.1 unless
  * NMF_FLAG_NO_METRICS.  Asynchronous.  iters >= 0. */

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -725,9 +726,16 @@ nmf_status nmf_workspace_size(const nmf_config* cfg, int64_t nnz, size_t* bytes)
   return NMF_OK;
 }
 
-nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col,
-                      const void* a_val, int64_t nnz, const void* u0, const void* v0,
-                      void* workspace, size_t ws_bytes, void* hip_stream, nmf_handle** out) {
+}  // extern "C"
+
+namespace {
+
+// nmf_create with the workspace already chosen; `caller_ws` asks for the
+// checks of a caller's workspace (the static one is known to be device
+// memory of the right alignment).
+nmf_status create_impl(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col, const void* a_val,
+                       int64_t nnz, const void* u0, const void* v0, void* workspace, size_t ws_bytes,
+                       void* hip_stream, nmf_handle** out, bool caller_ws) {
   if (out == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   nmf_status s = check_config(cfg);
@@ -742,7 +750,8 @@ nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int3
     return fail(nullptr, NMF_ERR_WORKSPACE, "workspace smaller than nmf_workspace_size()");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(nullptr, NMF_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-  if (!is_device_ptr(workspace)) return fail(nullptr, NMF_ERR_WORKSPACE, "workspace must be device memory");
+  if (caller_ws && !is_device_ptr(workspace))
+    return fail(nullptr, NMF_ERR_WORKSPACE, "workspace must be device memory");
   nmf_handle* h = new (std::nothrow) nmf_handle();
   if (h == nullptr) return fail(nullptr, NMF_ERR_DEVICE, "out of host memory");
   h->cfg = *cfg;
@@ -777,6 +786,76 @@ nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int3
   }
   *out = h;
   return NMF_OK;
+}
+
+}  // namespace
+
+// The static workspace of nmf_create_static: one array per device (each
+// GPU the library runs on holds its own copy until the process ends).  Host
+// code never passes the array's name to a kernel or a copy: it is a host-side
+// stand-in there.  The device address is taken once per device with
+// hipGetSymbolAddress, with that device current, and kept in `g_static`.
+static __device__ __align__(256) unsigned char scratch[NMF_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxStaticDevices = 64;
+struct StaticWorkspace {
+  void* ptr = nullptr;    // device address of `scratch` on this device
+  bool in_use = false;    // a live handle owns it
+};
+std::mutex g_static_mu;
+StaticWorkspace g_static[kMaxStaticDevices];
+
+}  // namespace
+
+extern "C" {
+
+nmf_status nmf_create(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col,
+                      const void* a_val, int64_t nnz, const void* u0, const void* v0,
+                      void* workspace, size_t ws_bytes, void* hip_stream, nmf_handle** out) {
+  return create_impl(cfg, a_rowptr, a_col, a_val, nnz, u0, v0, workspace, ws_bytes, hip_stream, out, true);
+}
+
+nmf_status nmf_create_static(const nmf_config* cfg, const int64_t* a_rowptr, const int32_t* a_col,
+                             const void* a_val, int64_t nnz, const void* u0, const void* v0, void* hip_stream,
+                             nmf_handle** out) {
+  if (out == nullptr) return fail(nullptr, NMF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  nmf_status s = check_config(cfg);
+  if (s != NMF_OK) return s;
+  if (nnz < 0) return fail(nullptr, NMF_ERR_INVALID_ARG, "nnz < 0");
+  size_t need = 0;
+  s = nmf_workspace_size(cfg, nnz, &need);
+  if (s != NMF_OK) return s;
+  if (need > NMF_STATIC_WORKSPACE_BYTES)
+    return fail(nullptr, NMF_ERR_WORKSPACE,
+                "problem needs " + std::to_string(need) + " bytes of workspace; the static workspace holds " +
+                    std::to_string(static_cast<unsigned long long>(NMF_STATIC_WORKSPACE_BYTES)) +
+                    " (use nmf_create with a caller workspace)");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxStaticDevices)
+    return fail(nullptr, NMF_ERR_DEVICE, "no HIP device for the static workspace");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticWorkspace& sw = g_static[dev];
+  if (sw.in_use)
+    return fail(nullptr, NMF_ERR_STATE,
+                "the static workspace of device " + std::to_string(dev) +
+                    " belongs to a live handle; destroy that handle first");
+  if (sw.ptr == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(nullptr, NMF_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    sw.ptr = p;
+  }
+  s = create_impl(cfg, a_rowptr, a_col, a_val, nnz, u0, v0, sw.ptr, NMF_STATIC_WORKSPACE_BYTES, hip_stream, out,
+                  false);
+  if (s == NMF_OK) {
+    sw.in_use = true;
+    (*out)->static_dev = dev;
+  }
+  return s;
 }
 
 nmf_status nmf_als_step(nmf_handle* h, int32_t iters) {
@@ -1193,6 +1272,10 @@ void nmf_destroy(nmf_handle* h) {
   if (h == nullptr) return;
   (void)hipStreamSynchronize(h->stream);
   for (auto& e : h->prof_ev) (void)hipEventDestroy(e);
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[h->static_dev].in_use = false;
+  }
   delete h;
 }
 

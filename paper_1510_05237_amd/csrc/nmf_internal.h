@@ -186,6 +186,7 @@ struct nmf_handle {
   int mask_words = 1;
   hipStream_t stream = nullptr;
   int device = 0;
+  int static_dev = -1;  // device whose static workspace this handle owns (nmf_create_static), else -1
   int num_cus = 256;
   // Compute units this problem's histogram pass is sized for: all of them
   // alone and in a batch's per-problem loop, its share of the GPU in a

@@ -78,6 +78,7 @@ SIGNATURES = {
     "nmf_workspace_size": (_I32, [ctypes.POINTER(nmf_config), _I64, ctypes.POINTER(ctypes.c_size_t)]),
     "nmf_create": (_I32, [ctypes.POINTER(nmf_config), _P, _P, _P, _I64, _P, _P, _P, ctypes.c_size_t, _P,
                           ctypes.POINTER(_P)]),
+    "nmf_create_static": (_I32, [ctypes.POINTER(nmf_config), _P, _P, _P, _I64, _P, _P, _P, ctypes.POINTER(_P)]),
     "nmf_als_step": (_I32, [_P, _I32]),
     "nmf_half_step": (_I32, [_P, _I32]),
     "nmf_error": (_I32, [_P, _PD]),
@@ -179,6 +180,15 @@ def nmf_create(cfg, a_rowptr, a_col, a_val, nnz, u0, v0, workspace, ws_bytes, st
     h = _P()
     st = load_library().nmf_create(ctypes.byref(cfg), _ptr(a_rowptr), _ptr(a_col), _ptr(a_val), nnz,
                                    _ptr(u0), _ptr(v0), _ptr(workspace), ws_bytes, stream, ctypes.byref(h))
+    _check(st, None)
+    return h.value
+
+
+def nmf_create_static(cfg, a_rowptr, a_col, a_val, nnz, u0, v0, stream) -> int:
+    """nmf_create on the library's static device workspace (no allocation)."""
+    h = _P()
+    st = load_library().nmf_create_static(ctypes.byref(cfg), _ptr(a_rowptr), _ptr(a_col), _ptr(a_val), nnz,
+                                          _ptr(u0), _ptr(v0), stream, ctypes.byref(h))
     _check(st, None)
     return h.value
 
@@ -404,10 +414,12 @@ class NMF:
     ``indptr``/``indices``/``data``: A in CSR over term rows (numpy arrays or
     torch tensors, host or device).  ``u0``: initial U (n x k); ``v0``
     optional.  ``dtype``: "f32" or "f64" (the type of data/u0/v0).
+    ``static_workspace``: run on the library's static per-device workspace
+    (nmf_create_static: no device allocation; one such handle per device).
     """
 
     def __init__(self, n, m, indptr, indices, data, u0, *, t_u, t_v, v0=None, mode="column",
-                 dtype="f32", flags=0, device="cuda:0", stream=None):
+                 dtype="f32", flags=0, device="cuda:0", stream=None, static_workspace=False):
         import torch
 
         load_library()
@@ -423,10 +435,15 @@ class NMF:
         self.nnz = nnz
         with torch.cuda.device(self.device):
             self.ws_bytes = nmf_workspace_size(self.cfg, nnz)
-            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            self.h = nmf_create(self.cfg, indptr, indices, data, nnz, u0, v0, self.workspace,
-                                self.ws_bytes, self.stream.cuda_stream)
+            if static_workspace:
+                # the library's own per-device workspace: nothing is allocated
+                self.workspace = None
+                self.h = nmf_create_static(self.cfg, indptr, indices, data, nnz, u0, v0, self.stream.cuda_stream)
+            else:
+                self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+                self.h = nmf_create(self.cfg, indptr, indices, data, nnz, u0, v0, self.workspace,
+                                    self.ws_bytes, self.stream.cuda_stream)
 
     # -- iteration
     def step(self, iters: int = 1):

@@ -82,3 +82,17 @@ def test_create_rejects_null_arguments_without_a_device():
     assert st == B.NMF_ERR_INVALID_ARG
     assert h.value is None
     assert "NULL" in B.nmf_last_error(None)
+
+
+def test_create_static_rejects_a_problem_beyond_its_workspace():
+    """The static workspace holds NMF_STATIC_WORKSPACE_BYTES; a larger
+    problem is refused before any device work (no GPU needed)."""
+    lib = B.load_library()
+    cfg = _cfg(n=100000, m=200000, k=50, t_u=1000, t_v=2000)
+    assert B.nmf_workspace_size(cfg, 20_000_000) > 64 << 20
+    h = ctypes.c_void_p()
+    rp = (ctypes.c_int64 * 2)(0, 1)
+    st = lib.nmf_create_static(ctypes.byref(cfg), rp, rp, rp, 20_000_000, rp, None, None, ctypes.byref(h))
+    assert st == B.NMF_ERR_WORKSPACE
+    assert h.value is None
+    assert "static workspace holds 67108864" in B.nmf_last_error(None)
