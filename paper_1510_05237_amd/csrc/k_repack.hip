@@ -129,6 +129,12 @@ __device__ __forceinline__ void k_build_body(const RepackArgs& a, int blk, int n
     const int li = tid * kRowsPerThread + i;
     const bool ne = cnt[i] > 0;
     const int sl = ne ? ln : -1;
+    // row table word of rows [32 w, 32 w + 32) (kScanRows is a multiple of
+    // 64, so a word is one half of a wave): its nonempty bits, and the
+    // nonempty rows before it
+    const uint64_t bw = __ballot(ne);
+    if ((r & 31) == 0 && r < a.rows)
+      a.F.rowtab[r >> 5] = make_int2(static_cast<int>(static_cast<uint32_t>(bw >> (lane_id() & 32))), ln);
     s_rp[li] = lc;
     s_slot[li] = sl;
     if (r < a.rows) {

@@ -18,9 +18,11 @@
 //    (v_mfma_f32_16x16x4f32), computing the transposed product
 //    (U_H^T)(A_H^T): element i of tile tt then holds document r0 + m,
 //    topic 16 tt + 4 q + i for lane (m = lane % 16, q = lane / 16).
-//  * Every other nonzero is streamed, 64 per step, lanes = nonzeros: its
-//    term's row metadata gives the byte offset of U's row in the compact
-//    dense copy (empty rows are skipped).  The step's hits are queued in
+//  * Every other nonzero is streamed, 64 per step, lanes = nonzeros: U's
+//    row table, staged once per block in LDS (one word per 32 terms: which
+//    of them have a nonempty row of U, and how many nonempty rows precede
+//    them), gives the term's row in the compact dense copy of U without a
+//    global load (empty rows are skipped).  The step's hits are queued in
 //    LDS per document, each document's run padded to a multiple of four
 //    with zero-weight entries, and the queue is read in batches of four
 //    rows: lane (c16 = lane % 16, u = lane / 16) loads topics 4 c16 .. + 3
@@ -82,7 +84,11 @@ struct VhArgs {
   const int64_t* rowptr;   // [rows + 1]: documents' nonzeros of the non-hot terms
   const int32_t* col;      // term of each nonzero
   const float* val;
-  const int2* meta;        // U row metadata {compact dense row, entry count}; null for a dense input
+  const int2* rowtab;      // U row table (see Factor::rowtab); null for a dense input
+  int32_t tab_words;       // words of the row table
+  const int32_t* sdf;      // per U row: streamed nonzeros of its term (gathered-entry count)
+  const int32_t* urp;      // U's row pointers [n_u + 1] (entries per row)
+  int64_t n_u;             // rows of U
   const float* F;          // compact dense U rows (pitch ld), or the dense input (pitch k)
   int32_t ld;
   uint32_t F_bytes;        // bytes of F (every load of it is range-checked)
@@ -103,9 +109,10 @@ struct VhArgs {
 // byte offsets and weights.
 constexpr size_t kVhPerWave = kVhTile * kVhTopics * sizeof(float) + kVhQueue * (sizeof(uint32_t) + sizeof(float));
 
-__host__ __device__ inline size_t vh_block_lds(int hot_ld, int k, bool solve) {
+__host__ __device__ inline size_t vh_block_lds(int hot_ld, int k, bool solve, int tab_words) {
   size_t b = static_cast<size_t>(hot_ld) * kVhTopics * sizeof(float);
   if (solve) b += static_cast<size_t>(k) * k * sizeof(double);
+  b += static_cast<size_t>(tab_words) * sizeof(int2);
   return (b + 15) / 16 * 16;
 }
 
@@ -129,7 +136,7 @@ __device__ __forceinline__ void vh_flush(vh_f4& acc, float* tile, int d, bool li
 // The tile's non-hot nonzeros [rb[0], rb[16]) into the accumulator.
 template <bool DENSE_IN>
 __device__ __forceinline__ void vh_stream(const VhArgs& a, const int64_t* rb, float* tile, uint32_t* q_off,
-                                          float* q_a, uint32_t& gath) {
+                                          float* q_a, const int2* stab) {
   const int lane = lane_id();
   const int c16 = lane & 15, u = lane >> 4;
   const bool live = 4 * c16 < a.k;
@@ -157,10 +164,12 @@ __device__ __forceinline__ void vh_stream(const VhArgs& a, const int64_t* rb, fl
       hit = valid;
       off = static_cast<uint32_t>(j) * ldb;
     } else if (valid) {
-      const int2 m = a.meta[j];
-      hit = m.y > 0;
-      off = static_cast<uint32_t>(m.x) * ldb;
-      gath += static_cast<uint32_t>(m.y);
+      // the term's word of the row table: is its U row nonempty, and which
+      // compact row is it
+      const int2 w = stab[j >> 5];
+      const uint32_t bit = 1u << (j & 31);
+      hit = (static_cast<uint32_t>(w.x) & bit) != 0u;
+      off = static_cast<uint32_t>(w.y + __popc(static_cast<uint32_t>(w.x) & (bit - 1u))) * ldb;
     }
     const int64_t left = p_end - base;
     const int last = left < 64 ? static_cast<int>(left) - 1 : 63;
@@ -214,9 +223,12 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   const int k = a.k;
   const int H = a.n_hot > 0 ? a.hot_ld : 0;
   const bool solve = a.W != nullptr;
+  const int tw = DENSE_IN ? 0 : a.tab_words;
   float* ub = reinterpret_cast<float*>(smem);  // [H / 16][4][64][4]
   double* sW = reinterpret_cast<double*>(smem + static_cast<size_t>(H) * kVhTopics * sizeof(float));
-  unsigned char* waves0 = smem + vh_block_lds(H, k, solve);
+  int2* stab = reinterpret_cast<int2*>(reinterpret_cast<unsigned char*>(sW) +
+                                       (solve ? static_cast<size_t>(k) * k * sizeof(double) : 0));
+  unsigned char* waves0 = smem + vh_block_lds(H, k, solve, tw);
   // stage U's hot rows (zeros for empty rows and topics past k) and W
   if (H > 0) {
     const __amdgpu_buffer_rsrc_t fr = vh_rsrc(a.F, a.F_bytes);
@@ -234,6 +246,14 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   }
   if (solve)
     for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
+  for (int i = threadIdx.x; i < tw; i += blockDim.x) stab[i] = a.rowtab[i];
+  // gathered-entry count (the streamed nonzeros times the entries of their
+  // terms' rows of U), this block's share of the terms
+  uint32_t gath = 0;
+  if (!DENSE_IN && a.gathered != nullptr)
+    for (int64_t r = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x; r < a.n_u;
+         r += static_cast<int64_t>(nblk) * blockDim.x)
+      gath += static_cast<uint32_t>(a.sdf[r]) * static_cast<uint32_t>(a.urp[r + 1] - a.urp[r]);
   __syncthreads();
 
   const int lane = lane_id();
@@ -247,7 +267,6 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   const int64_t tiles = (a.rows + kVhTile - 1) / kVhTile;
   constexpr int HG = kMaxHot / 16;
   const __amdgpu_buffer_rsrc_t hr = vh_rsrc(a.hot, static_cast<uint32_t>(H > 0 ? a.rows * H * 4 : 0));
-  uint32_t gath = 0;  // this lane's gathered U entries (at most k per nonzero it loads)
   for (int64_t t = static_cast<int64_t>(blk) * bw + wv; t < tiles; t += nw) {
     const int64_t r0 = kVhTile * t;
     const int nrows = static_cast<int>(a.rows - r0 < kVhTile ? a.rows - r0 : kVhTile);
@@ -260,7 +279,7 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
 #pragma unroll
     for (int i = 0; i <= kVhTile; ++i) rb[i] = a.rowptr[r0 + (i < nrows ? i : nrows)];
     __builtin_amdgcn_wave_barrier();
-    vh_stream<DENSE_IN>(a, rb, tile, q_off, q_a, gath);
+    vh_stream<DENSE_IN>(a, rb, tile, q_off, q_a, stab);
     __builtin_amdgcn_wave_barrier();
     vh_f4 arow4[HG];
 #pragma unroll
@@ -369,7 +388,8 @@ __global__ __launch_bounds__(64 * kVhWavesMax) void k_vhalf_b(const VhArgs* as, 
 
 template <int NT, bool DENSE_IN>
 hipError_t vh_launch(nmf_handle* h, const VhArgs& a, int waves_max) {
-  const size_t blk_lds = vh_block_lds(a.n_hot > 0 ? a.hot_ld : 0, a.k, a.W != nullptr);
+  const size_t blk_lds = vh_block_lds(a.n_hot > 0 ? a.hot_ld : 0, a.k, a.W != nullptr,
+                                      a.rowtab != nullptr ? a.tab_words : 0);
   int waves = std::min(std::max(waves_max, 1), kVhWavesMax);
   while (waves > 1 && blk_lds + waves * kVhPerWave > kVhLds) waves /= 2;
   const size_t lds = blk_lds + waves * kVhPerWave;
@@ -406,7 +426,11 @@ hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* den
   a.rowptr = p.rowptr;
   a.col = p.col;
   a.val = static_cast<const float*>(p.val);
-  a.meta = dense_in ? nullptr : F.meta;
+  a.rowtab = dense_in ? nullptr : F.rowtab;
+  a.tab_words = dense_in ? 0 : static_cast<int32_t>((F.rows + 31) / 32);
+  a.sdf = p.sdf;
+  a.urp = F.row_ptr;
+  a.n_u = F.rows;
   a.F = dense_in ? dense_in : static_cast<const float*>(F.dense);
   a.ld = dense_in ? h->k : F.ld;
   a.F_bytes = static_cast<uint32_t>(dense_in ? h->n * h->k * 4 : F.rows * F.ld * 4);

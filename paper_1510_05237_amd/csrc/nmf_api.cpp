@@ -150,9 +150,11 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
   h->planAt.rowptr = cv.take<int64_t>(m + 1);
   h->planAt.col = cv.take<int32_t>(nnz);
   h->planAt.val = cv.take<char>(nnz * elt);
-  // room for the V half's hot block when one can exist (float32, k <= 64,
-  // the flag not set, its byte offsets within 32 bits): see do_create
-  if (c.dtype == NMF_F32 && k <= 64 && !(c.flags & NMF_FLAG_NO_HOT) && (m + 16) * kMaxHot * 4 < (int64_t{1} << 32)) {
+  // per term: its nonzeros in the V-half stream (the gathered-entry count)
+  h->planAt.sdf = cv.take<int32_t>(n);
+  // room for the V half's hot block when one can exist (the fused V-half
+  // kernel serves the problem and the flag is not set): see do_create
+  if (vhalf_fits(elt, n, m, k) && !(c.flags & NMF_FLAG_NO_HOT)) {
     const int hot_max = static_cast<int>(std::min<int64_t>(kMaxHot, (n + 15) / 16 * 16));
     h->planAt.hot_col = cv.take<int32_t>(kMaxHot);
     h->planAt.hot = cv.take<char>(m * hot_max * elt);
@@ -178,6 +180,7 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
     f.counts = cv.take<int32_t>(4);
     f.meta = cv.take<int2>(rows);
     f.packed = cv.take<char>(rows * k * 2 * elt);
+    f.rowtab = cv.take<int2>((rows + 31) / 32);
   };
   factor(h->U[0], n);
   factor(h->U[1], n);
@@ -480,8 +483,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   // most nonzeros first (ties: lower row), at most kMaxHot; their entries
   // leave the V-half stream for a dense docs x hot block
   std::vector<int32_t> hot;
-  if (sizeof(T) == 4 && h->k <= 64 && !(h->cfg.flags & NMF_FLAG_NO_HOT) &&
-      (m + 16) * kMaxHot * 4 < (int64_t{1} << 32)) {
+  if (vhalf_fits(sizeof(T), n, m, h->k) && !(h->cfg.flags & NMF_FLAG_NO_HOT)) {
     const int64_t need = std::max<int64_t>(kHotMinNnz, static_cast<int64_t>(std::ceil(kHotDensity * m)));
     for (int64_t i = 0; i < n; ++i)
       if (rp[i + 1] - rp[i] >= need) hot.push_back(static_cast<int32_t>(i));
@@ -551,6 +553,13 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
     return fail(h, NMF_ERR_WORKSPACE, "internal: no room for the hot block");
   h->planAt.n_hot = n_hot;
   h->planAt.hot_ld = hot_ld;
+  {
+    // each term's nonzeros in the V-half stream (hot terms: none)
+    std::vector<int32_t> sdf(n);
+    for (int64_t i = 0; i < n; ++i)
+      sdf[i] = (n_hot && hot_of[i] >= 0) ? 0 : static_cast<int32_t>(rp[i + 1] - rp[i]);
+    HIPCHK(h, hipMemcpy(h->planAt.sdf, sdf.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   if (n_hot) {
     HIPCHK(h, hipMemcpy(h->planAt.hot_col, hot.data(), n_hot * sizeof(int32_t), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->planAt.hot, hot_block.data(), hot_block.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -773,7 +782,7 @@ nmf_status create_impl(const nmf_config* cfg, const int64_t* a_rowptr, const int
   // float32 with k <= 64 (32-bit byte offsets into V_pre): the fused V-half
   // kernel, whose gathers read every nonempty row of U from its compact
   // dense copy
-  h->use_vhalf = h->elt == 4 && h->k <= 64 && (h->m + 16) * h->k * 4 < (int64_t{1} << 32);
+  h->use_vhalf = vhalf_fits(h->elt, h->n, h->m, h->k);
   if (h->use_vhalf) h->waves[0] = 16;
   carve(h, h->ws, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
   s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)

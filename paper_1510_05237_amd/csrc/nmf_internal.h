@@ -71,7 +71,20 @@ struct Plan {
   int32_t hot_ld = 0;
   int32_t* hot_col = nullptr;  // [kMaxHot]: factor row of hot column h
   void* hot = nullptr;         // [rows][hot_ld] T
+  // Per row of the gathered factor: how many of this plan's streamed
+  // nonzeros lie in its column (the hot ones excluded); the gathered-entry
+  // count of a product is sum over rows of this times the row's entries
+  int32_t* sdf = nullptr;      // [rows of the gathered factor]
 };
+
+// The fused V-half kernel serves float32 factors with k <= 64 whose byte
+// offsets into V_pre and the hot block fit 32 bits and whose U row table
+// (8 bytes per 32 terms) fits its LDS share; the hot block exists only then.
+constexpr int64_t kVhTabWords = 8192;  // at most 262144 terms
+inline bool vhalf_fits(size_t elt, int64_t n, int64_t m, int k) {
+  return elt == 4 && k <= 64 && (m + 16) * k * 4 < (int64_t{1} << 32) &&
+         (m + 16) * kMaxHot * 4 < (int64_t{1} << 32) && (n + 31) / 32 <= kVhTabWords;
+}
 
 // A factor as stored (row-compressed sparse) plus the gather cache the SpMM
 // reads: every nonempty row expanded to a dense row (64-byte aligned rows, so
@@ -91,6 +104,10 @@ struct Factor {
   // per entry {value, topic}
   int2* meta = nullptr;        // [rows]
   void* packed = nullptr;      // [rows * k] FactorEnt<T>
+  // Row table: word w = {bit i set when row 32 w + i is nonempty, number of
+  // nonempty rows before row 32 w}, so a row's compact index is found from
+  // one word (the fused V-half kernel keeps U's table in LDS)
+  int2* rowtab = nullptr;      // [(rows + 31) / 32]
 };
 
 // One stored factor entry as the SpMM gathers it (8 bytes for float).
