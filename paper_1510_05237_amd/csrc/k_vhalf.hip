@@ -18,23 +18,20 @@
 //    (v_mfma_f32_16x16x4f32), computing the transposed product
 //    (U_H^T)(A_H^T): element i of tile tt then holds document r0 + m,
 //    topic 16 tt + 4 q + i for lane (m = lane % 16, q = lane / 16).
-//  * Every other nonzero is streamed, 64 per step, lanes = nonzeros: U's
-//    row table, staged once per block in LDS (one word per 32 terms: which
-//    of them have a nonempty row of U, and how many nonempty rows precede
-//    them), gives the term's row in the compact dense copy of U without a
-//    global load (empty rows are skipped).  The step's hits are queued in
-//    LDS per document, each document's run padded to a multiple of four
-//    with zero-weight entries, and the queue is read in batches of four
-//    rows: lane (c16 = lane % 16, u = lane / 16) loads topics 4 c16 .. + 3
-//    of the batch's row u as one float4 and accumulates them, so one vector
-//    instruction handles four gathered rows.  When the document changes
-//    (wave-uniform: a batch never spans two documents) the four lane groups'
-//    sums are combined by two xor-shuffles in a fixed order and lane group 0
-//    adds them to the document's row of the wave's LDS accumulator.  No
-//    floating-point atomics: every sum is formed in a fixed order, so two
-//    runs are bitwise identical.
-//  * Epilogue: each lane adds the accumulator's sums of its (document,
-//    topic) slots to the hot product it holds, then the float64 solve runs
+//  * Every other nonzero is streamed straight into the registers that the
+//    hot product accumulates into: lane (m, q) owns document r0 + m and the
+//    topics 16 tt + 4 q + i (the fp32 MFMA result layout).  Per step each
+//    document's next 16 nonzeros are read, four per lane, as one 16-byte
+//    load of terms and one of values; U's row table, staged once per block
+//    in LDS (one word per 32 terms: which of them have a nonempty row of U,
+//    and how many nonempty rows precede them), gives each term's row in the
+//    compact dense copy of U without a global load.  The document's four
+//    lanes then take its 16 nonzeros in order (each broadcast from the lane
+//    that read it): a nonempty row is read as one 16-byte load per topic
+//    group and multiply-added into the lane's sums; empty rows are skipped.
+//    Every sum is formed in nonzero order in one lane: no atomics, no
+//    cross-lane reduction, and two runs are bitwise identical.
+//  * Epilogue: the float64 solve runs
 //    on the matrix cores (v_mfma_f64_16x16x4f64) with the raw sums as the A
 //    operand straight from registers and W from LDS (the contraction order
 //    of raw W is free); the result holds document r0 + q + 4 i, topic
@@ -51,11 +48,13 @@ namespace {
 
 typedef float vh_f4 __attribute__((ext_vector_type(4)));
 typedef double vh_d4 __attribute__((ext_vector_type(4)));
+typedef int vh_i4 __attribute__((ext_vector_type(4)));
 
 constexpr int kVhTile = 16;                       // documents per wave tile
 constexpr int kVhTopics = 64;                     // topic slots (k <= 64)
-constexpr int kVhQueue = 64 + 3 * kVhTile;        // a step's hits, every document run padded to a multiple of 4
 constexpr int kVhWavesMax = 16;
+constexpr int kVhGroup = 2;                       // streamed rows a lane reads at once
+constexpr int kVhHotChunk = 8;                    // 16-column groups of the hot block read at once
 constexpr size_t kVhLds = 160 * 1024;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t vh_rsrc(const void* p, uint32_t bytes) {
@@ -65,6 +64,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t vh_rsrc(const void* p, uint32_
 }
 __device__ __forceinline__ vh_f4 vh_load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(vh_f4, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0));
+}
+__device__ __forceinline__ vh_i4 vh_load4i(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(vh_i4, __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(off), 0, 0));
 }
 __device__ __forceinline__ float vh_load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
@@ -84,6 +86,7 @@ struct VhArgs {
   const int64_t* rowptr;   // [rows + 1]: documents' nonzeros of the non-hot terms
   const int32_t* col;      // term of each nonzero
   const float* val;
+  uint32_t stream_bytes;   // bytes of col (and of val), padding and spare entries included
   const int2* rowtab;      // U row table (see Factor::rowtab); null for a dense input
   int32_t tab_words;       // words of the row table
   const int32_t* sdf;      // per U row: streamed nonzeros of its term (gathered-entry count)
@@ -94,6 +97,8 @@ struct VhArgs {
   uint32_t F_bytes;        // bytes of F (every load of it is range-checked)
   const float* hot;        // [rows][hot_ld]: hot block (null when n_hot == 0)
   const int32_t* hot_col;  // [n_hot]: U row of hot column h
+  const int32_t* warm_col; // [n_warm]: U row of warm term w (stream term -2 - w)
+  int32_t n_warm;
   int32_t hot_ld;          // multiple of 16, <= kMaxHot
   int32_t n_hot;
   const int32_t* slot;     // U row -> compact dense row (-1: empty), null for a dense input
@@ -105,120 +110,118 @@ struct VhArgs {
   unsigned long long* gathered;  // [kGathSlots]: U entries of the streamed rows (null: not counted)
 };
 
-// Per wave: the accumulator (16 documents x 64 topics), then the queue's
-// byte offsets and weights.
-constexpr size_t kVhPerWave = kVhTile * kVhTopics * sizeof(float) + kVhQueue * (sizeof(uint32_t) + sizeof(float));
-
-__host__ __device__ inline size_t vh_block_lds(int hot_ld, int k, bool solve, int tab_words) {
+// LDS of a block: U's hot rows (MFMA operand layout), W, U's row table,
+// then U's warm rows (64 floats each).
+__host__ __device__ inline size_t vh_block_lds(int hot_ld, int k, bool solve, int tab_words, int n_warm) {
   size_t b = static_cast<size_t>(hot_ld) * kVhTopics * sizeof(float);
   if (solve) b += static_cast<size_t>(k) * k * sizeof(double);
   b += static_cast<size_t>(tab_words) * sizeof(int2);
-  return (b + 15) / 16 * 16;
+  b = (b + 15) / 16 * 16;
+  return b + static_cast<size_t>(n_warm) * kVhTopics * sizeof(float);
+}
+__host__ __device__ inline size_t vh_warm_offset(int hot_ld, int k, bool solve, int tab_words) {
+  return vh_block_lds(hot_ld, k, solve, tab_words, 0);
 }
 
-// Adds the four lane groups' sums (fixed order) of document d into its row
-// of the accumulator and clears them.  Wave-uniform call.
-__device__ __forceinline__ void vh_flush(vh_f4& acc, float* tile, int d, bool live) {
+// The tile's streamed nonzeros into acc: lane (m, q) adds, for every nonzero
+// (term j, value a) of document r0 + m, a times topics 16 tt + 4 q .. + 3 of
+// U's row j to acc[tt], in nonzero order.  [rb, re): the document's
+// nonzeros (empty past the tile's last document).
+template <int NT, bool DENSE_IN>
+__device__ __forceinline__ void vh_stream(const VhArgs& a, int64_t rb, int64_t re, const int2* stab,
+                                          const float* warm, vh_f4* acc) {
   const int lane = lane_id();
-  vh_f4 s;
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    float v = acc[x] + __shfl_xor(acc[x], 16, 64);
-    s[x] = v + __shfl_xor(v, 32, 64);
-  }
-  if (lane < 16 && live) {
-    vh_f4* t = reinterpret_cast<vh_f4*>(tile + d * kVhTopics + 4 * lane);
-    *t = *t + s;
-  }
-  acc = vh_f4{0.f, 0.f, 0.f, 0.f};
-}
-
-// The tile's non-hot nonzeros [rb[0], rb[16]) into the accumulator.
-template <bool DENSE_IN>
-__device__ __forceinline__ void vh_stream(const VhArgs& a, const int64_t* rb, float* tile, uint32_t* q_off,
-                                          float* q_a, const int2* stab) {
-  const int lane = lane_id();
-  const int c16 = lane & 15, u = lane >> 4;
-  const bool live = 4 * c16 < a.k;
+  const int m = lane & 15, q = lane >> 4;
   const __amdgpu_buffer_rsrc_t Fr = vh_rsrc(a.F, a.F_bytes);
+  // every document's run starts at a multiple of four entries (padded with
+  // term -1) and the arrays carry four spare entries past their end, so the
+  // 16-byte reads are aligned and a read at a document's end stays inside
+  const __amdgpu_buffer_rsrc_t cr = vh_rsrc(a.col, a.stream_bytes);
+  const __amdgpu_buffer_rsrc_t vr = vh_rsrc(a.val, a.stream_bytes);
   const uint32_t ldb = static_cast<uint32_t>(a.ld) * 4u;
-  const uint32_t lo = 16u * static_cast<uint32_t>(c16);
-  vh_f4 acc = {0.f, 0.f, 0.f, 0.f};
-  int cur_d = 0;
-  const int64_t p_end = rb[kVhTile];
-  for (int64_t base = rb[0]; base < p_end; base += 64) {
-    const int64_t p = base + lane;
-    const bool valid = p < p_end;
-    int32_t j = 0;
-    float av = 0.f;
-    if (valid) {
-      j = __builtin_nontemporal_load(&a.col[p]);
-      av = __builtin_nontemporal_load(&a.val[p]);
-    }
-    int d = 0;
+  const uint32_t lo = 16u * static_cast<uint32_t>(q);
+  bool live[NT];
 #pragma unroll
-    for (int i = 1; i < kVhTile; ++i) d += p >= rb[i] ? 1 : 0;
-    bool hit = false;
-    uint32_t off = 0;
+  for (int tt = 0; tt < NT; ++tt) live[tt] = 16 * tt + 4 * q < a.k;
+  // steps of 16 nonzeros per document, as many as the tile's longest needs
+  int ns = static_cast<int>((re - rb + 15) >> 4);
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) ns = max(ns, __shfl_xor(ns, o, 64));
+  ns = vh_uniform(ns);
+  // the next step's terms and values are read while this step's rows are
+  // gathered
+  int64_t p = rb + 4 * q;
+  vh_i4 cv = vh_load4i(cr, static_cast<uint32_t>(p) * 4u);
+  vh_f4 av = vh_load4(vr, static_cast<uint32_t>(p) * 4u);
+  for (int s = 0; s < ns; ++s, p += 16) {
+    const vh_i4 cur = cv;
+    const vh_f4 cav = av;
+    if (s + 1 < ns) {
+      cv = vh_load4i(cr, static_cast<uint32_t>(p + 16) * 4u);
+      av = vh_load4(vr, static_cast<uint32_t>(p + 16) * 4u);
+    }
+    // sl: compact row of U (>= 0), warm row w (-2 - w) or nothing (-1)
+    int sl[4];
     if (DENSE_IN) {
-      hit = valid;
-      off = static_cast<uint32_t>(j) * ldb;
-    } else if (valid) {
-      // the term's word of the row table: is its U row nonempty, and which
-      // compact row is it
-      const int2 w = stab[j >> 5];
-      const uint32_t bit = 1u << (j & 31);
-      hit = (static_cast<uint32_t>(w.x) & bit) != 0u;
-      off = static_cast<uint32_t>(w.y + __popc(static_cast<uint32_t>(w.x) & (bit - 1u))) * ldb;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sl[e] = (p + e < re) ? cur[e] : -1;
+    } else {
+      // each term's word of the row table (all four read at once): is its U
+      // row nonempty, and which compact row is it
+      int2 w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[e] = stab[cur[e] >= 0 ? (cur[e] >> 5) : 0];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t bit = 1u << (cur[e] & 31);
+        const bool hit = p + e < re && cur[e] >= 0 && (static_cast<uint32_t>(w[e].x) & bit) != 0u;
+        sl[e] = hit ? w[e].y + __popc(static_cast<uint32_t>(w[e].x) & (bit - 1u)) : (p + e < re && cur[e] < -1 ? cur[e] : -1);
+      }
     }
-    const int64_t left = p_end - base;
-    const int last = left < 64 ? static_cast<int>(left) - 1 : 63;
-    const int d_lo = vh_uniform(d);
-    const int d_hi = vh_uniform(__shfl(d, last, 64));
-    for (int dd = d_lo; dd <= d_hi; ++dd) {
-      const bool mine = hit && d == dd;
-      const uint64_t mb = __ballot(mine);
-      if (mb == 0) continue;
-      if (dd != cur_d) {
-        vh_flush(acc, tile, cur_d, live);
-        cur_d = dd;
-      }
-      const int cnt = __popcll(mb);
-      const int cnt4 = (cnt + 3) & ~3;
-      if (mine) {
-        const int pos = lane_rank(mb);
-        q_off[pos] = off;
-        q_a[pos] = av;
-      }
-      if (lane < cnt4 - cnt) {  // zero-weight padding (row 0 of F, or zeros past its end)
-        q_off[cnt + lane] = 0u;
-        q_a[cnt + lane] = 0.f;
-      }
-      __builtin_amdgcn_wave_barrier();
-      // batches of four rows, up to four batches' loads in flight
-      for (int h = 0; h < cnt4; h += 16) {
-        vh_f4 f[4];
-        float w[4];
+    // the document's 16 nonzeros in order, kVhGroup rows in flight per lane
+#pragma unroll 1
+    for (int jj = 0; jj < 16; jj += kVhGroup) {
+      int sj[kVhGroup];
+      float aj[kVhGroup];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int e = h + 4 * b + u;
-          const bool in = h + 4 * b < cnt4;
-          const uint32_t o = in ? q_off[e] : 0u;
-          w[b] = in ? q_a[e] : 0.f;
-          f[b] = (in && live) ? vh_row4<DENSE_IN>(Fr, o + lo) : vh_f4{0.f, 0.f, 0.f, 0.f};
+      for (int u = 0; u < kVhGroup; ++u) {
+        const int e = (jj + u) & 3;  // element e of the lane that read nonzero jj + u
+        const int src = 16 * ((jj + u) >> 2) + m;
+        const int se = e == 0 ? sl[0] : e == 1 ? sl[1] : e == 2 ? sl[2] : sl[3];
+        const float ae = e == 0 ? cav[0] : e == 1 ? cav[1] : e == 2 ? cav[2] : cav[3];
+        sj[u] = __shfl(se, src, 64);
+        aj[u] = __shfl(ae, src, 64);
+      }
+      vh_f4 f[kVhGroup][NT];
+#pragma unroll
+      for (int u = 0; u < kVhGroup; ++u) {
+        if (sj[u] >= 0) {
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt)
+            f[u][tt] = live[tt] ? vh_row4<DENSE_IN>(Fr, static_cast<uint32_t>(sj[u]) * ldb + lo + 64u * tt)
+                                : vh_f4{0.f, 0.f, 0.f, 0.f};
+        } else if (sj[u] < -1) {
+          const float* wr = warm + (-2 - sj[u]) * kVhTopics + 4 * q;
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) f[u][tt] = *reinterpret_cast<const vh_f4*>(wr + 16 * tt);
+        } else {
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) f[u][tt] = vh_f4{0.f, 0.f, 0.f, 0.f};
         }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc += w[b] * f[b];
       }
-      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < kVhGroup; ++u)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt)
+          if (sj[u] != -1) acc[tt] += aj[u] * f[u][tt];
     }
   }
-  vh_flush(acc, tile, cur_d, live);
 }
 
 template <int NT, bool DENSE_IN>
 __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int bw = blockDim.x >> 6;
   if (*a.status != 0) return;
   const int k = a.k;
   const int H = a.n_hot > 0 ? a.hot_ld : 0;
@@ -228,7 +231,7 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   double* sW = reinterpret_cast<double*>(smem + static_cast<size_t>(H) * kVhTopics * sizeof(float));
   int2* stab = reinterpret_cast<int2*>(reinterpret_cast<unsigned char*>(sW) +
                                        (solve ? static_cast<size_t>(k) * k * sizeof(double) : 0));
-  unsigned char* waves0 = smem + vh_block_lds(H, k, solve, tw);
+  float* warm = reinterpret_cast<float*>(smem + vh_warm_offset(H, k, solve, tw));
   // stage U's hot rows (zeros for empty rows and topics past k) and W
   if (H > 0) {
     const __amdgpu_buffer_rsrc_t fr = vh_rsrc(a.F, a.F_bytes);
@@ -247,6 +250,18 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   if (solve)
     for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
   for (int i = threadIdx.x; i < tw; i += blockDim.x) stab[i] = a.rowtab[i];
+  // stage U's warm rows (zeros for empty rows and topics past k)
+  if (a.n_warm > 0) {
+    const __amdgpu_buffer_rsrc_t fr = vh_rsrc(a.F, a.F_bytes);
+    for (int i = threadIdx.x; i < a.n_warm * kVhTopics; i += blockDim.x) {
+      const int w = i / kVhTopics, c = i - w * kVhTopics;
+      const int r = a.warm_col[w];
+      const int s = a.slot != nullptr ? a.slot[r] : r;
+      const int64_t off = s >= 0 ? static_cast<int64_t>(s) * a.ld * 4 : 0;
+      const float v = vh_load1(fr, static_cast<uint32_t>(off) + 4u * static_cast<uint32_t>(c));
+      warm[i] = (s >= 0 && c < k) ? v : 0.f;
+    }
+  }
   // gathered-entry count (the streamed nonzeros times the entries of their
   // terms' rows of U), this block's share of the terms
   uint32_t gath = 0;
@@ -259,62 +274,56 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
   const int m = lane & 15, q = lane >> 4;
-  float* tile = reinterpret_cast<float*>(waves0 + wv * kVhPerWave);
-  uint32_t* q_off = reinterpret_cast<uint32_t*>(tile + kVhTile * kVhTopics);
-  float* q_a = reinterpret_cast<float*>(q_off + kVhQueue);
-  const int bw = blockDim.x >> 6;
-  const int64_t nw = static_cast<int64_t>(nblk) * bw;
   const int64_t tiles = (a.rows + kVhTile - 1) / kVhTile;
-  constexpr int HG = kMaxHot / 16;
   const __amdgpu_buffer_rsrc_t hr = vh_rsrc(a.hot, static_cast<uint32_t>(H > 0 ? a.rows * H * 4 : 0));
+  // wave w of the launch takes tiles w, w + W, w + 2 W, ...: the waves
+  // running at once work on neighbouring documents
+  const int64_t nw = static_cast<int64_t>(nblk) * bw;
   for (int64_t t = static_cast<int64_t>(blk) * bw + wv; t < tiles; t += nw) {
     const int64_t r0 = kVhTile * t;
     const int nrows = static_cast<int>(a.rows - r0 < kVhTile ? a.rows - r0 : kVhTile);
-    // the hot columns of the 16 documents stay in flight during the stream
-    // (rows past the end read as zero)
+    // the hot columns of the 16 documents (rows past the end read as zero)
     const uint32_t abase = static_cast<uint32_t>((r0 + m) * H + 4 * q) * 4u;
-#pragma unroll
-    for (int i = 0; i < kVhTile * kVhTopics / 64; ++i) tile[lane + 64 * i] = 0.f;
-    int64_t rb[kVhTile + 1];
-#pragma unroll
-    for (int i = 0; i <= kVhTile; ++i) rb[i] = a.rowptr[r0 + (i < nrows ? i : nrows)];
-    __builtin_amdgcn_wave_barrier();
-    vh_stream<DENSE_IN>(a, rb, tile, q_off, q_a, stab);
-    __builtin_amdgcn_wave_barrier();
-    vh_f4 arow4[HG];
-#pragma unroll
-    for (int g = 0; g < HG; ++g)
-      arow4[g] = 16 * g < H ? vh_load4(hr, abase + 64u * g) : vh_f4{0.f, 0.f, 0.f, 0.f};
-    // hot product: tile tt = (U_H^T)(topics 16 tt ..) x (A_H^T)(.., docs)
+    const int64_t rb = a.rowptr[r0 + (m < nrows ? m : nrows)];
+    const int64_t re = a.rowptr[r0 + (m + 1 < nrows ? m + 1 : nrows)];
+    // streamed part first, then the hot product adds on the same sums
     vh_f4 acc[4];
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) acc[tt] = vh_f4{0.f, 0.f, 0.f, 0.f};
+    vh_stream<NT, DENSE_IN>(a, rb, re, stab, warm, acc);
+    // hot product: tile tt = (U_H^T)(topics 16 tt ..) x (A_H^T)(.., docs),
+    // the hot columns read eight 16-column groups at a time
+    for (int g0 = 0; g0 < H / 16; g0 += kVhHotChunk) {
+      vh_f4 arow4[kVhHotChunk];
 #pragma unroll
-    for (int g = 0; g < HG; ++g) {
-      if (16 * g >= H) break;
-      const vh_f4 av = arow4[g];
-      vh_f4 bv[4];
+      for (int g = 0; g < kVhHotChunk; ++g)
+        arow4[g] = 16 * (g0 + g) < H ? vh_load4(hr, abase + 64u * (g0 + g)) : vh_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt)
-        bv[tt] = *reinterpret_cast<const vh_f4*>(&ub[((g * 4 + q) * kVhTopics + 16 * tt + m) * 4]);
+      for (int gg = 0; gg < kVhHotChunk; ++gg) {
+        const int g = g0 + gg;
+        if (16 * g >= H) break;
+        const vh_f4 av = arow4[gg];
+        vh_f4 bv[4];
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].x, av.x, acc[tt], 0, 0, 0);
+        for (int tt = 0; tt < NT; ++tt)
+          bv[tt] = *reinterpret_cast<const vh_f4*>(&ub[((g * 4 + q) * kVhTopics + 16 * tt + m) * 4]);
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].y, av.y, acc[tt], 0, 0, 0);
+        for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].x, av.x, acc[tt], 0, 0, 0);
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].z, av.z, acc[tt], 0, 0, 0);
+        for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].y, av.y, acc[tt], 0, 0, 0);
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].w, av.w, acc[tt], 0, 0, 0);
+        for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].z, av.z, acc[tt], 0, 0, 0);
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[tt].w, av.w, acc[tt], 0, 0, 0);
+      }
     }
-    // raw sums of document r0 + m, topic 16 tt + 4 q + i: hot product plus
-    // the streamed part from the accumulator
+    // raw sums of document r0 + m, topic 16 tt + 4 q + i (topics past k,
+    // which a dense input's next row may have filled, are zeroed)
     float raw[4][4];
 #pragma unroll
-    for (int tt = 0; tt < NT; ++tt) {
-      const vh_f4 cold = *reinterpret_cast<const vh_f4*>(tile + m * kVhTopics + 16 * tt + 4 * q);
+    for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) raw[tt][i] = 16 * tt + 4 * q + i < k ? acc[tt][i] + cold[i] : 0.f;
-    }
+      for (int i = 0; i < 4; ++i) raw[tt][i] = 16 * tt + 4 * q + i < k ? acc[tt][i] : 0.f;
     bool bad = false;
     const int64_t ra = r0 + m;
     if (!solve) {
@@ -389,10 +398,9 @@ __global__ __launch_bounds__(64 * kVhWavesMax) void k_vhalf_b(const VhArgs* as, 
 template <int NT, bool DENSE_IN>
 hipError_t vh_launch(nmf_handle* h, const VhArgs& a, int waves_max) {
   const size_t blk_lds = vh_block_lds(a.n_hot > 0 ? a.hot_ld : 0, a.k, a.W != nullptr,
-                                      a.rowtab != nullptr ? a.tab_words : 0);
+                                      a.rowtab != nullptr ? a.tab_words : 0, a.n_warm);
   int waves = std::min(std::max(waves_max, 1), kVhWavesMax);
-  while (waves > 1 && blk_lds + waves * kVhPerWave > kVhLds) waves /= 2;
-  const size_t lds = blk_lds + waves * kVhPerWave;
+  const size_t lds = blk_lds;
   if (lds > kVhLds) return hipErrorInvalidValue;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_vhalf<NT, DENSE_IN>, 64 * waves, lds) != hipSuccess)
@@ -418,14 +426,15 @@ hipError_t vh_dispatch(nmf_handle* h, const VhArgs& a, int waves) {
 
 hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* dense_in, float* X, const double* W,
                  int waves) {
-  // byte offsets into the hot block, F and X are 32-bit
+  // byte offsets into the hot block, the stream, F and X are 32-bit
   if (h->k > kVhTopics || p.hot_ld > kMaxHot || (p.rows + kVhTile) * p.hot_ld * 4 >= (int64_t{1} << 32) ||
-      (p.rows + kVhTile) * h->k * 4 >= (int64_t{1} << 32))
+      (p.rows + kVhTile) * h->k * 4 >= (int64_t{1} << 32) || (p.nnz + 4) * 4 >= (int64_t{1} << 32))
     return hipErrorInvalidValue;
   VhArgs a{};
   a.rowptr = p.rowptr;
   a.col = p.col;
   a.val = static_cast<const float*>(p.val);
+  a.stream_bytes = static_cast<uint32_t>((p.nnz + 4) * 4);  // the padded stream and its spare entries
   a.rowtab = dense_in ? nullptr : F.rowtab;
   a.tab_words = dense_in ? 0 : static_cast<int32_t>((F.rows + 31) / 32);
   a.sdf = p.sdf;
@@ -436,6 +445,8 @@ hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* den
   a.F_bytes = static_cast<uint32_t>(dense_in ? h->n * h->k * 4 : F.rows * F.ld * 4);
   a.hot = static_cast<const float*>(p.hot);
   a.hot_col = p.hot_col;
+  a.warm_col = p.warm_col;
+  a.n_warm = p.n_warm;
   a.hot_ld = p.hot_ld;
   a.n_hot = p.n_hot;
   a.slot = dense_in ? nullptr : F.slot;

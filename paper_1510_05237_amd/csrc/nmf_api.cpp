@@ -148,13 +148,16 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
   h->planA.val = cv.take<char>(nnz * elt);
   h->planAt.rows = m;
   h->planAt.rowptr = cv.take<int64_t>(m + 1);
-  h->planAt.col = cv.take<int32_t>(nnz);
-  h->planAt.val = cv.take<char>(nnz * elt);
+  // (the fused V-half kernel's stream is padded: see vh_stream_cap)
+  const int64_t nnz_at = vhalf_fits(elt, n, m, k, nnz) ? vh_stream_cap(m, nnz) : nnz;
+  h->planAt.col = cv.take<int32_t>(nnz_at);
+  h->planAt.val = cv.take<char>(nnz_at * elt);
   // per term: its nonzeros in the V-half stream (the gathered-entry count)
   h->planAt.sdf = cv.take<int32_t>(n);
+  if (vhalf_fits(elt, n, m, k, nnz)) h->planAt.warm_col = cv.take<int32_t>(kMaxWarm);
   // room for the V half's hot block when one can exist (the fused V-half
   // kernel serves the problem and the flag is not set): see do_create
-  if (vhalf_fits(elt, n, m, k) && !(c.flags & NMF_FLAG_NO_HOT)) {
+  if (vhalf_fits(elt, n, m, k, nnz) && !(c.flags & NMF_FLAG_NO_HOT)) {
     const int hot_max = static_cast<int>(std::min<int64_t>(kMaxHot, (n + 15) / 16 * 16));
     h->planAt.hot_col = cv.take<int32_t>(kMaxHot);
     h->planAt.hot = cv.take<char>(m * hot_max * elt);
@@ -483,7 +486,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   // most nonzeros first (ties: lower row), at most kMaxHot; their entries
   // leave the V-half stream for a dense docs x hot block
   std::vector<int32_t> hot;
-  if (vhalf_fits(sizeof(T), n, m, h->k) && !(h->cfg.flags & NMF_FLAG_NO_HOT)) {
+  if (vhalf_fits(sizeof(T), n, m, h->k, nnz) && !(h->cfg.flags & NMF_FLAG_NO_HOT)) {
     const int64_t need = std::max<int64_t>(kHotMinNnz, static_cast<int64_t>(std::ceil(kHotDensity * m)));
     for (int64_t i = 0; i < n; ++i)
       if (rp[i + 1] - rp[i] >= need) hot.push_back(static_cast<int32_t>(i));
@@ -495,16 +498,38 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   const int hot_ld = (n_hot + 15) / 16 * 16;
   std::vector<int32_t> hot_of(n_hot ? n : 0, -1);
   for (int x = 0; x < n_hot; ++x) hot_of[hot[x]] = x;
+  // warm terms (fused V-half kernel): the most frequent of the rest, at
+  // least kHotMinNnz nonzeros each, most first (ties: lower row), at most
+  // kMaxWarm; their rows of U are read from LDS
+  std::vector<int32_t> warm;
+  if (h->use_vhalf) {
+    for (int64_t i = 0; i < n; ++i)
+      if ((!n_hot || hot_of[i] < 0) && rp[i + 1] - rp[i] >= kHotMinNnz) warm.push_back(static_cast<int32_t>(i));
+    std::stable_sort(warm.begin(), warm.end(),
+                     [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    // as many as the kernel's LDS holds beside its hot rows, W and U's row table
+    const int64_t base = (static_cast<int64_t>(hot_ld) * 64 * 4 + static_cast<int64_t>(h->k) * h->k * 8 +
+                          (n + 31) / 32 * 8 + 15) / 16 * 16;
+    const int64_t room = std::max<int64_t>(0, (int64_t{160} * 1024 - base) / (64 * 4));
+    if (static_cast<int64_t>(warm.size()) > std::min<int64_t>(kMaxWarm, room))
+      warm.resize(static_cast<size_t>(std::min<int64_t>(kMaxWarm, room)));
+  }
+  std::vector<int32_t> warm_of(warm.empty() ? 0 : n, -1);
+  for (size_t w = 0; w < warm.size(); ++w) warm_of[warm[w]] = static_cast<int32_t>(w);
   std::vector<T> hot_block(static_cast<size_t>(n_hot ? m : 0) * hot_ld, T(0));
-  // transpose of the rest (stable counting sort: rows ascending within each column)
+  // transpose of the rest (stable counting sort: rows ascending within each
+  // column); for the fused V-half kernel every document's run is padded to
+  // a multiple of four with term -1, value 0
   std::vector<int64_t> cp(m + 1, 0);
   for (int64_t i = 0; i < n; ++i)
     if (!n_hot || hot_of[i] < 0)
       for (int64_t p = rp[i]; p < rp[i + 1]; ++p) ++cp[col[p] + 1];
+  if (h->use_vhalf)
+    for (int64_t j = 0; j < m; ++j) cp[j + 1] = (cp[j + 1] + 3) & ~int64_t{3};
   for (int64_t j = 0; j < m; ++j) cp[j + 1] += cp[j];
   const int64_t nnz_t = cp[m];
-  std::vector<int32_t> crow(nnz_t);
-  std::vector<T> cval(nnz_t);
+  std::vector<int32_t> crow(nnz_t, -1);
+  std::vector<T> cval(nnz_t, T(0));
   {
     std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
     for (int64_t i = 0; i < n; ++i) {
@@ -515,7 +540,7 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
           continue;
         }
         const int64_t q = cur[col[p]]++;
-        crow[q] = static_cast<int32_t>(i);
+        crow[q] = (!warm.empty() && warm_of[i] >= 0) ? -2 - warm_of[i] : static_cast<int32_t>(i);
         cval[q] = val[p];
       }
     }
@@ -523,7 +548,8 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   // rows per light item = the epilogue row group of the SpMM instantiation
   const int group = spmm_row_group(h->k);
   HostPlan pa = build_plan(rp, n, group);
-  HostPlan pt = build_plan(cp.data(), m, group);
+  // (the fused V-half kernel needs no work items)
+  HostPlan pt = h->use_vhalf ? HostPlan{} : build_plan(cp.data(), m, group);
   const PlanSizes ba = plan_bounds(n, nnz), bt = plan_bounds(m, nnz);
   if (static_cast<int64_t>(pa.items.size()) > ba.items || static_cast<int64_t>(pt.items.size()) > bt.items ||
       pa.parts > ba.parts || pt.parts > bt.parts)
@@ -548,11 +574,16 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   HIPCHK(h, hipMemcpy(h->planA.col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.val, val, nnz * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz_t * sizeof(int32_t), hipMemcpyHostToDevice));
+  h->planA.nnz = nnz;
+  h->planAt.nnz = nnz_t;
   HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz_t * sizeof(T), hipMemcpyHostToDevice));
   if (n_hot && (h->planAt.hot == nullptr || h->planAt.hot_col == nullptr))
     return fail(h, NMF_ERR_WORKSPACE, "internal: no room for the hot block");
   h->planAt.n_hot = n_hot;
   h->planAt.hot_ld = hot_ld;
+  h->planAt.n_warm = static_cast<int32_t>(warm.size());
+  if (!warm.empty())
+    HIPCHK(h, hipMemcpy(h->planAt.warm_col, warm.data(), warm.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   {
     // each term's nonzeros in the V-half stream (hot terms: none)
     std::vector<int32_t> sdf(n);
@@ -782,7 +813,7 @@ nmf_status create_impl(const nmf_config* cfg, const int64_t* a_rowptr, const int
   // float32 with k <= 64 (32-bit byte offsets into V_pre): the fused V-half
   // kernel, whose gathers read every nonempty row of U from its compact
   // dense copy
-  h->use_vhalf = vhalf_fits(h->elt, h->n, h->m, h->k);
+  h->use_vhalf = vhalf_fits(h->elt, h->n, h->m, h->k, nnz);
   if (h->use_vhalf) h->waves[0] = 16;
   carve(h, h->ws, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
   s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)

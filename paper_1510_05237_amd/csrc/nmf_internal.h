@@ -15,6 +15,7 @@ namespace nmfk {
 
 constexpr int kMaxK = 128;       // topics supported (2 per lane at most)
 constexpr int kMaxHot = 128;     // most hot columns split off the V-half stream (float32)
+constexpr int kMaxWarm = 256;    // most warm terms, whose rows of U the V-half kernel keeps in LDS
 constexpr double kHotDensity = 0.0625;  // a hot column holds at least this share of the rows
 constexpr int64_t kHotMinNnz = 16;     // ... and at least this many nonzeros
 constexpr int kWave = 64;        // CDNA wavefront width
@@ -51,6 +52,7 @@ struct WorkItem {
 // SpMM plan for one orientation of A (CSR of A: U half; CSR of A^T: V half).
 struct Plan {
   int64_t rows = 0;
+  int64_t nnz = 0;            // entries in col/val (the fused V-half stream: padding included)
   int64_t* rowptr = nullptr;  // [rows + 1]
   int32_t* col = nullptr;     // [nnz]
   void* val = nullptr;        // [nnz] T
@@ -71,6 +73,11 @@ struct Plan {
   int32_t hot_ld = 0;
   int32_t* hot_col = nullptr;  // [kMaxHot]: factor row of hot column h
   void* hot = nullptr;         // [rows][hot_ld] T
+  // Warm columns (fused V-half stream only): the next most frequent terms
+  // after the hot ones stay in the stream, but their entries carry term
+  // -2 - w and the kernel reads factor row warm_col[w] from LDS
+  int32_t n_warm = 0;
+  int32_t* warm_col = nullptr;  // [kMaxWarm]
   // Per row of the gathered factor: how many of this plan's streamed
   // nonzeros lie in its column (the hot ones excluded); the gathered-entry
   // count of a product is sum over rows of this times the row's entries
@@ -78,11 +85,16 @@ struct Plan {
 };
 
 // The fused V-half kernel serves float32 factors with k <= 64 whose byte
-// offsets into V_pre and the hot block fit 32 bits and whose U row table
+// offsets into V_pre, the hot block and the stream fit 32 bits and whose U row table
 // (8 bytes per 32 terms) fits its LDS share; the hot block exists only then.
 constexpr int64_t kVhTabWords = 8192;  // at most 262144 terms
-inline bool vhalf_fits(size_t elt, int64_t n, int64_t m, int k) {
+// Its stream pads every document's nonzeros to a multiple of four (term -1,
+// value 0), so that each lane's four-nonzero reads are 16-byte aligned, and
+// keeps four spare entries past the end: vh_stream_cap entries in all.
+inline int64_t vh_stream_cap(int64_t m, int64_t nnz) { return nnz + 3 * m + 4; }
+inline bool vhalf_fits(size_t elt, int64_t n, int64_t m, int k, int64_t nnz) {
   return elt == 4 && k <= 64 && (m + 16) * k * 4 < (int64_t{1} << 32) &&
+         vh_stream_cap(m, nnz) * 4 < (int64_t{1} << 32) &&
          (m + 16) * kMaxHot * 4 < (int64_t{1} << 32) && (n + 31) / 32 <= kVhTabWords;
 }
 
