@@ -82,34 +82,118 @@ def read_traffic(stage: str):
     return float(s["fetch_bytes"] + s["write_bytes"])
 
 
+def host_info() -> dict:
+    """CPU model, logical cores and RAM of the host the oracle runs on."""
+    model, ram = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cores": os.cpu_count(), "ram_gib": ram}
+
+
+def _blas_threads() -> int:
+    from threadpoolctl import threadpool_info
+
+    return max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+
+
 def cpu_baseline(corpus, u0, p, iters: int):
-    """The FP64 oracle as it stands, single-threaded, on a bounded sample:
-    one untimed iteration from U0, then `iters` timed steady-state iterations
-    of the same workload."""
-    import numpy as np
+    """The FP64 oracle as it stands, on all of the host's cores (its dense
+    products and solves run in the multithreaded BLAS; scipy's sparse
+    products are single-threaded), on a bounded sample: one untimed
+    iteration from U0, then `iters` timed steady-state iterations of the same
+    workload."""
     from threadpoolctl import threadpool_limits
 
     import oracle
 
     A = corpus.scipy()
-    with threadpool_limits(limits=1):
+    cores = os.cpu_count() or 1
+    with threadpool_limits(limits=cores):
         st = oracle.als(A, u0, p["t_u"], p["t_v"], 1)
         times = []
         for _ in range(iters):
             t0 = time.perf_counter()
             st = oracle.als(A, u0, p["t_u"], p["t_v"], 1, state=st)
             times.append(time.perf_counter() - t0)
+        threads = _blas_threads()
     med = statistics.median(times)
     return {
         "value": 1.0 / med,
         "unit": "it/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"{iters} steady-state ALS iterations (after 1 untimed from U0) of the full "
-                   f"{corpus.n}x{corpus.m} / {corpus.nnz}-nnz workload, FP64 numpy/scipy oracle, "
-                   f"1 thread, median {med:.2f} s/iteration"),
+                   f"{corpus.n}x{corpus.m} / {corpus.nnz}-nnz workload, FP64 numpy/scipy oracle, BLAS on "
+                   f"{threads} threads (sparse products single-threaded), median {med:.2f} s/iteration"),
+        "host": host_info(),
         "E_after": float(st.E[-1]),
     }
+
+
+def cpu_loss_baseline():
+    """The FP64 oracle's loss and gradient (Eq. (2) squared, both partial
+    derivatives) once on the 100k x 200k matrix with sparse U, V (t = 1000
+    and 2000 per column, seed 4): the same evaluation NMFLoss performs."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    import synth
+
+    c, _, _, p = synth.make_workload("plain_f32_100kx200k", with_init=False)
+    rng = np.random.Generator(np.random.PCG64(4))
+    U = synth.sparse_factor_init(c.n, p["k"], p["t_u"], rng=rng, dtype="f32")
+    V = synth.sparse_factor_init(c.m, p["k"], p["t_v"], rng=rng, dtype="f32")
+    A = c.scipy()
+    with threadpool_limits(limits=os.cpu_count() or 1):
+        t0 = time.perf_counter()
+        oracle.loss(A, U, V)
+        oracle.loss_grad(A, U, V)
+        dt = time.perf_counter() - t0
+    return {"workload": "plain_f32_100kx200k sparse U,V (t_u=1000, t_v=2000, seed 4)", "ms_fwd_bwd": round(dt * 1e3, 1),
+            "threads": _blas_threads()}
+
+
+def cpu_batch_baseline(problems, sample: int = 16):
+    """The FP64 oracle on a sample of the many-corpora batch: one ALS
+    iteration (after one untimed) of `sample` corpora spread over the batch
+    (the smallest and the largest included), extrapolated to one iteration
+    of every corpus by the sample's time per nonzero."""
+    import numpy as np
+    import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    nnz = np.array([int(p["indptr"][-1]) for p in problems])
+    order = np.argsort(nnz, kind="stable")
+    pick = sorted(set(order[np.linspace(0, len(problems) - 1, sample).round().astype(int)].tolist()))
+    t_tot, nnz_s = 0.0, 0
+    with threadpool_limits(limits=os.cpu_count() or 1):
+        for i in pick:
+            p = problems[i]
+            A = sp.csr_matrix((p["data"].astype(np.float64), p["indices"], p["indptr"]), shape=(p["n"], p["m"]))
+            u0 = p["u0"].astype(np.float64)
+            st = oracle.als(A, u0, p["t_u"], p["t_v"], 1)
+            t0 = time.perf_counter()
+            oracle.als(A, u0, p["t_u"], p["t_v"], 1, state=st)
+            t_tot += time.perf_counter() - t0
+            nnz_s += int(nnz[i])
+    est = t_tot * nnz.sum() / nnz_s
+    return {"corpora_timed": len(pick), "nnz_timed": nnz_s, "s_timed": round(t_tot, 2),
+            "s_per_batch_iteration_extrapolated": round(float(est), 1), "threads": _blas_threads(),
+            "note": "one ALS iteration of every corpus, extrapolated from the sample by nonzeros"}
 
 
 def batch_bench(problems, iters: int, warmup: int):
@@ -545,10 +629,15 @@ def main():
     del rp, ci, cv, u0d
     torch.cuda.empty_cache()
     out["batched"] = batch_bench(batch, args.batch_iters, args.batch_warmup) if batch else None
+    batch_problems = batch
     batch = None
     if not args.no_cpu_baseline:
         log("timing the FP64 CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(corpus, u0, p, args.cpu_iters)
+        log("timing the oracle's loss and gradient, and a sample of the batch")
+        out["cpu_baseline"]["loss_fwd_bwd"] = cpu_loss_baseline()
+        if batch_problems:
+            out["cpu_baseline"]["batched"] = cpu_batch_baseline(batch_problems)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
