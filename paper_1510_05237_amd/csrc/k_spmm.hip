@@ -17,7 +17,10 @@
 //    the factor row's metadata {where, how many entries};
 //  * factor rows with at most `sparse_row` entries are gathered entry by entry
 //    (one {value, topic} load per entry, lanes still = nonzeros) and each
-//    product is added into the accumulator at (row, topic) with an LDS atomic;
+//    product is added into the accumulator at (row, topic) in a fixed order:
+//    where several lanes of one instruction add to the same place, the
+//    lowest lane goes first (found with an integer atomicMin on a small
+//    claim table; no floating-point atomics);
 //  * denser factor rows are queued in row order and then read whole from the
 //    compact dense copy of the factor, lanes = topics, eight rows in flight;
 //    the running sums for the current row stay in registers and go to the
@@ -53,12 +56,17 @@ constexpr int kTileEntries = 512;
 // halved when each lane holds two topics).
 constexpr int kQueueBatch = 8;
 
+// Claim table of the ordered entry-by-entry adds (one per wave): slot
+// (row, topic) of the accumulator hashes to entry (topic + 16 row) % 128.
+constexpr int kClaims = 128;
+
 // Per wave: the queue's values, byte offsets and item rows, then the
-// accumulator.
+// accumulator, then the claim table.
 template <typename T, int RG, bool WIDE>
 __host__ __device__ inline size_t spmm_per_wave(int) {
   constexpr size_t Q = queue_len<WIDE>();
-  return Q * (sizeof(T) + sizeof(uint32_t)) + (Q + 15) / 16 * 16 + kTileEntries * sizeof(T);
+  return Q * (sizeof(T) + sizeof(uint32_t)) + (Q + 15) / 16 * 16 + kTileEntries * sizeof(T) +
+         kClaims * sizeof(int32_t);
 }
 
 // LDS of one block: W (unless raw), then each wave's buffers.
@@ -98,6 +106,7 @@ struct WaveLds {
   uint8_t* q_r;     //                  row within the item
   void* q_a;        //                  the nonzero's value
   void* tile;       // accumulator: tile[topic * RG + row]
+  int32_t* claim;   // claim table of the ordered adds (INT32_MAX when free)
 };
 
 template <typename T, int RG, bool WIDE>
@@ -109,6 +118,7 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, size_t wave0, i
   w.q_off = reinterpret_cast<uint32_t*>(base + Q * sizeof(T));
   w.q_r = base + Q * (sizeof(T) + sizeof(uint32_t));
   w.tile = base + Q * (sizeof(T) + sizeof(uint32_t)) + (Q + 15) / 16 * 16;
+  w.claim = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(w.tile) + kTileEntries * sizeof(T));
   return w;
 }
 
@@ -295,6 +305,31 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
   return nh8;
 }
 
+// Adds v into tile[slot] on every lane where `pend` holds.  Lanes of one
+// call that add to the same slot do so in ascending lane order: in each
+// sub-round every pending lane writes its lane number into its slot's claim
+// entry with an integer atomicMin (the result does not depend on the order
+// in which the hardware applies the lanes), the lane that finds its own
+// number there adds (no other lane of the sub-round touches that slot) and
+// frees the entry, and the rest try again.  Different slots that share a
+// claim entry only wait one more sub-round.  The sums are therefore the same
+// on every run.
+template <typename T, int RG>
+__device__ __forceinline__ void ordered_add(T* tile, int32_t* claim, int t, int r, T v, bool pend) {
+  const int lane = lane_id();
+  const int slot = t * RG + r;
+  int32_t* cl = &claim[(t + 16 * r) & (kClaims - 1)];
+  while (__ballot(pend) != 0) {
+    if (pend) __hip_atomic_fetch_min(cl, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const bool win = pend && __hip_atomic_load(cl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == lane;
+    if (win) {
+      tile[slot] += v;
+      __hip_atomic_store(cl, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      pend = false;
+    }
+  }
+}
+
 // Adds the nonzeros [p0, p1) of an item (rows bounded by rb[0..nrows]) times
 // F into the accumulator.
 //  * Narrow form (64 nonzeros per step): loads are predicated on the lanes
@@ -401,16 +436,18 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
           for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-              if (act[s][d]) atomicAdd(&tile[en[s][d].t * RG + r[s]], av[s] * en[s][d].v);
+              ordered_add<T, RG>(tile, w.claim, static_cast<int>(en[s][d].t), r[s], av[s] * en[s][d].v, act[s][d]);
         }
       } else {
         for (int e = 0; __ballot(sparse[0] && e < cnt[0]) != 0; ++e) {
-          if (sparse[0] && e < cnt[0]) {
+          const bool act = sparse[0] && e < cnt[0];
+          FactorEnt<T> en{T(0), 0u};
+          if (act) {
             int idx = e + rot[0];
             if (idx >= cnt[0]) idx -= cnt[0];
-            const FactorEnt<T> en = ents[x[0] + idx];
-            atomicAdd(&tile[en.t * RG + r[0]], av[0] * en.v);
+            en = ents[x[0] + idx];
           }
+          ordered_add<T, RG>(tile, w.claim, static_cast<int>(en.t), r[0], av[0] * en.v, act);
         }
       }
     }
@@ -509,6 +546,8 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
   const double* sW = reinterpret_cast<const double*>(smem);
   const WaveLds w = wave_lds<T, RG, WIDE>(smem, wave0, k, wv);
   T* tile = static_cast<T*>(w.tile);
+#pragma unroll
+  for (int i = 0; i < kClaims / 64; ++i) w.claim[lane + 64 * i] = INT32_MAX;
 
   const int bw = blockDim.x >> 6;
   const int nw = nblk * bw;
