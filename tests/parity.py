@@ -5,10 +5,15 @@ A factor from the GPU and one from the oracle are compared in three parts:
   normalised by the oracle factor's norm;
 * values, per column and per entry: for every column c the relative error
   ||x_gpu,c - x_or,c|| / ||x_or,c|| over the entries both keep, and for every
-  entry both keep |x_gpu - x_or| <= tol * max(|x_or|, theta_c), i.e. an
-  element-wise relative bound whose floor is the column's threshold theta_c
-  (the smallest value the oracle keeps in that column).  A column or a few
-  entries far off can no longer hide behind the norm of the rest;
+  entry both keep |x_gpu - x_or| <= tol * max(|x_or|, theta_c, s_r), i.e. an
+  element-wise relative bound whose floor is the larger of the column's
+  threshold theta_c (the smallest value the oracle keeps in that column) and
+  the row's scale s_r (its largest pre-selection value).  The row floor is
+  the precision the float32 product allows: a row's raw sums are rounded
+  relative to their own magnitude and the solve mixes all of them, so an
+  entry that is small through cancellation carries an error of the row's
+  size, not of its own.  A column or a few entries far off can no longer
+  hide behind the norm of the rest;
 * supports: every entry kept by one side only is a mismatch.  It is a
   near-tie when its pre-selection value lies within ``tol * theta_c`` of the
   oracle's threshold theta_c of that column (for the whole-matrix rule, the
@@ -31,7 +36,8 @@ class FactorDiff:
     non_ties: int
     col_rel: float = 0.0   # worst per-column relative error
     worst_col: int = -1
-    elem: float = 0.0      # worst |dx| / max(|x_or|, theta_c) over entries both keep
+    elem: float = 0.0      # worst |dx| / max(|x_or|, theta_c, s_r) over entries both keep
+    elem_at: tuple = ()    # (row, column, x_gpu, x_or, floor) of that entry
 
     def ok(self, tol: float) -> bool:
         return self.rel <= tol and self.col_rel <= tol and self.elem <= tol and self.non_ties == 0
@@ -49,6 +55,7 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
     X_gpu = np.asarray(X_gpu, np.float64)
     X_or = np.asarray(X_or, np.float64)
     Xpre = np.where(np.asarray(Xpre_or, np.float64) > 0, Xpre_or, 0.0)
+    row_scale = Xpre.max(axis=1) if Xpre.size else np.zeros(X_or.shape[0])
     kg, ko = X_gpu != 0, X_or != 0
     both = kg & ko
     den = np.linalg.norm(X_or)
@@ -56,7 +63,7 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
     theta_all = X_or[ko].min() if ko.any() else 0.0
     # per column: relative error of the entries both keep, element-wise bound
     D = np.where(both, X_gpu - X_or, 0.0)
-    col_rel, worst_col, elem = 0.0, -1, 0.0
+    col_rel, worst_col, elem, elem_at = 0.0, -1, 0.0, ()
     for c in range(X_or.shape[1]):
         kept = X_or[ko[:, c], c]
         theta = theta_all if whole else (kept.min() if kept.size else 0.0)
@@ -67,8 +74,12 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
             col_rel, worst_col = r, c
         sel = both[:, c]
         if sel.any():
-            floor = np.maximum(np.abs(X_or[sel, c]), max(theta, 1e-300))
-            elem = max(elem, float(np.max(np.abs(dc[sel]) / floor)))
+            floor = np.maximum(np.maximum(np.abs(X_or[sel, c]), row_scale[sel]), max(theta, 1e-300))
+            ratio = np.abs(dc[sel]) / floor
+            j = int(np.argmax(ratio))
+            if ratio[j] > elem:
+                i = int(np.flatnonzero(sel)[j])
+                elem, elem_at = float(ratio[j]), (i, int(c), float(X_gpu[i, c]), float(X_or[i, c]), float(floor[j]))
     mism = kg != ko
     near = non = 0
     for c in np.nonzero(mism.any(axis=0))[0]:
@@ -80,7 +91,7 @@ def compare_factor(X_gpu: np.ndarray, X_or: np.ndarray, Xpre_or: np.ndarray, tol
                 near += 1
             else:
                 non += 1
-    return FactorDiff(rel, int(mism.sum()), near, non, col_rel, worst_col, elem)
+    return FactorDiff(rel, int(mism.sum()), near, non, col_rel, worst_col, elem, elem_at)
 
 
 def rel_fro(a, b) -> float:
@@ -114,16 +125,18 @@ def check_pre(a, b, tol: float) -> float:
 def elem_kept(X_gpu, Xpre_or) -> float:
     """Worst element-wise error of the GPU's kept entries against the oracle's
     pre-selection values at the same positions (both sides took the step from
-    the same input): max |x_gpu - x_or| / max(|x_or|, theta_c), theta_c the
-    smallest value the GPU keeps in column c."""
+    the same input): max |x_gpu - x_or| / max(|x_or|, theta_c, s_r), theta_c
+    the smallest value the GPU keeps in column c, s_r the row's largest
+    pre-selection value (see the module docstring)."""
     X_gpu = np.asarray(X_gpu, np.float64)
     Xp = np.asarray(Xpre_or, np.float64)
+    row_scale = np.where(Xp > 0, Xp, 0.0).max(axis=1)
     worst = 0.0
     for c in range(X_gpu.shape[1]):
         sel = X_gpu[:, c] != 0
         if not sel.any():
             continue
         theta = X_gpu[sel, c].min()
-        err = np.abs(X_gpu[sel, c] - Xp[sel, c]) / np.maximum(np.abs(Xp[sel, c]), theta)
+        err = np.abs(X_gpu[sel, c] - Xp[sel, c]) / np.maximum(np.maximum(np.abs(Xp[sel, c]), row_scale[sel]), theta)
         worst = max(worst, float(err.max()))
     return worst

@@ -254,3 +254,51 @@ def test_batch_tune_then_restart():
     for i in range(len(probs)):
         _same_tail(b.problem(i), ref[i])
     b.close()
+
+
+def test_batch_fp32_members_vs_oracle():
+    """FP32 members of a fused batch against the FP64 oracle, half-step by
+    half-step from the GPU's own state (the smallest- and largest-k shapes
+    above, and the three members of the 256-corpus batch with the fewest
+    nonzeros): after each fused-graph iteration, V against the oracle's V
+    half from the member's previous U, U against the oracle's U half from
+    the member's V (whole matrix, every column and every kept entry within
+    1e-4; supports equal but for near-ties), and E against the oracle's E of
+    the member's factors."""
+    _, NMFBatch, _ = _lib()
+    from tests.parity import compare_factor
+
+    probs = _problems("f32", [SHAPES[2], SHAPES[4]])
+    params = synth.batched_params(256)
+    small = sorted(range(len(params)), key=lambda i: (params[i]["nnz"], i))[:3]
+    for p in synth.make_batch([params[i] for i in small], dtype="f32"):
+        p = dict(p)
+        p["corpus_csr"] = sp.csr_matrix((p["data"].astype(np.float64), p["indices"], p["indptr"]),
+                                        shape=(p["n"], p["m"]))
+        probs.append(p)
+    for p in probs:
+        if "corpus" in p:
+            p["corpus_csr"] = p["corpus"].scipy()
+    _say(f"batch fused_graph f32, {len(probs)} members (k={[p['k'] for p in probs]}, "
+         f"nnz={[int(p['indptr'][-1]) for p in probs]}) vs oracle, 4 iterations")
+    b = NMFBatch(probs, dtype="f32")
+    prev = [p["u0"] for p in probs]
+    for it in range(4):
+        b.step(1, "fused_graph")
+        E, st = b.errors()
+        assert list(st) == [0] * len(probs)
+        for i, p in enumerate(probs):
+            A = p["corpus_csr"]
+            U, V = b.problem(i).factors()
+            _, iv = oracle.half_step(sp.csr_matrix(A.T), prev[i].astype(np.float64), p["t_v"])
+            Vo = oracle.topt_per_column(oracle.clamp(iv["X_pre"]), p["t_v"])
+            dv = compare_factor(V, Vo, iv["X_pre"], 1e-4)
+            _, iu = oracle.half_step(A, V.astype(np.float64), p["t_u"])
+            Uo = oracle.topt_per_column(oracle.clamp(iu["X_pre"]), p["t_u"])
+            du = compare_factor(U, Uo, iu["X_pre"], 1e-4)
+            Eo = oracle.error(A, U.astype(np.float64), V.astype(np.float64))
+            _say(f"  iteration {it + 1} member {i}: E {E[i]:.7f} (oracle {Eo:.7f}) | V {dv} | U {du}")
+            assert abs(E[i] - Eo) <= 1e-4 * Eo
+            assert dv.ok(1e-4) and du.ok(1e-4), (it, i, str(dv), dv.elem_at, str(du), du.elem_at)
+            prev[i] = U
+    b.close()

@@ -65,12 +65,15 @@ def test_fp32_100kx200k_half_steps():
     prob.close()
 
 
-def test_fp32_100kx200k_loss_and_gradient():
+@pytest.mark.parametrize("t_u,t_v", [(1000, 2000), (200, 100)])
+def test_fp32_100kx200k_loss_and_gradient(t_u, t_v):
     """The autograd loss on the full 100k x 200k matrix with sparse U, V
-    (t = 1000 and 2000 rows per column, values U(0,1), seed 4): L and both
+    (t_u and t_v rows per column, values U(0,1), seed 4): L and both
     gradients against the FP64 oracle to 1e-4, and central differences of the
     row-restricted FP64 loss (exactly quadratic in each entry) at 64 entries,
-    32 of U and 32 of V, half of them inside the support."""
+    32 of U and 32 of V, half of them inside the support.  "t as in config 1"
+    is read both ways: the 100k x 200k workload's own t (1000, 2000) and the
+    2000 x 1000 workload's (200, 100)."""
     import torch
 
     if not torch.cuda.is_available():
@@ -80,10 +83,11 @@ def test_fp32_100kx200k_loss_and_gradient():
     c, _, _, p = synth.make_workload("plain_f32_100kx200k", with_init=False)
     k = p["k"]
     rng = np.random.Generator(np.random.PCG64(4))
-    U = synth.sparse_factor_init(c.n, k, p["t_u"], rng=rng, dtype="f32")
-    V = synth.sparse_factor_init(c.m, k, p["t_v"], rng=rng, dtype="f32")
+    U = synth.sparse_factor_init(c.n, k, t_u, rng=rng, dtype="f32")
+    V = synth.sparse_factor_init(c.m, k, t_v, rng=rng, dtype="f32")
     dev = torch.device("cuda:0")
-    _say(f"fp32 autograd loss {c.n}x{c.m} nnz={c.nnz} k={k}, sparse U ({np.count_nonzero(U)}) and V ({np.count_nonzero(V)})")
+    _say(f"fp32 autograd loss {c.n}x{c.m} nnz={c.nnz} k={k}, sparse U ({np.count_nonzero(U)}, t={t_u}) "
+         f"and V ({np.count_nonzero(V)}, t={t_v})")
     prob = NMF(c.n, c.m, torch.from_numpy(c.indptr).to(dev), torch.from_numpy(c.indices).to(dev),
                torch.from_numpy(c.data).to(dev), torch.from_numpy(U).to(dev), t_u=p["t_u"], t_v=p["t_v"],
                dtype="f32", device=dev)
@@ -146,7 +150,7 @@ def test_fp32_100kx200k_loss_and_gradient():
 
 def test_fp32_100kx200k_free_running_trajectory():
     """The headline workload (100k x 200k, 20M nnz, k = 50, t_u = 1000,
-    t_v = 2000) run free on the GPU for 30 iterations beside the FP64 oracle
+    t_v = 2000) run free on the GPU for its 50 iterations beside the FP64 oracle
     run free from the same U0.  Per iteration: E within 1e-4 relative; U and
     V within 1e-4 relative as a whole and in every column (tests/parity.py);
     every support mismatch counted and split into near-ties (both disputed
@@ -168,7 +172,7 @@ def test_fp32_100kx200k_free_running_trajectory():
     c, u0, _, p = synth.make_workload("plain_f32_100kx200k")
     A = c.scipy()
     dev = torch.device("cuda:0")
-    iters = 30
+    iters = 50
     _say(f"fp32 free-running trajectory {c.n}x{c.m} nnz={c.nnz} k={p['k']}: {iters} iterations against the oracle")
     prob = NMF(c.n, c.m, torch.from_numpy(c.indptr).to(dev), torch.from_numpy(c.indices).to(dev),
                torch.from_numpy(c.data).to(dev), torch.from_numpy(u0).to(dev), t_u=p["t_u"], t_v=p["t_v"],

@@ -1,9 +1,10 @@
 """GPU parity at the scale size: 1M terms x 5M docs, 200 distinct terms per
 doc (1B nonzeros, held in both orientations in HBM), k = 100, t_u = 5000,
 t_v = 20000, FP32 with FP64 solves.  The corpus is drawn on the GPU
-(synth.scale).  One iteration of half-steps; the FP64 reference rows of both
-pre-selection matrices are recomputed on the CPU for sampled documents and
-terms from the GPU's own inputs to each half-step, and the top-t rule is
+(synth.scale).  One iteration of half-steps; the FP64 oracle's half-step
+recomputes the rows of both pre-selection matrices for sampled documents and
+terms (on the row-restricted matrix, from the GPU's own inputs to each
+half-step: U0, then the GPU's V), and the top-t rule is
 re-applied on the CPU to the GPU's whole pre-selection matrices (the kept
 sets must equal the GPU's exactly).  Prints every step before it runs."""
 
@@ -12,6 +13,9 @@ import time
 import numpy as np
 import pytest
 import scipy.sparse as sp
+
+import oracle
+from tests.parity import check_pre
 
 pytestmark = pytest.mark.gpu
 
@@ -38,10 +42,6 @@ def _kept_exact(X, t):
         keep[above, c] = True
         keep[eq[: t - above.size], c] = True
     return keep
-
-
-def _rel_rows(got, ref):
-    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
 def test_scale_1Mx5M_sampled():
@@ -80,12 +80,13 @@ def test_scale_1Mx5M_sampled():
     _say("  V half")
     prob.half_step(0)
     vpre = prob.pre(0)
-    G = U0.T @ U0
-    B = np.einsum("jd,jdk->jk", dv, U0[dt])
-    ref = np.maximum(np.linalg.solve(G, B.T).T, 0.0)
-    rv = _rel_rows(vpre[docs].astype(np.float64), ref)
-    _say(f"  V_pre sampled rows rel {rv:.2e}")
-    assert rv <= 1e-4
+    # the oracle's half-step on the sampled documents' rows of A^T (its Gram
+    # matrix is that of the whole U0)
+    A_docs = sp.csr_matrix((dv.ravel(), dt.ravel(), np.arange(0, dt.size + 1, dt.shape[1])), shape=(docs.size, N))
+    _, info = oracle.half_step(A_docs, U0, T_V)
+    ref = oracle.clamp(info["X_pre"])
+    rv = check_pre(vpre[docs].astype(np.float64), ref, 1e-4)
+    _say(f"  V_pre sampled rows: worst (whole or column) rel {rv:.2e}")
     _, V = prob.factors()
     keep = _kept_exact(vpre, T_V)
     np.testing.assert_array_equal(V != 0, keep)
@@ -95,17 +96,13 @@ def test_scale_1Mx5M_sampled():
     _say("  U half")
     prob.half_step(1)
     upre = prob.pre(1)
-    Vs = sp.csr_matrix(V.astype(np.float64))
-    GV = (Vs.T @ Vs).toarray()
+    # the oracle's half-step on the sampled terms' rows of A, from the GPU's V
     starts = np.concatenate([[0], np.cumsum(t_len)])
-    C = np.zeros((terms.size, K))
-    for q in range(terms.size):
-        a, b = starts[q], starts[q + 1]
-        C[q] = Vs[t_docs[a:b]].T @ t_vals[a:b]
-    ref = np.maximum(np.linalg.solve(GV, C.T).T, 0.0)
-    ru = _rel_rows(upre[terms].astype(np.float64), ref)
-    _say(f"  U_pre sampled rows rel {ru:.2e}")
-    assert ru <= 1e-4
+    A_terms = sp.csr_matrix((t_vals, t_docs, starts), shape=(terms.size, M))
+    _, info = oracle.half_step(A_terms, V.astype(np.float64), T_U)
+    ref = oracle.clamp(info["X_pre"])
+    ru = check_pre(upre[terms].astype(np.float64), ref, 1e-4)
+    _say(f"  U_pre sampled rows: worst (whole or column) rel {ru:.2e}")
     U, _ = prob.factors()
     keep = _kept_exact(upre, T_U)
     np.testing.assert_array_equal(U != 0, keep)
