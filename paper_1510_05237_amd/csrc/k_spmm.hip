@@ -59,6 +59,18 @@ constexpr int kQueueBatch = 8;
 // Claim table of the ordered entry-by-entry adds (one per wave): slot
 // (row, topic) of the accumulator hashes to entry (topic + 16 row) % 128.
 constexpr int kClaims = 128;
+// Sub-rounds before the claim table is cleared and the tag restarts (tags
+// stay far from overflowing the 32-bit entries).
+constexpr int32_t kTagMax = 1 << 22;
+
+// Restarts the tag and clears the wave's claim table once the tag has grown
+// large (wave-uniform).
+__device__ __forceinline__ void claim_restart(int32_t* claim, int32_t& tag) {
+  if (tag >= kTagMax) {
+    for (int i = lane_id(); i < kClaims; i += 64) claim[i] = 0;
+    tag = 0;
+  }
+}
 
 // Per wave: the queue's values, byte offsets and item rows, then the
 // accumulator, then the claim table.
@@ -106,7 +118,7 @@ struct WaveLds {
   uint8_t* q_r;     //                  row within the item
   void* q_a;        //                  the nonzero's value
   void* tile;       // accumulator: tile[topic * RG + row]
-  int32_t* claim;   // claim table of the ordered adds (INT32_MAX when free)
+  int32_t* claim;   // claim table of the ordered adds (tags of earlier sub-rounds; zero at start)
 };
 
 template <typename T, int RG, bool WIDE>
@@ -307,24 +319,28 @@ __device__ __forceinline__ int queue_hits(const WaveLds& w, const bool* hit, con
 
 // Adds v into tile[slot] on every lane where `pend` holds.  Lanes of one
 // call that add to the same slot do so in ascending lane order: in each
-// sub-round every pending lane writes its lane number into its slot's claim
-// entry with an integer atomicMin (the result does not depend on the order
-// in which the hardware applies the lanes), the lane that finds its own
-// number there adds (no other lane of the sub-round touches that slot) and
-// frees the entry, and the rest try again.  Different slots that share a
-// claim entry only wait one more sub-round.  The sums are therefore the same
-// on every run.
+// sub-round every pending lane writes the tag (sub-round << 6 | 63 - lane)
+// into its slot's claim entry with an integer atomicMax (the result does not
+// depend on the order in which the hardware applies the lanes, and tags of
+// earlier sub-rounds are smaller), and the lane that finds its own tag there
+// adds; the winners of a sub-round hold distinct slots, so their adds never
+// collide.  The rest try again.  Different slots that share a claim entry
+// only wait one more sub-round.  The sums are therefore the same on every
+// run.  `tag` counts the wave's sub-rounds (wave-uniform; the claim table
+// starts at zero).
 template <typename T, int RG>
-__device__ __forceinline__ void ordered_add(T* tile, int32_t* claim, int t, int r, T v, bool pend) {
+__device__ __forceinline__ void ordered_add(T* tile, int32_t* claim, int32_t& tag, int t, int r, T v, bool pend) {
   const int lane = lane_id();
   const int slot = t * RG + r;
   int32_t* cl = &claim[(t + 16 * r) & (kClaims - 1)];
   while (__ballot(pend) != 0) {
-    if (pend) __hip_atomic_fetch_min(cl, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const bool win = pend && __hip_atomic_load(cl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == lane;
+    claim_restart(claim, tag);
+    ++tag;
+    const int32_t mine = (tag << 6) | (63 - lane);
+    if (pend) __hip_atomic_fetch_max(cl, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const bool win = pend && __hip_atomic_load(cl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == mine;
     if (win) {
-      tile[slot] += v;
-      __hip_atomic_store(cl, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&tile[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       pend = false;
     }
   }
@@ -343,7 +359,7 @@ __device__ __forceinline__ void ordered_add(T* tile, int32_t* claim, int t, int 
 //    wave mostly waits on the metadata and entry gathers.
 template <typename T, int KPL, int RG, bool DENSE_IN, bool WIDE>
 __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_t p1, const int64_t* rb,
-                                           int nrows, const WaveLds& w, uint32_t& gath) {
+                                           int nrows, const WaveLds& w, uint32_t& gath, int32_t& tag) {
   constexpr int NS = WIDE ? 2 : 1;
   const int lane = lane_id();
   const int k = a.k;
@@ -436,7 +452,7 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
           for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-              ordered_add<T, RG>(tile, w.claim, static_cast<int>(en[s][d].t), r[s], av[s] * en[s][d].v, act[s][d]);
+              ordered_add<T, RG>(tile, w.claim, tag, static_cast<int>(en[s][d].t), r[s], av[s] * en[s][d].v, act[s][d]);
         }
       } else {
         for (int e = 0; __ballot(sparse[0] && e < cnt[0]) != 0; ++e) {
@@ -447,7 +463,7 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
             if (idx >= cnt[0]) idx -= cnt[0];
             en = ents[x[0] + idx];
           }
-          ordered_add<T, RG>(tile, w.claim, static_cast<int>(en.t), r[0], av[0] * en.v, act);
+          ordered_add<T, RG>(tile, w.claim, tag, static_cast<int>(en.t), r[0], av[0] * en.v, act);
         }
       }
     }
@@ -547,11 +563,12 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
   const WaveLds w = wave_lds<T, RG, WIDE>(smem, wave0, k, wv);
   T* tile = static_cast<T*>(w.tile);
 #pragma unroll
-  for (int i = 0; i < kClaims / 64; ++i) w.claim[lane + 64 * i] = INT32_MAX;
+  for (int i = 0; i < kClaims / 64; ++i) w.claim[lane + 64 * i] = 0;
 
   const int bw = blockDim.x >> 6;
   const int nw = nblk * bw;
   uint32_t gath = 0;  // this lane's gathered entries (fits: at most k per nonzero it loads)
+  int32_t tag = 0;    // sub-rounds of the ordered adds so far (wave-uniform)
   for (int it = blk * bw + wv; it < a.n_items; it += nw) {
     const WorkItem wi = a.items[it];
     clear_tile<T, KPL, RG>(tile, k);
@@ -564,13 +581,13 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
       int64_t rb[RG + 1];
 #pragma unroll
       for (int i = 0; i <= RG; ++i) rb[i] = a.rowptr[wi.r0 + (i < nrows ? i : nrows)];
-      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, rb[0], rb[nrows], rb, nrows, w, gath);
+      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, rb[0], rb[nrows], rb, nrows, w, gath, tag);
       epilogue<T, KPL, RG, RAW, STORE_C>(a, tile, sW, nrows, wi.r0);
     } else {
       int64_t rb[RG + 1];
 #pragma unroll
       for (int i = 0; i <= RG; ++i) rb[i] = i == 0 ? wi.p0 : wi.p1;
-      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, wi.p0, wi.p1, rb, 1, w, gath);
+      accumulate<T, KPL, RG, DENSE_IN, WIDE>(a, wi.p0, wi.p1, rb, 1, w, gath, tag);
       T* part = static_cast<T*>(a.partials);
 #pragma unroll
       for (int q = 0; q < KPL; ++q) {
