@@ -346,6 +346,39 @@ __device__ __forceinline__ void ordered_add(T* tile, int32_t* claim, int32_t& ta
   }
 }
 
+// A single-row item's entry-by-entry products are not added into the
+// accumulator one by one: each step appends them, in a fixed order (round,
+// then nonzero), to a list kept in the wave's accumulator space (unused
+// until the item ends: the row's sums stay in registers), and the list is
+// then summed with lanes = topics, each lane adding the entries of its topic
+// in list order.  No two lanes ever add to one place.
+constexpr int kListCap = 256;
+
+template <typename T, int KPL>
+__device__ __forceinline__ void scan_list(const int32_t* lt, const T* lw, int n, T* acc) {
+  const int lane = lane_id();
+  int j = 0;
+  for (; j + 4 <= n; j += 4) {
+    int tv[4];
+    T wv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      tv[u] = lt[j + u];
+      wv[u] = lw[j + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < KPL; ++q) acc[q] += tv[u] == lane + 64 * q ? wv[u] : T(0);
+  }
+  for (; j < n; ++j) {
+    const int tv = lt[j];
+    const T wv = lw[j];
+#pragma unroll
+    for (int q = 0; q < KPL; ++q) acc[q] += tv == lane + 64 * q ? wv : T(0);
+  }
+}
+
 // Adds the nonzeros [p0, p1) of an item (rows bounded by rb[0..nrows]) times
 // F into the accumulator.
 //  * Narrow form (64 nonzeros per step): loads are predicated on the lanes
@@ -431,7 +464,46 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
         sparse[s] = cnt[s] > 0 && cnt[s] <= a.sparse_row;
         rot[s] = sparse[s] ? lane % cnt[s] : 0;
       }
-      if (WIDE) {
+      if (nrows == 1) {
+        // one row: the products go to the list (see scan_list), which is
+        // summed into the row's registers whenever it could overflow and at
+        // the end of the step
+        int32_t* lt = reinterpret_cast<int32_t*>(tile);
+        T* lw = reinterpret_cast<T*>(lt + kListCap);
+        int nl = 0;
+        for (int e = 0; __ballot((sparse[0] && e < cnt[0]) || (sparse[NS - 1] && e < cnt[NS - 1])) != 0; ++e) {
+          bool act[NS];
+          uint64_t bal[NS];
+          int tot = 0;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            act[s] = sparse[s] && e < cnt[s];
+            bal[s] = __ballot(act[s]);
+            tot += __popcll(bal[s]);
+          }
+          if (nl + tot > kListCap) {
+            __builtin_amdgcn_wave_barrier();
+            scan_list<T, KPL>(lt, lw, nl, acc);
+            __builtin_amdgcn_wave_barrier();
+            nl = 0;
+          }
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            if (act[s]) {
+              int idx = e + rot[s];
+              if (idx >= cnt[s]) idx -= cnt[s];
+              const FactorEnt<T> en = ents[x[s] + idx];
+              const int pos = nl + lane_rank(bal[s]);
+              lt[pos] = static_cast<int32_t>(en.t);
+              lw[pos] = av[s] * en.v;
+            }
+            nl += __popcll(bal[s]);
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        scan_list<T, KPL>(lt, lw, nl, acc);
+        __builtin_amdgcn_wave_barrier();
+      } else if (WIDE) {
         // entries e and e + 1 of every row per round; a round only runs when
         // some lane has an entry left, so entry 0 exists and serves as the
         // inactive lanes' address
@@ -473,6 +545,13 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
     for (int s = 0; s < NS; ++s) hit[s] = DENSE_IN ? valid[s] : cnt[s] > a.sparse_row;
     const int nq = queue_hits<T, NS>(w, hit, x, r, av, ldb);
     run_queue<T, KPL, RG>(w, Fr, nq, k, acc, cur_r);
+  }
+  if (!DENSE_IN && nrows == 1) {
+    // the accumulator space held the list: the row's sums replace it
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int i = 0; i < kTileEntries / 64; ++i) tile[lane + 64 * i] = T(0);
+    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
   for (int q = 0; q < KPL; ++q) tile[(lane + 64 * q) * RG + cur_r] += acc[q];

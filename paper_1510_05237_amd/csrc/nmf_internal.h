@@ -137,7 +137,6 @@ inline int32_t dense_ld(int32_t k, size_t elt) {
   return (k + v - 1) / v * v;
 }
 
-constexpr int kSparseRow = 3;  // default: factor rows with at most this many entries are gathered entry by entry
 
 // Gram matrix of a factor and its inverse.
 struct Gram {
@@ -254,7 +253,7 @@ struct nmf_handle {
   // (its own queue replaces the entry-by-entry gathers: NMF_PARAM_SPARSE_ROW_V
   // and NMF_PARAM_WIDE_V do not apply)
   bool use_vhalf = false;
-  int sparse_row[2] = {1, nmfk::kSparseRow};  // NMF_PARAM_SPARSE_ROW_V / _U
+  int sparse_row[2] = {1, 1};                 // NMF_PARAM_SPARSE_ROW_V / _U
   bool wide[2] = {false, true};               // NMF_PARAM_WIDE_V / _U
   int waves[2] = {16, 8};                     // NMF_PARAM_WAVES_V / _U: waves per SpMM block
   // stage timing (nmf_profile)
