@@ -377,7 +377,44 @@ def compare_rules(total_iters: int = 100):
             h.close()
         out[name] = dict(ms=round(min(times), 3), E=E)
         log(f"rules: {name} {out[name]}")
-    return {"workload": f"pubmed_like_{n}x{m}", "nnz": c.nnz, "k": k, "iters": total_iters, "rules": out}
+    res = [{"workload": f"pubmed_like_{n}x{m}", "nnz": c.nnz, "k": k, "iters": total_iters, "rules": out}]
+    res.append(compare_rules_wide(total_iters))
+    return res
+
+
+def compare_rules_wide(total_iters: int = 100):
+    """Per-column ALS (Algorithm 2) against sequential ALS (Algorithm 3) with
+    one topic per block at k = 50 on the 100k x 200k corpus (t = 1000 / 2000
+    per column): 100 iterations each, the sequential run as 50 blocks of two.
+    Sequential blocks gather and store only their own column of the fixed
+    factor; every other stage still spans all k columns."""
+    import torch
+
+    import synth
+    from paper_1510_05237_amd import NMF
+
+    c, u0, _, p = synth.make_workload("plain_f32_100kx200k")
+    k = p["k"]
+    dev = torch.device("cuda:0")
+    args = [torch.from_numpy(x).to(dev) for x in (c.indptr, c.indices, c.data, u0)]
+    out = {}
+    for name in ("column", "sequential"):
+        times = []
+        for rep in range(2):
+            h = NMF(c.n, c.m, *args, t_u=p["t_u"], t_v=p["t_v"], dtype="f32", device=dev, mode="column")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "sequential":
+                h.sequential(1, total_iters // k)
+            else:
+                h.step(total_iters)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            E = h.error()
+            h.close()
+        out[name] = dict(ms=round(min(times), 3), E=E)
+        log(f"rules (k={k}): {name} {out[name]}")
+    return {"workload": f"plain_{c.n}x{c.m}", "nnz": c.nnz, "k": k, "k2": 1, "iters": total_iters, "rules": out}
 
 
 def compare_autograd(reps: int = 20):

@@ -265,23 +265,24 @@ nmf_status nmf_profile_read(nmf_handle* h, double* ms, int64_t* count, int32_t n
 /* Tuning parameters (performance only; results stay within the documented
  * tolerance and are reproducible for a given setting). */
 enum {
-  NMF_PARAM_SPARSE_ROW_V = 0, /* V half: U rows with <= this many entries are
-                                 gathered entry by entry, denser rows whole
-                                 (0..128; default 1, or 2 with a hot block:
-                                 see NMF_FLAG_NO_HOT)                       */
-  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V (default 3) */
+  NMF_PARAM_SPARSE_ROW_V = 0, /* V half through the SpMM stream (float64, or
+                                 k > 64): U rows with <= this many entries
+                                 are gathered entry by entry, denser rows
+                                 whole (0..128; default 1).  The fused
+                                 V-half kernel (float32, k <= 64) reads
+                                 every nonempty row whole and ignores it    */
+  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V (default 1) */
   NMF_PARAM_WIDE_V = 2,       /* V half SpMM step form: 0 = 64 nonzeros per
                                  step with loads only on the lanes that need
-                                 them (default without a hot block; suits
-                                 factors whose gathered rows are mostly
-                                 dense), 1 = 128 nonzeros per step with every
-                                 load issued on all lanes (suits very sparse
-                                 gathered rows; default with a hot block)   */
+                                 them (default; suits factors whose gathered
+                                 rows are mostly dense), 1 = 128 nonzeros per
+                                 step with every load issued on all lanes
+                                 (suits very sparse gathered rows); not used
+                                 by the fused V-half kernel                 */
   NMF_PARAM_WIDE_U = 3,       /* U half: the same (default 1)               */
-  NMF_PARAM_WAVES_V = 4,      /* V half SpMM: waves per block, 1/2/4/8/16
-                                 (default 16, 4 with a hot block; fewer when
-                                 the k x k inverse and the wave buffers
-                                 exceed the LDS)                            */
+  NMF_PARAM_WAVES_V = 4,      /* V half: waves per block, 1/2/4/8/16 (default
+                                 16; fewer when the k x k inverse and the
+                                 wave buffers exceed the LDS)               */
   NMF_PARAM_WAVES_U = 5,      /* U half: the same (default 8)               */
   NMF_NUM_PARAMS = 6
 };
@@ -305,8 +306,10 @@ nmf_status nmf_set_param(nmf_handle* h, int32_t param, int64_t value);
  * used).  Block 0 is Algorithm 2 on those k2 topics.  U and V keep all k
  * columns (later blocks' columns are zero until solved); each iteration
  * records E and R (Section 3.1) of the full factors in the history, R
- * against U as it stood when the iteration began.  k2 must divide k.
- * Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (NMF_MODE_WHOLE),
+ * against U as it stood when the iteration began.  k2 must divide k.  With
+ * k2 < k the block's sparse products gather and store only its k2 columns of
+ * the fixed factor (the U half skips the nonzeros whose row of V stores
+ * nothing in them).  Asynchronous.  Errors: INVALID_ARG, UNSUPPORTED (NMF_MODE_WHOLE),
  * NOT_SPD (a block's Gram matrix; sticky, reported at the next sync). */
 nmf_status nmf_sequential(nmf_handle* h, int32_t k2, int32_t iters);
 

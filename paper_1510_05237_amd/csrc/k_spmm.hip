@@ -81,11 +81,15 @@ __host__ __device__ inline size_t spmm_per_wave(int) {
          kClaims * sizeof(int32_t);
 }
 
-// LDS of one block: W (unless raw), then each wave's buffers.
+// LDS of one block: W (or, for a raw product, the row filter), then each
+// wave's buffers.
+__host__ __device__ inline size_t spmm_head_bytes(int k, bool raw, int filter_words) {
+  return raw ? (static_cast<size_t>(filter_words) * sizeof(uint32_t) + 15) / 16 * 16
+             : static_cast<size_t>(k) * k * sizeof(double);
+}
 template <typename T, int RG, bool WIDE>
-size_t spmm_lds_bytes(int k, bool raw, int waves) {
-  const size_t w = raw ? 0 : static_cast<size_t>(k) * k * sizeof(double);
-  return w + waves * spmm_per_wave<T, RG, WIDE>(k);
+size_t spmm_lds_bytes(int k, bool raw, int waves, int filter_words = 0) {
+  return spmm_head_bytes(k, raw, filter_words) + waves * spmm_per_wave<T, RG, WIDE>(k);
 }
 
 struct SpmmArgs {
@@ -108,10 +112,24 @@ struct SpmmArgs {
   const double* W;
   void* X;
   void* C;
-  int32_t k;
+  int32_t k;           // topics of the product (the column window's width)
+  int32_t c0;          // first factor column of the window (stored entries are shifted by it)
+  int32_t x_ld;        // raw output: row pitch of X and first column written
+  int32_t x_c0;
+  const uint32_t* filter;  // raw products only: bit j set when factor row j can contribute
+  int32_t filter_words;    // (null: every row); staged in LDS, other nonzeros are skipped
   int32_t* status;
   unsigned long long* gathered;  // [kGathSlots] entries gathered (null: not counted)
 };
+
+// A stored entry's topic within the column window [c0, c0 + k); an entry
+// outside it adds zero (to topic 0).
+template <typename T>
+__device__ __forceinline__ FactorEnt<T> in_window(FactorEnt<T> en, int c0, int k) {
+  const int t = static_cast<int>(en.t) - c0;
+  const bool in = static_cast<unsigned>(t) < static_cast<unsigned>(k);
+  return FactorEnt<T>{in ? en.v : T(0), in ? static_cast<uint32_t>(t) : 0u};
+}
 
 struct WaveLds {
   uint32_t* q_off;  // dense-row queue: byte offset of the factor row in F
@@ -119,6 +137,7 @@ struct WaveLds {
   void* q_a;        //                  the nonzero's value
   void* tile;       // accumulator: tile[topic * RG + row]
   int32_t* claim;   // claim table of the ordered adds (tags of earlier sub-rounds; zero at start)
+  const uint32_t* filt;  // row filter in LDS (null: none)
 };
 
 template <typename T, int RG, bool WIDE>
@@ -131,6 +150,7 @@ __device__ __forceinline__ WaveLds wave_lds(unsigned char* smem, size_t wave0, i
   w.q_r = base + Q * (sizeof(T) + sizeof(uint32_t));
   w.tile = base + Q * (sizeof(T) + sizeof(uint32_t)) + (Q + 15) / 16 * 16;
   w.claim = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(w.tile) + kTileEntries * sizeof(T));
+  w.filt = nullptr;
   return w;
 }
 
@@ -142,9 +162,12 @@ __device__ __forceinline__ size_t load_block(const SpmmArgs& a, unsigned char* s
   if (!RAW) {
     double* sW = reinterpret_cast<double*>(smem);
     for (int i = threadIdx.x; i < k * k; i += blockDim.x) sW[i] = a.W[i];
+  } else if (a.filter != nullptr) {
+    uint32_t* f = reinterpret_cast<uint32_t*>(smem);
+    for (int i = threadIdx.x; i < a.filter_words; i += blockDim.x) f[i] = a.filter[i];
   }
   __syncthreads();
-  return RAW ? 0 : static_cast<size_t>(k) * k * sizeof(double);
+  return spmm_head_bytes(k, RAW, a.filter != nullptr ? a.filter_words : 0);
 }
 
 // Wave-uniform copy of a value every lane holds (an SGPR operand).
@@ -432,13 +455,18 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
 #pragma unroll
       for (int i = 1; i < RG; ++i) r[s] += (i < nrows && p[s] >= rb[i]) ? 1 : 0;
     }
+    if (!DENSE_IN && w.filt != nullptr) {
+      // nonzeros whose factor row has nothing in the column window add nothing
+#pragma unroll
+      for (int s = 0; s < NS; ++s) valid[s] = valid[s] && ((w.filt[j[s] >> 5] >> (j[s] & 31)) & 1u) != 0u;
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       if (DENSE_IN) {
         x[s] = j[s];
         cnt[s] = valid[s] ? k : 0;
       } else if (WIDE) {
-        const int2 m = a.meta[j[s]];
+        const int2 m = a.meta[valid[s] ? j[s] : 0];
         x[s] = m.x;
         cnt[s] = valid[s] ? m.y : 0;
         av[s] = valid[s] ? av[s] : T(0);
@@ -492,7 +520,7 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
             if (act[s]) {
               int idx = e + rot[s];
               if (idx >= cnt[s]) idx -= cnt[s];
-              const FactorEnt<T> en = ents[x[s] + idx];
+              const FactorEnt<T> en = in_window(ents[x[s] + idx], a.c0, k);
               const int pos = nl + lane_rank(bal[s]);
               lt[pos] = static_cast<int32_t>(en.t);
               lw[pos] = av[s] * en.v;
@@ -518,7 +546,7 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
               act[s][d] = sparse[s] && e + d < cnt[s];
               int idx = e + d + rot[s];
               if (idx >= cnt[s]) idx -= cnt[s];
-              en[s][d] = ents[act[s][d] ? x[s] + idx : 0];
+              en[s][d] = in_window(ents[act[s][d] ? x[s] + idx : 0], a.c0, k);
             }
 #pragma unroll
           for (int s = 0; s < NS; ++s)
@@ -533,7 +561,7 @@ __device__ __forceinline__ void accumulate(const SpmmArgs& a, int64_t p0, int64_
           if (act) {
             int idx = e + rot[0];
             if (idx >= cnt[0]) idx -= cnt[0];
-            en = ents[x[0] + idx];
+            en = in_window(ents[x[0] + idx], a.c0, k);
           }
           ordered_add<T, RG>(tile, w.claim, tag, static_cast<int>(en.t), r[0], av[0] * en.v, act);
         }
@@ -575,7 +603,7 @@ __device__ __forceinline__ void epilogue(const SpmmArgs& a, const T* tile, const
         if (c < k) {
           const T x = tile[c * RG + r];
           bad |= !isfinite(x);
-          X[static_cast<int64_t>(r0 + r) * k + c] = x;
+          X[static_cast<int64_t>(r0 + r) * a.x_ld + a.x_c0 + c] = x;
         }
       }
     }
@@ -639,7 +667,8 @@ __device__ __forceinline__ void spmm_body(const SpmmArgs& a, int blk, int nblk) 
   const int wv = threadIdx.x >> 6;
   const size_t wave0 = load_block<RAW>(a, smem);
   const double* sW = reinterpret_cast<const double*>(smem);
-  const WaveLds w = wave_lds<T, RG, WIDE>(smem, wave0, k, wv);
+  WaveLds w = wave_lds<T, RG, WIDE>(smem, wave0, k, wv);
+  if (RAW && a.filter != nullptr) w.filt = reinterpret_cast<const uint32_t*>(smem);
   T* tile = static_cast<T*>(w.tile);
 #pragma unroll
   for (int i = 0; i < kClaims / 64; ++i) w.claim[lane + 64 * i] = 0;
@@ -751,8 +780,9 @@ template <typename T, int KPL, int RG, bool RAW, bool STORE_C, bool DENSE_IN, bo
 hipError_t launch(nmf_handle* h, const SpmmArgs& a, int waves_max) {
   // W (float64, k x k) is shared by the block; with large k fewer waves fit
   int waves = std::min(waves_max, kWaves);
-  while (waves > 1 && spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves) > kLdsBytes) waves /= 2;
-  const size_t lds = spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves);
+  const int fw = a.filter != nullptr ? a.filter_words : 0;
+  while (waves > 1 && spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves, fw) > kLdsBytes) waves /= 2;
+  const size_t lds = spmm_lds_bytes<T, RG, WIDE>(a.k, RAW, waves, fw);
   if (lds > kLdsBytes) return hipErrorInvalidValue;
   // one wave of blocks: as many as are resident at once (registers and LDS),
   // so no block starts late and the strided item loop stays balanced
@@ -774,7 +804,8 @@ hipError_t launch(nmf_handle* h, const SpmmArgs& a, int waves_max) {
 
 template <typename T>
 hipError_t spmm_stream(nmf_handle* h, const Plan& p, const Factor& F, const double* W, T* X, T* C,
-                       bool raw, const T* dense_in, int sparse_row, bool wide, int waves) {
+                       bool raw, const T* dense_in, int sparse_row, bool wide, int waves,
+                       const ColWindow* win = nullptr, const uint32_t* filter = nullptr, int32_t filter_words = 0) {
   SpmmArgs a{};
   a.rowptr = p.rowptr;
   a.col = p.col;
@@ -796,9 +827,27 @@ hipError_t spmm_stream(nmf_handle* h, const Plan& p, const Factor& F, const doub
   a.X = X;
   a.C = C;
   a.k = h->k;
+  a.c0 = 0;
+  a.x_ld = h->k;
+  a.x_c0 = 0;
+  if (win != nullptr) {
+    // raw product of factor columns [c0, c0 + kw): dense rows are read from
+    // column c0 on, stored entries are shifted into the window
+    if (!raw || dense_in != nullptr || win->kw < 1 || win->c0 < 0 || win->c0 + win->kw > h->k ||
+        win->x_c0 < 0 || win->x_c0 + win->kw > win->x_ld)
+      return hipErrorInvalidValue;
+    a.k = win->kw;
+    a.c0 = win->c0;
+    a.x_ld = win->x_ld;
+    a.x_c0 = win->x_c0;
+    a.F = static_cast<const T*>(F.dense) + win->c0;
+    a.F_bytes -= static_cast<uint32_t>(win->c0 * sizeof(T));
+    a.filter = filter;
+    a.filter_words = filter_words;
+  }
   a.status = h->status;
   a.gathered = dense_in ? nullptr : h->met.gathered + (&p == &h->planA ? kGathSlots : 0);
-  const bool two = h->k > 64;
+  const bool two = a.k > 64;
   const bool dense = dense_in != nullptr;
   if (p.n_hot > 0) return hipErrorInvalidValue;  // a hot block belongs to the fused V-half kernel
   if (raw) {
@@ -838,8 +887,41 @@ hipError_t spmm(nmf_handle* h, const Plan& p, const Factor& F, const double* W, 
   return vhalf_placeholder(h);
 }
 
+// Raw product over a column window of the factor (see ColWindow).
+template <typename T>
+hipError_t spmm_window(nmf_handle* h, const Plan& p, const Factor& F, T* X, const ColWindow& win, int sparse_row,
+                       const Factor& S) {
+  if constexpr (sizeof(T) == 4) {
+    if (h->use_vhalf && &p == &h->planAt) {
+      // the fused kernel reads 16-byte groups of 64-byte aligned rows
+      const int32_t ldn = dense_ld(win.kw, sizeof(float));
+      hipError_t e = narrow_rows(h, F, win.c0, win.kw, ldn, static_cast<float*>(S.dense));
+      if (e != hipSuccess) return e;
+      Factor Fn = F;
+      Fn.dense = S.dense;
+      Fn.ld = ldn;
+      return vhalf_window(h, p, Fn, X, win);
+    }
+  }
+  // the filter bitmap goes through S's values; it is used while it fits in
+  // there and in a quarter of the LDS
+  const int64_t fw = (F.rows + 31) / 32;
+  const bool filt = fw * 4 <= static_cast<int64_t>(kLdsBytes / 4) &&
+                    fw * 4 <= S.rows * static_cast<int64_t>(h->k) * static_cast<int64_t>(sizeof(T));
+  if (filt) {
+    hipError_t e = window_bits(h, F, win.c0, win.kw, static_cast<uint32_t*>(S.val));
+    if (e != hipSuccess) return e;
+  }
+  return spmm_stream<T>(h, p, F, nullptr, X, nullptr, true, nullptr, sparse_row, false, 8, &win,
+                        filt ? static_cast<const uint32_t*>(S.val) : nullptr, static_cast<int32_t>(fw));
+}
+
 template hipError_t spmm<float>(nmf_handle*, const Plan&, const Factor&, const double*, float*,
                                 float*, bool, const float*, int, bool, int);
+template hipError_t spmm_window<float>(nmf_handle*, const Plan&, const Factor&, float*, const ColWindow&, int,
+                                       const Factor&);
+template hipError_t spmm_window<double>(nmf_handle*, const Plan&, const Factor&, double*, const ColWindow&, int,
+                                        const Factor&);
 template hipError_t spmm<double>(nmf_handle*, const Plan&, const Factor&, const double*, double*,
                                  double*, bool, const double*, int, bool, int);
 

@@ -53,7 +53,12 @@ typedef int vh_i4 __attribute__((ext_vector_type(4)));
 constexpr int kVhTile = 16;                       // documents per wave tile
 constexpr int kVhTopics = 64;                     // topic slots (k <= 64)
 constexpr int kVhWavesMax = 16;
-constexpr int kVhGroup = 2;                       // streamed rows a lane reads at once
+// Streamed rows a lane reads at once: 8 / NT, so that the rows in flight
+// take the same registers whatever k (two 52-topic rows, or eight of 16).
+template <int NT>
+constexpr int vh_group() {
+  return NT == 1 ? 8 : NT == 2 ? 4 : 2;
+}
 constexpr int kVhHotChunk = 8;                    // 16-column groups of the hot block read at once
 constexpr size_t kVhLds = 160 * 1024;
 
@@ -105,7 +110,9 @@ struct VhArgs {
   int64_t rows;            // documents
   int32_t k;
   const double* W;         // k x k, or null: X receives the raw sums
-  float* X;                // [rows][k]
+  float* X;                // [rows][k]; raw sums: pitch x_ld from column x_c0
+  int32_t x_ld;
+  int32_t x_c0;
   int32_t* status;
   unsigned long long* gathered;  // [kGathSlots]: U entries of the streamed rows (null: not counted)
 };
@@ -178,13 +185,14 @@ __device__ __forceinline__ void vh_stream(const VhArgs& a, int64_t rb, int64_t r
         sl[e] = hit ? w[e].y + __popc(static_cast<uint32_t>(w[e].x) & (bit - 1u)) : (p + e < re && cur[e] < -1 ? cur[e] : -1);
       }
     }
-    // the document's 16 nonzeros in order, kVhGroup rows in flight per lane
+    // the document's 16 nonzeros in order, G rows in flight per lane
+    constexpr int G = vh_group<NT>();
 #pragma unroll 1
-    for (int jj = 0; jj < 16; jj += kVhGroup) {
-      int sj[kVhGroup];
-      float aj[kVhGroup];
+    for (int jj = 0; jj < 16; jj += G) {
+      int sj[G];
+      float aj[G];
 #pragma unroll
-      for (int u = 0; u < kVhGroup; ++u) {
+      for (int u = 0; u < G; ++u) {
         const int e = (jj + u) & 3;  // element e of the lane that read nonzero jj + u
         const int src = 16 * ((jj + u) >> 2) + m;
         const int se = e == 0 ? sl[0] : e == 1 ? sl[1] : e == 2 ? sl[2] : sl[3];
@@ -192,9 +200,9 @@ __device__ __forceinline__ void vh_stream(const VhArgs& a, int64_t rb, int64_t r
         sj[u] = __shfl(se, src, 64);
         aj[u] = __shfl(ae, src, 64);
       }
-      vh_f4 f[kVhGroup][NT];
+      vh_f4 f[G][NT];
 #pragma unroll
-      for (int u = 0; u < kVhGroup; ++u) {
+      for (int u = 0; u < G; ++u) {
         if (sj[u] >= 0) {
 #pragma unroll
           for (int tt = 0; tt < NT; ++tt)
@@ -210,7 +218,7 @@ __device__ __forceinline__ void vh_stream(const VhArgs& a, int64_t rb, int64_t r
         }
       }
 #pragma unroll
-      for (int u = 0; u < kVhGroup; ++u)
+      for (int u = 0; u < G; ++u)
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt)
           if (sj[u] != -1) acc[tt] += aj[u] * f[u][tt];
@@ -334,7 +342,7 @@ __device__ __forceinline__ void vh_body(const VhArgs& a, int blk, int nblk) {
           const int c = 16 * tt + 4 * q + i;
           if (ra < a.rows && c < k) {
             bad |= !isfinite(raw[tt][i]);
-            a.X[ra * k + c] = raw[tt][i];
+            a.X[ra * a.x_ld + a.x_c0 + c] = raw[tt][i];
           }
         }
       if (__ballot(bad) != 0 && lane == 0) atomicCAS(a.status, 0, static_cast<int32_t>(NMF_ERR_NONFINITE));
@@ -454,9 +462,48 @@ hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* den
   a.k = h->k;
   a.W = W;
   a.X = X;
+  a.x_ld = h->k;
+  a.x_c0 = 0;
   a.status = h->status;
   a.gathered = dense_in ? nullptr : h->met.gathered;
   return dense_in ? vh_dispatch<true>(h, a, waves) : vh_dispatch<false>(h, a, waves);
+}
+
+hipError_t vhalf_window(nmf_handle* h, const Plan& p, const Factor& F, float* X, const ColWindow& win) {
+  if (win.kw < 1 || win.kw > kVhTopics || win.x_c0 < 0 || win.x_c0 + win.kw > win.x_ld || F.ld < win.kw ||
+      F.ld % 16 != 0 || p.hot_ld > kMaxHot || (p.rows + kVhTile) * p.hot_ld * 4 >= (int64_t{1} << 32) ||
+      (p.rows + kVhTile) * win.x_ld * 4 >= (int64_t{1} << 32) || (p.nnz + 4) * 4 >= (int64_t{1} << 32) ||
+      F.rows * F.ld * 4 >= (int64_t{1} << 32))
+    return hipErrorInvalidValue;
+  VhArgs a{};
+  a.rowptr = p.rowptr;
+  a.col = p.col;
+  a.val = static_cast<const float*>(p.val);
+  a.stream_bytes = static_cast<uint32_t>((p.nnz + 4) * 4);
+  a.rowtab = F.rowtab;
+  a.tab_words = static_cast<int32_t>((F.rows + 31) / 32);
+  a.sdf = p.sdf;
+  a.urp = F.row_ptr;
+  a.n_u = F.rows;
+  a.F = static_cast<const float*>(F.dense);
+  a.ld = F.ld;
+  a.F_bytes = static_cast<uint32_t>(F.rows * F.ld * 4);
+  a.hot = static_cast<const float*>(p.hot);
+  a.hot_col = p.hot_col;
+  a.warm_col = p.warm_col;
+  a.n_warm = p.n_warm;
+  a.hot_ld = p.hot_ld;
+  a.n_hot = p.n_hot;
+  a.slot = F.slot;
+  a.rows = p.rows;
+  a.k = win.kw;
+  a.W = nullptr;
+  a.X = X;
+  a.x_ld = win.x_ld;
+  a.x_c0 = win.x_c0;
+  a.status = h->status;
+  a.gathered = h->met.gathered;
+  return vh_dispatch<false>(h, a, h->waves[0]);
 }
 
 // Empty launches in the places of a product's second and third kernels, so

@@ -677,6 +677,12 @@ nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
   double* W22 = h->lossG + static_cast<size_t>(k2) * k2;  // its inverse
   HIPCHK(h, densify<T>(h, h->U[h->cur_u], upre));
   HIPCHK(h, seq_save<T>(h, upre, U0b, h->n, k2));
+  // With k2 < k the products gather and store only the block's columns.  C
+  // (A V, read by the metrics) then keeps in the columns of every finished
+  // block what that block's last U half stored there (A V of those columns,
+  // which stay fixed); columns of later blocks stay zero.
+  const bool window = k2 < k;
+  if (window) HIPCHK(h, seq_setup<T>(h, C, nullptr, h->n, 0, 0));  // C <- 0
   for (int b = 0; b < eta; ++b) {
     const int k1 = b * k2;
     // U = [finished blocks | U0 | 0]
@@ -691,8 +697,14 @@ nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
       const int nxt = 1 - h->cur_u;
       Factor& Un = h->U[nxt];
       // V half: V2 = (A^T U2 - V1 U1^T U2) (U2^T U2)^-1
+      const ColWindow win{k1, k2, k, k1};
       PROF(h, -1, NMF_STAGE_SPMM_V);
-      HIPCHK(h, spmm<T>(h, h->planAt, Uo, nullptr, vpre, nullptr, true, nullptr, h->sparse_row[0]));
+      // (U[nxt] is rebuilt after the U half's product: until then its buffers
+      // hold the narrow copy of U's block columns and the row filter bits)
+      if (window)
+        HIPCHK(h, spmm_window<T>(h, h->planAt, Uo, vpre, win, h->sparse_row[0], Un));
+      else
+        HIPCHK(h, spmm<T>(h, h->planAt, Uo, nullptr, vpre, nullptr, true, nullptr, h->sparse_row[0]));
       HIPCHK(h, block_inverse(h, h->gU.G, k1, k2, Gb, W22, h->scratch_i));
       HIPCHK(h, seq_solve<T>(h, vpre, vpre, h->m, h->V, h->gU.G, W22, k1, k2));
       PROF(h, NMF_STAGE_SPMM_V, NMF_STAGE_SELECT_V);
@@ -704,7 +716,10 @@ nmf_status do_sequential(nmf_handle* h, int32_t k2, int32_t iters) {
       HIPCHK(h, seq_max(h, Uo, h->V));
       PROF(h, NMF_STAGE_GRAM_V, NMF_STAGE_SPMM_U);
       // U half: U2 = (A V2 - U1 V1^T V2) (V2^T V2)^-1
-      HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr, h->sparse_row[1]));
+      if (window)
+        HIPCHK(h, spmm_window<T>(h, h->planA, h->V, C, win, h->sparse_row[1], Un));
+      else
+        HIPCHK(h, spmm<T>(h, h->planA, h->V, nullptr, C, nullptr, true, nullptr, h->sparse_row[1]));
       HIPCHK(h, block_inverse(h, h->gV.G, k1, k2, Gb, W22, h->scratch_i));
       HIPCHK(h, seq_solve<T>(h, C, upre, h->n, Uo, h->gV.G, W22, k1, k2));
       PROF(h, NMF_STAGE_SPMM_U, NMF_STAGE_SELECT_U);

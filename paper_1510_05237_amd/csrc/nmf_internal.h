@@ -272,6 +272,16 @@ struct nmf_handle {
 
 namespace nmfk {
 
+// Column window of a raw product: factor columns [c0, c0 + kw) only, stored
+// into X (row pitch x_ld) from column x_c0 on.  Sequential ALS solves k2
+// columns at a time and gathers only those.
+struct ColWindow {
+  int32_t c0;
+  int32_t kw;
+  int32_t x_ld;
+  int32_t x_c0;
+};
+
 // Kernel launchers (one translation unit each), instantiated for float and
 // double.  All enqueue on h->stream and return hipSuccess or the launch error.
 template <typename T>
@@ -315,6 +325,22 @@ hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* den
                  int waves);
 // An empty launch record (keeps every product's launch sequence equally long).
 hipError_t vhalf_placeholder(nmf_handle* h);
+// Raw sums of the fused V-half kernel over a column window; F holds only the
+// window's columns (compact rows of pitch F.ld, as narrow_rows writes them).
+hipError_t vhalf_window(nmf_handle* h, const Plan& p, const Factor& F, float* X, const ColWindow& win);
+// Raw product over a column window: the SpMM stream skipping (row filter in
+// LDS) the nonzeros whose factor row stores nothing in the window, or the
+// fused V-half kernel on a narrow copy of the window's columns.  S is a
+// factor of F's shape whose buffers are free during the call (its values
+// take the filter bits, its dense rows the narrow copy).
+template <typename T>
+hipError_t spmm_window(nmf_handle* h, const Plan& p, const Factor& F, T* X, const ColWindow& win, int sparse_row,
+                       const Factor& S);
+// (k_seq.hip) bits[w] bit i: row 32 w + i of F stores an entry in [c0, c0 + kw).
+hipError_t window_bits(nmf_handle* h, const Factor& F, int c0, int kw, uint32_t* bits);
+// (k_seq.hip, float) out[s][0, ldn) <- columns [c0, c0 + kw) of F's compact
+// dense row s (zero past kw), for every compact row s.
+hipError_t narrow_rows(nmf_handle* h, const Factor& F, int c0, int kw, int ldn, float* out);
 
 // Sequential ALS (k_seq.hip, k_gram.hip).
 template <typename T>
