@@ -7,9 +7,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "nmf_internal.h"
@@ -251,6 +254,55 @@ nmf_status check_config(const nmf_config* c) {
   return NMF_OK;
 }
 
+// Host work of handle creation split over threads: f(part, begin, end) for
+// `parts` consecutive ranges given by bounds[0..parts] (the last range on the
+// calling thread; a range whose thread cannot be started runs inline).
+template <class F>
+void par_ranges(const std::vector<int64_t>& bounds, F&& f) {
+  const int parts = static_cast<int>(bounds.size()) - 1;
+  std::vector<std::thread> th;
+  for (int t = 0; t < parts; ++t) {
+    const int64_t b = bounds[t], e = bounds[t + 1];
+    if (t + 1 == parts) {
+      f(t, b, e);
+      break;
+    }
+    try {
+      th.emplace_back([&f, t, b, e] { f(t, b, e); });
+    } catch (...) {
+      f(t, b, e);
+    }
+  }
+  for (auto& x : th) x.join();
+}
+
+// Threads for host work over `work` elements: one per 2^20, at most the
+// hardware's, at most 32.
+int host_parts(int64_t work) {
+  const int64_t hw = std::max<unsigned>(1u, std::thread::hardware_concurrency());
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({hw, int64_t{32}, work >> 20})));
+}
+
+// [0, n) in `parts` equal ranges.
+std::vector<int64_t> even_bounds(int64_t n, int parts) {
+  std::vector<int64_t> b(parts + 1);
+  for (int t = 0; t <= parts; ++t) b[t] = n * t / parts;
+  return b;
+}
+
+// Rows [0, n) in `parts` ranges of about equal nonzero counts (row pointer rp).
+std::vector<int64_t> nnz_bounds(const int64_t* rp, int64_t n, int parts) {
+  std::vector<int64_t> b(parts + 1);
+  b[0] = 0;
+  b[parts] = n;
+  for (int t = 1; t < parts; ++t) {
+    const int64_t want = rp[n] / parts * t;
+    b[t] = std::max(b[t - 1], static_cast<int64_t>(std::lower_bound(rp, rp + n + 1, want) - rp));
+    b[t] = std::min(b[t], n);
+  }
+  return b;
+}
+
 template <typename T>
 bool values_ok(const T* v, int64_t count, bool* any_pos) {
   bool pos = false;
@@ -261,6 +313,24 @@ bool values_ok(const T* v, int64_t count, bool* any_pos) {
   }
   if (any_pos) *any_pos = pos;
   return true;
+}
+
+template <typename T>
+bool values_ok_par(const T* v, int64_t count, bool* any_pos) {
+  const int parts = host_parts(count);
+  std::vector<char> ok(parts, 1), pos(parts, 0);
+  par_ranges(even_bounds(count, parts), [&](int t, int64_t b, int64_t e) {
+    bool p = false;
+    ok[t] = values_ok(v + b, e - b, &p) ? 1 : 0;
+    pos[t] = p ? 1 : 0;
+  });
+  bool all = true, any = false;
+  for (int t = 0; t < parts; ++t) {
+    all = all && ok[t];
+    any = any || pos[t];
+  }
+  if (any_pos) *any_pos = any;
+  return all;
 }
 
 // host <- or -> device copy on the handle's stream, then wait
@@ -447,40 +517,64 @@ template <typename T>
 nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in, const void* val_in,
                      const void* u0, const void* v0) {
   const int64_t n = h->n, m = h->m, nnz = h->nnz;
-  // A on the host for validation, the transpose and the work plans
-  std::vector<int64_t> rp_h;
-  std::vector<int32_t> col_h;
-  std::vector<T> val_h;
+  // A on the host for validation, the transpose and the work plans (the
+  // loops over nonzeros run on host threads, each over a range of rows)
+  std::unique_ptr<int64_t[]> rp_h;
+  std::unique_ptr<int32_t[]> col_h;
+  std::unique_ptr<T[]> val_h;
   const int64_t* rp = rp_in;
   const int32_t* col = col_in;
   const T* val = static_cast<const T*>(val_in);
   if (is_device_ptr(rp_in)) {
-    rp_h.resize(n + 1);
-    HIPCHK(h, hipMemcpy(rp_h.data(), rp_in, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-    rp = rp_h.data();
+    rp_h.reset(new (std::nothrow) int64_t[n + 1]);
+    if (!rp_h) return fail(h, NMF_ERR_DEVICE, "out of host memory");
+    HIPCHK(h, hipMemcpy(rp_h.get(), rp_in, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    rp = rp_h.get();
   }
   if (rp[0] != 0 || rp[n] != nnz) return fail(h, NMF_ERR_INVALID_ARG, "row pointer must start at 0 and end at nnz");
   for (int64_t i = 0; i < n; ++i)
     if (rp[i + 1] < rp[i]) return fail(h, NMF_ERR_INVALID_ARG, "row pointer decreases");
   if (nnz > 0 && is_device_ptr(col_in)) {
-    col_h.resize(nnz);
-    HIPCHK(h, hipMemcpy(col_h.data(), col_in, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
-    col = col_h.data();
+    col_h.reset(new (std::nothrow) int32_t[nnz]);
+    if (!col_h) return fail(h, NMF_ERR_DEVICE, "out of host memory");
+    HIPCHK(h, hipMemcpy(col_h.get(), col_in, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+    col = col_h.get();
   }
   if (nnz > 0 && is_device_ptr(val_in)) {
-    val_h.resize(nnz);
-    HIPCHK(h, hipMemcpy(val_h.data(), val_in, nnz * sizeof(T), hipMemcpyDeviceToHost));
-    val = val_h.data();
+    val_h.reset(new (std::nothrow) T[nnz]);
+    if (!val_h) return fail(h, NMF_ERR_DEVICE, "out of host memory");
+    HIPCHK(h, hipMemcpy(val_h.get(), val_in, nnz * sizeof(T), hipMemcpyDeviceToHost));
+    val = val_h.get();
   }
-  for (int64_t i = 0; i < n; ++i) {
-    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-      const int32_t j = col[p];
-      if (j < 0 || j >= m) return fail(h, NMF_ERR_INVALID_ARG, "column index out of range");
-      if (p > rp[i] && j <= col[p - 1]) return fail(h, NMF_ERR_INVALID_ARG, "column indices not strictly increasing in a row");
+  const int parts = host_parts(nnz);
+  const std::vector<int64_t> rows_of = nnz_bounds(rp, n, parts);  // each part's rows
+  {
+    // 1: a column out of range, 2: not increasing (the first row that fails decides)
+    std::vector<int64_t> bad_row(parts, n);
+    std::vector<int> bad_kind(parts, 0);
+    par_ranges(rows_of, [&](int t, int64_t b, int64_t e) {
+      for (int64_t i = b; i < e && bad_kind[t] == 0; ++i)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+          const int32_t j = col[p];
+          if (j < 0 || j >= m) {
+            bad_kind[t] = 1;
+            bad_row[t] = i;
+            break;
+          }
+          if (p > rp[i] && j <= col[p - 1]) {
+            bad_kind[t] = 2;
+            bad_row[t] = i;
+            break;
+          }
+        }
+    });
+    for (int t = 0; t < parts; ++t) {
+      if (bad_kind[t] == 1) return fail(h, NMF_ERR_INVALID_ARG, "column index out of range");
+      if (bad_kind[t] == 2) return fail(h, NMF_ERR_INVALID_ARG, "column indices not strictly increasing in a row");
     }
   }
   bool any_pos = false;
-  if (!values_ok(val, nnz, &any_pos)) return fail(h, NMF_ERR_INVALID_INPUT, "A has a negative or non-finite value");
+  if (!values_ok_par(val, nnz, &any_pos)) return fail(h, NMF_ERR_INVALID_INPUT, "A has a negative or non-finite value");
   if (!any_pos) return fail(h, NMF_ERR_INVALID_INPUT, "||A|| = 0");
   // hot terms (float32): rows of A with at least kHotDensity * m nonzeros,
   // most nonzeros first (ties: lower row), at most kMaxHot; their entries
@@ -519,31 +613,66 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   std::vector<T> hot_block(static_cast<size_t>(n_hot ? m : 0) * hot_ld, T(0));
   // transpose of the rest (stable counting sort: rows ascending within each
   // column); for the fused V-half kernel every document's run is padded to
-  // a multiple of four with term -1, value 0
+  // a multiple of four with term -1, value 0.  Each part counts its rows'
+  // nonzeros per column; a part's entries of column j then start at the
+  // column's start plus the earlier parts' counts, so the result does not
+  // depend on the number of parts.
+  const bool skip_hot = n_hot > 0;
+  std::vector<std::vector<int32_t>> pc(parts);  // per part: its count, then its offset, per column
+  par_ranges(rows_of, [&](int t, int64_t b, int64_t e) {
+    pc[t].assign(m, 0);
+    int32_t* c = pc[t].data();
+    for (int64_t i = b; i < e; ++i)
+      if (!skip_hot || hot_of[i] < 0)
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) ++c[col[p]];
+  });
   std::vector<int64_t> cp(m + 1, 0);
-  for (int64_t i = 0; i < n; ++i)
-    if (!n_hot || hot_of[i] < 0)
-      for (int64_t p = rp[i]; p < rp[i + 1]; ++p) ++cp[col[p] + 1];
-  if (h->use_vhalf)
-    for (int64_t j = 0; j < m; ++j) cp[j + 1] = (cp[j + 1] + 3) & ~int64_t{3};
+  const int cparts = host_parts(m * static_cast<int64_t>(parts) * 4);
+  const std::vector<int64_t> cols_of = even_bounds(m, cparts);
+  par_ranges(cols_of, [&](int, int64_t b, int64_t e) {
+    for (int64_t j = b; j < e; ++j) {
+      int64_t c = 0;
+      for (int t = 0; t < parts; ++t) {
+        const int32_t x = pc[t][j];
+        pc[t][j] = static_cast<int32_t>(c);  // within-column offset of part t (a column holds < 2^29)
+        c += x;
+      }
+      cp[j + 1] = h->use_vhalf ? (c + 3) & ~int64_t{3} : c;
+    }
+  });
   for (int64_t j = 0; j < m; ++j) cp[j + 1] += cp[j];
   const int64_t nnz_t = cp[m];
-  std::vector<int32_t> crow(nnz_t, -1);
-  std::vector<T> cval(nnz_t, T(0));
-  {
-    std::vector<int64_t> cur(cp.begin(), cp.end() - 1);
-    for (int64_t i = 0; i < n; ++i) {
-      const int x = n_hot ? hot_of[i] : -1;
+  std::unique_ptr<int32_t[]> crow_p(new (std::nothrow) int32_t[nnz_t > 0 ? nnz_t : 1]);
+  std::unique_ptr<T[]> cval_p(new (std::nothrow) T[nnz_t > 0 ? nnz_t : 1]);
+  if (!crow_p || !cval_p) return fail(h, NMF_ERR_DEVICE, "out of host memory");
+  int32_t* crow = crow_p.get();
+  T* cval = cval_p.get();
+  par_ranges(rows_of, [&](int t, int64_t b, int64_t e) {
+    int32_t* off = pc[t].data();
+    for (int64_t i = b; i < e; ++i) {
+      const int x = skip_hot ? hot_of[i] : -1;
       for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+        const int32_t j = col[p];
         if (x >= 0) {
-          hot_block[static_cast<size_t>(col[p]) * hot_ld + x] = val[p];
+          hot_block[static_cast<size_t>(j) * hot_ld + x] = val[p];
           continue;
         }
-        const int64_t q = cur[col[p]]++;
+        const int64_t q = cp[j] + off[j]++;
         crow[q] = (!warm.empty() && warm_of[i] >= 0) ? -2 - warm_of[i] : static_cast<int32_t>(i);
         cval[q] = val[p];
       }
     }
+  });
+  if (h->use_vhalf) {
+    // each document's padding after its own entries (the last part's
+    // offset has reached the column's count)
+    par_ranges(cols_of, [&](int, int64_t b, int64_t e) {
+      for (int64_t j = b; j < e; ++j)
+        for (int64_t q = cp[j] + pc[parts - 1][j]; q < cp[j + 1]; ++q) {
+          crow[q] = -1;
+          cval[q] = T(0);
+        }
+    });
   }
   // rows per light item = the epilogue row group of the SpMM instantiation
   const int group = spmm_row_group(h->k);
@@ -573,10 +702,10 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   HIPCHK(h, hipMemcpy(h->planAt.rowptr, cp.data(), (m + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.col, col, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->planA.val, val, nnz * sizeof(T), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->planAt.col, crow.data(), nnz_t * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.col, crow, nnz_t * sizeof(int32_t), hipMemcpyHostToDevice));
   h->planA.nnz = nnz;
   h->planAt.nnz = nnz_t;
-  HIPCHK(h, hipMemcpy(h->planAt.val, cval.data(), nnz_t * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->planAt.val, cval, nnz_t * sizeof(T), hipMemcpyHostToDevice));
   if (n_hot && (h->planAt.hot == nullptr || h->planAt.hot_col == nullptr))
     return fail(h, NMF_ERR_WORKSPACE, "internal: no room for the hot block");
   h->planAt.n_hot = n_hot;
