@@ -271,19 +271,22 @@ enum {
                                  whole (0..128; default 1).  The fused
                                  V-half kernel (float32, k <= 64) reads
                                  every nonempty row whole and ignores it    */
-  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V (default 1) */
+  NMF_PARAM_SPARSE_ROW_U = 1, /* U half: the same for rows of V (default 1;
+                                 3 when k > 64)                             */
   NMF_PARAM_WIDE_V = 2,       /* V half SpMM step form: 0 = 64 nonzeros per
                                  step with loads only on the lanes that need
                                  them (default; suits factors whose gathered
                                  rows are mostly dense), 1 = 128 nonzeros per
                                  step with every load issued on all lanes
-                                 (suits very sparse gathered rows); not used
-                                 by the fused V-half kernel                 */
+                                 (suits very sparse gathered rows; default
+                                 when k > 64); not used by the fused V-half
+                                 kernel                                     */
   NMF_PARAM_WIDE_U = 3,       /* U half: the same (default 1)               */
   NMF_PARAM_WAVES_V = 4,      /* V half: waves per block, 1/2/4/8/16 (default
                                  16; fewer when the k x k inverse and the
                                  wave buffers exceed the LDS)               */
-  NMF_PARAM_WAVES_U = 5,      /* U half: the same (default 8)               */
+  NMF_PARAM_WAVES_U = 5,      /* U half: the same (default 8; 16 when
+                                 k > 64)                                    */
   NMF_NUM_PARAMS = 6
 };
 
