@@ -39,6 +39,7 @@ constexpr int kRowsPerBlock = kSelBlockRows;  // rows of X per hist/collect bloc
 constexpr int kPadBins = kBins + 1;
 constexpr int kFinish = 64;  // candidates ranked directly by one wave
 constexpr int kHistRows = 8;                       // rows in flight per wave in k_hist
+constexpr int kHistThreads = 1024;                 // k_hist block: 16 waves, one block per CU
 constexpr int kCollectRows = kRowsPerBlock / 4;    // k_collect: every row of a wave's share at once
 static_assert(kRowsPerBlock == 4 * kCollectRows, "k_collect: each of the 4 waves reads kCollectRows rows");
 
@@ -71,23 +72,24 @@ __device__ __forceinline__ void k_hist_body(const SelArgs& a, int blk, int nblk)
   if (*a.status != 0) return;
   const int k = a.k;
   const int nh = WHOLE ? 1 : k;
-  for (int i = threadIdx.x; i < nh * kPadBins; i += 256) h[i] = 0;
+  for (int i = threadIdx.x; i < nh * kPadBins; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const int lane = lane_id();
   const int wv = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const int64_t r_begin = static_cast<int64_t>(blk) * a.hist_rows;
   int64_t r_end = r_begin + a.hist_rows;
   if (r_end > a.rows) r_end = a.rows;
   // kHistRows rows per wave per step keep that many loads in flight
-  for (int64_t r = r_begin + wv; r < r_end; r += 4 * kHistRows) {
+  for (int64_t r = r_begin + wv; r < r_end; r += nw * kHistRows) {
 #pragma unroll
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
       if (c < k) {
         typename KO::K key[kHistRows];
 #pragma unroll
-        for (int u = 0; u < kHistRows; ++u) key[u] = r + 4 * u < r_end ? KO::key(X[(r + 4 * u) * k + c]) : 0;
+        for (int u = 0; u < kHistRows; ++u) key[u] = r + nw * u < r_end ? KO::key(X[(r + nw * u) * k + c]) : 0;
 #pragma unroll
         for (int u = 0; u < kHistRows; ++u)
           if (key[u] != 0) atomicAdd(&h[(WHOLE ? 0 : c * kPadBins) + top_digit<T>(key[u])], 1u);
@@ -95,16 +97,16 @@ __device__ __forceinline__ void k_hist_body(const SelArgs& a, int blk, int nblk)
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nh * kBins; i += 256) {
+  for (int i = threadIdx.x; i < nh * kBins; i += blockDim.x) {
     const int c = i / kBins, d = i - c * kBins;
     const uint32_t v = h[c * kPadBins + d];
     if (v) atomicAdd(&a.hist[i], v);
   }
 }
 template <typename T, int KPL, bool WHOLE>
-__global__ __launch_bounds__(256) void k_hist(SelArgs a) { k_hist_body<T, KPL, WHOLE>(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kHistThreads) void k_hist(SelArgs a) { k_hist_body<T, KPL, WHOLE>(a, blockIdx.x, gridDim.x); }
 template <typename T, int KPL, bool WHOLE>
-__global__ __launch_bounds__(256) void k_hist_b(const SelArgs* as, const BlockMap* map) {
+__global__ __launch_bounds__(kHistThreads) void k_hist_b(const SelArgs* as, const BlockMap* map) {
   const BlockMap m = map[blockIdx.x];
   const SelArgs a = as[m.prob];
   k_hist_body<T, KPL, WHOLE>(a, m.blk, m.nblk);
@@ -461,9 +463,9 @@ __global__ __launch_bounds__(1024) void k_refine_b(const SelArgs* as, const Bloc
 template <typename T, int KPL, bool WHOLE>
 hipError_t run(nmf_handle* h, SelArgs& a) {
   const unsigned blocks = static_cast<unsigned>((a.rows + kRowsPerBlock - 1) / kRowsPerBlock);
-  // two histogram blocks per compute unit the problem has: enough rows each
-  // that the flush of the block histograms stays small
-  const int64_t want = 2 * static_cast<int64_t>(h->hist_cus);
+  // one 16-wave histogram block per compute unit the problem has: enough
+  // rows each that the flush of the block histograms stays small
+  const int64_t want = static_cast<int64_t>(h->hist_cus);
   a.hist_rows = static_cast<int32_t>(std::max<int64_t>(kRowsPerBlock, (a.rows + want - 1) / want));
   const unsigned hblocks = static_cast<unsigned>((a.rows + a.hist_rows - 1) / a.hist_rows);
   const size_t hbytes = static_cast<size_t>(WHOLE ? 1 : a.k) * kPadBins * sizeof(uint32_t);
@@ -475,7 +477,8 @@ hipError_t run(nmf_handle* h, SelArgs& a) {
     one.k = 1;
     one.flat_k = a.k;
   }
-  if ((e = launch_rec(h, k_hist<T, KPL, WHOLE>, k_hist_b<T, KPL, WHOLE>, hblocks, 256, hbytes, a)) != hipSuccess)
+  if ((e = launch_rec(h, k_hist<T, KPL, WHOLE>, k_hist_b<T, KPL, WHOLE>, hblocks, kHistThreads, hbytes, a)) !=
+      hipSuccess)
     return e;
   if ((e = launch_rec(h, k_pick, k_pick_b, (one.k + 3) / 4, 256, 0, one)) != hipSuccess) return e;
   if ((e = launch_rec(h, k_collect<T, KPL, WHOLE>, k_collect_b<T, KPL, WHOLE>, blocks, 256, stage, a)) != hipSuccess)
