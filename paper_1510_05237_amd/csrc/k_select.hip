@@ -217,12 +217,14 @@ __device__ __forceinline__ void k_collect_body(const SelArgs& a, int blk, int nb
       }
       keep_bits[q] = __ballot(keep);
     }
-    // the wave owns row r: write its keep-mask words directly
+    // the wave owns row r: its keep-mask words (zero until now: the repack
+    // clears them after use) are plain stores; the threshold bin's picks are
+    // added by k_refine after this kernel
     if (lane < a.mw) {
       const int q = lane >> 1;
       const uint64_t b = keep_bits[q < KPL ? q : 0];
       const uint32_t word = (lane & 1) ? static_cast<uint32_t>(b >> 32) : static_cast<uint32_t>(b);
-      if (word) atomicOr(&a.mask[r * a.mw + lane], word);
+      if (word) a.mask[r * a.mw + lane] = word;
     }
   }
 #pragma unroll
