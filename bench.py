@@ -246,6 +246,15 @@ def batch_bench(problems, iters: int, warmup: int):
             raise RuntimeError(f"batch {how}: member status {st[st != 0][:4]}")
     equal = all(np.array_equal(errs["loop"], e) for e in errs.values())
     nnz = sum(int(p["indptr"][-1]) for p in problems)
+    # algorithmic bytes of one batch iteration's two products, every problem
+    # at its factors' final storage (the same count as the single-problem
+    # roofline), over the fused and graph-captured iteration time
+    prod_bytes = 0.0
+    for i, p in enumerate(problems):
+        _, _, nu, nv = b.problem(i).history()
+        prod_bytes += spmm_algorithmic_bytes(p["m"], p["n"], int(p["indptr"][-1]), float(nu[-1]), p["k"], 4, False)
+        prod_bytes += spmm_algorithmic_bytes(p["n"], p["m"], int(p["indptr"][-1]), float(nv[-1]), p["k"], 4, True)
+    gbs = prod_bytes / (res["fused_graph"] * 1e-3) / 1e9
     b.close()
     del u0d
     torch.cuda.empty_cache()
@@ -259,6 +268,10 @@ def batch_bench(problems, iters: int, warmup: int):
         "problem_iters_per_s": {h: round(len(problems) * 1e3 / v, 1) for h, v in res.items()},
         "speedup_vs_loop": {h: round(res["loop"] / v, 2) for h, v in res.items()},
         "equal_accuracy": bool(equal),
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(gbs / 8000.0, 4), "algorithmic_bytes_per_iteration": prod_bytes,
+                     "note": "both products' algorithmic bytes of every problem over the whole fused, "
+                             "graph-captured batch iteration"},
         "tuned_spmm": tuned,
         "E_mean": float(np.mean(errs["fused_graph"])),
     }

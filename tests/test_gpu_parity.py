@@ -318,6 +318,34 @@ def test_k128_fits_lds(dtype):
     prob.close()
 
 
+def test_k128_fp32_half_steps_vs_oracle():
+    """k = 128 in float32 (two topics per lane, the stream kernel in both
+    halves, the k > 64 defaults): three iterations half-step by half-step
+    from the GPU's own state, V against the oracle's V half from the
+    previous U and U against the oracle's U half from the GPU's V (whole
+    matrix, every column and every kept entry within 1e-4; supports equal
+    but for near-ties)."""
+    c = synth.make_corpus(700, 500, seed=42, alpha=1.1, nnz=30000, dtype="f32")
+    u0, _ = synth.make_init(700, 500, 128, seed=42, dtype="f32")
+    _say(f"f32 700x500 nnz={c.nnz} k=128, 3 iterations half-step by half-step")
+    A = c.scipy()
+    prob = _problem(c, u0, 128, 40, 30, "f32")
+    prev = u0.astype(np.float64)
+    for it in range(3):
+        prob.step(1)
+        U, V = prob.factors()
+        _, iv = oracle.half_step(sp.csr_matrix(A.T), prev, 30)
+        Vo = oracle.topt_per_column(oracle.clamp(iv["X_pre"]), 30)
+        dv = compare_factor(V, Vo, iv["X_pre"], 1e-4)
+        _, iu = oracle.half_step(A, V.astype(np.float64), 40)
+        Uo = oracle.topt_per_column(oracle.clamp(iu["X_pre"]), 40)
+        du = compare_factor(U, Uo, iu["X_pre"], 1e-4)
+        _say(f"  iteration {it + 1}: V {dv} | U {du}")
+        assert dv.ok(1e-4) and du.ok(1e-4), (it, str(dv), dv.elem_at, str(du), du.elem_at)
+        prev = U.astype(np.float64)
+    prob.close()
+
+
 def test_power_of_two_scaling_gpu():
     """Scaling A by 2^p leaves U and every support bit-identical and scales V
     by exactly 2^p on the GPU too (rounding commutes with the scaling)."""
