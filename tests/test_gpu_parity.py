@@ -499,7 +499,8 @@ def test_hot_block_split(k):
     """float32, k <= 64: the densest terms' nonzeros are multiplied as a
     dense block on the matrix cores instead of streamed.  V_pre of a V half,
     plain iterations and the loss gradient agree with the unsplit path
-    (NMF_FLAG_NO_HOT) to float32 rounding, and V_pre with the oracle."""
+    (NMF_FLAG_NO_HOT) to float32 rounding; V_pre, two further iterations
+    (half-step by half-step) and the gradient agree with the oracle."""
     import torch
     from paper_1510_05237_amd import NMF_FLAG_NO_HOT, NMFLoss
 
@@ -528,6 +529,20 @@ def test_hot_block_split(k):
     Ea, _, _, _ = a.history()
     Eb, _, _, _ = b.history()
     np.testing.assert_allclose(Ea, Eb, rtol=1e-4)
+    # two more iterations of the hot path, half-step by half-step against
+    # the oracle from the GPU's own state (every column and kept entry)
+    A = c.scipy()
+    prev = a.factors()[0].astype(np.float64)
+    for it in range(2):
+        a.step(1)
+        U, V = a.factors()
+        _, iv = oracle.half_step(sp.csr_matrix(A.T), prev, 80)
+        dv = compare_factor(V, oracle.topt_per_column(oracle.clamp(iv["X_pre"]), 80), iv["X_pre"], 1e-4)
+        _, iu = oracle.half_step(A, V.astype(np.float64), 60)
+        du = compare_factor(U, oracle.topt_per_column(oracle.clamp(iu["X_pre"]), 60), iu["X_pre"], 1e-4)
+        _say(f"  hot path iteration {it + 1} vs oracle: V {dv} | U {du}")
+        assert dv.ok(1e-4) and du.ok(1e-4), (it, str(dv), dv.elem_at, str(du), du.elem_at)
+        prev = U.astype(np.float64)
     # the loss gradient through the hot block (dense U input)
     rng = np.random.Generator(np.random.PCG64(5))
     U = synth.sparse_factor_init(n, k, 60, rng=rng, dtype="f32")
@@ -539,5 +554,8 @@ def test_hot_block_split(k):
         NMFLoss.apply(p, Ut, Vt).backward()
         grads.append((Ut.grad.cpu().numpy(), Vt.grad.cpu().numpy()))
     assert rel_fro(grads[0][0], grads[1][0]) < 1e-5 and rel_fro(grads[0][1], grads[1][1]) < 1e-5
+    # and the hot path's gradient against the oracle's
+    gU, gV = oracle.loss_grad(c.scipy(), U.astype(np.float64), V.astype(np.float64))
+    assert rel_fro(grads[0][0], gU) < 1e-4 and rel_fro(grads[0][1], gV) < 1e-4
     a.close()
     b.close()
