@@ -403,6 +403,20 @@ __global__ __launch_bounds__(64 * kVhWavesMax) void k_vhalf_b(const VhArgs* as, 
   vh_body<NT, DENSE_IN>(a, mp.blk, mp.nblk);
 }
 
+// The batched form for every topic-tile count: one launch serves all the
+// problems of a batch, each block running its problem's instantiation
+// (the LDS of the launch is the largest any problem needs).
+__global__ __launch_bounds__(64 * kVhWavesMax) void k_vhalf_any_b(const VhArgs* as, const BlockMap* map) {
+  const BlockMap mp = map[blockIdx.x];
+  const VhArgs a = as[mp.prob];
+  switch ((a.k + 15) / 16) {
+    case 1: vh_body<1, false>(a, mp.blk, mp.nblk); break;
+    case 2: vh_body<2, false>(a, mp.blk, mp.nblk); break;
+    case 3: vh_body<3, false>(a, mp.blk, mp.nblk); break;
+    default: vh_body<4, false>(a, mp.blk, mp.nblk); break;
+  }
+}
+
 template <int NT, bool DENSE_IN>
 hipError_t vh_launch(nmf_handle* h, const VhArgs& a, int waves_max) {
   const size_t blk_lds = vh_block_lds(a.n_hot > 0 ? a.hot_ld : 0, a.k, a.W != nullptr,
@@ -417,7 +431,8 @@ hipError_t vh_launch(nmf_handle* h, const VhArgs& a, int waves_max) {
   const int64_t tiles = (a.rows + kVhTile - 1) / kVhTile;
   const unsigned blocks =
       static_cast<unsigned>(std::min<int64_t>((tiles + waves - 1) / waves, static_cast<int64_t>(h->num_cus) * per_cu));
-  return launch_rec(h, k_vhalf<NT, DENSE_IN>, k_vhalf_b<NT, DENSE_IN>, blocks, 64u * waves, lds, a);
+  return launch_rec(h, k_vhalf<NT, DENSE_IN>, DENSE_IN ? k_vhalf_b<NT, DENSE_IN> : k_vhalf_any_b, blocks, 64u * waves,
+                    lds, a);
 }
 
 template <bool DENSE_IN>
