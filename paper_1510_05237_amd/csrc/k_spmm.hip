@@ -16,11 +16,15 @@
 //  * lanes = nonzeros: coalesced loads of (col, a) and one 8-byte gather of
 //    the factor row's metadata {where, how many entries};
 //  * factor rows with at most `sparse_row` entries are gathered entry by entry
-//    (one {value, topic} load per entry, lanes still = nonzeros) and each
-//    product is added into the accumulator at (row, topic) in a fixed order:
-//    where several lanes of one instruction add to the same place, the
-//    lowest lane goes first (found with an integer atomicMin on a small
-//    claim table; no floating-point atomics);
+//    (one {value, topic} load per entry, lanes still = nonzeros); no
+//    floating-point atomics add their products: an item of one row appends
+//    them to a list in a fixed order that is summed with lanes = topics (see
+//    scan_list), an item of several rows adds each at (row, topic) of the
+//    accumulator in claim sub-rounds where the lowest lane goes first (see
+//    ordered_add);
+//  * a raw product may cover a window of the factor's columns (sequential
+//    ALS), with a bitmap in LDS of the factor rows that store anything in it:
+//    the other nonzeros are skipped before their metadata gather;
 //  * denser factor rows are queued in row order and then read whole from the
 //    compact dense copy of the factor, lanes = topics, eight rows in flight;
 //    the running sums for the current row stay in registers and go to the
