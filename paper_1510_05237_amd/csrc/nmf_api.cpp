@@ -618,9 +618,10 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   // column's start plus the earlier parts' counts, so the result does not
   // depend on the number of parts.
   const bool skip_hot = n_hot > 0;
-  std::vector<std::vector<int32_t>> pc(parts);  // per part: its count, then its offset, per column
+  // per part: its count, then its offset, per column (allocated here: the
+  // worker threads allocate nothing)
+  std::vector<std::vector<int32_t>> pc(parts, std::vector<int32_t>(m, 0));
   par_ranges(rows_of, [&](int t, int64_t b, int64_t e) {
-    pc[t].assign(m, 0);
     int32_t* c = pc[t].data();
     for (int64_t i = b; i < e; ++i)
       if (!skip_hot || hot_of[i] < 0)
@@ -969,8 +970,14 @@ nmf_status create_impl(const nmf_config* cfg, const int64_t* a_rowptr, const int
     h->waves[1] = 16;
   }
   carve(h, h->ws, *cfg, nnz, plan_bounds(cfg->n, nnz), plan_bounds(cfg->m, nnz));
-  s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)
-                  : do_create<float>(h, a_rowptr, a_col, a_val, u0, v0);
+  try {
+    s = h->elt == 8 ? do_create<double>(h, a_rowptr, a_col, a_val, u0, v0)
+                    : do_create<float>(h, a_rowptr, a_col, a_val, u0, v0);
+  } catch (const std::bad_alloc&) {
+    s = fail(h, NMF_ERR_DEVICE, "out of host memory");
+  } catch (...) {
+    s = fail(h, NMF_ERR_DEVICE, "host error while creating the handle");
+  }
   if (s != NMF_OK) {
     g_create_error = h->last_error;
     (void)hipStreamSynchronize(h->stream);
