@@ -1747,7 +1747,7 @@ nmf_status nmf_batch_workspace_size(int32_t count, const nmf_config* cfgs, const
   return NMF_OK;
 }
 
-nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t* const* a_rowptr,
+static nmf_status nmf_batch_create_impl(int32_t count, const nmf_config* cfgs, const int64_t* const* a_rowptr,
                             const int32_t* const* a_col, const void* const* a_val, const int64_t* nnz,
                             const void* const* u0, void* workspace, size_t ws_bytes, void* hip_stream,
                             nmf_batch** out) {
@@ -1811,7 +1811,7 @@ nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t
   return NMF_OK;
 }
 
-nmf_status nmf_batch_step(nmf_batch* b, int32_t iters, int32_t how) {
+static nmf_status nmf_batch_step_impl(nmf_batch* b, int32_t iters, int32_t how) {
   if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
   if (iters < 0) return batch_fail(b, NMF_ERR_INVALID_ARG, "iters < 0");
   if (how < NMF_BATCH_LOOP || how > NMF_BATCH_FUSED_GRAPH) return batch_fail(b, NMF_ERR_INVALID_ARG, "unknown mode");
@@ -1852,7 +1852,7 @@ nmf_status nmf_batch_errors(nmf_batch* b, double* E, int32_t* status) {
   return first;
 }
 
-nmf_status nmf_batch_set_param(nmf_batch* b, int32_t i, int32_t param, int64_t value) {
+static nmf_status nmf_batch_set_param_impl(nmf_batch* b, int32_t i, int32_t param, int64_t value) {
   if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
   if (i < -1 || i >= static_cast<int32_t>(b->h.size())) return batch_fail(b, NMF_ERR_INVALID_ARG, "no such problem");
   BCHK(b, hipStreamSynchronize(b->stream));
@@ -1864,7 +1864,7 @@ nmf_status nmf_batch_set_param(nmf_batch* b, int32_t i, int32_t param, int64_t v
   return rebuild_plans(b);
 }
 
-nmf_status nmf_batch_tune(nmf_batch* b, int32_t iters, int32_t* chosen) {
+static nmf_status nmf_batch_tune_impl(nmf_batch* b, int32_t iters, int32_t* chosen) {
   if (b == nullptr) return batch_fail(nullptr, NMF_ERR_INVALID_ARG, "batch is NULL");
   if (iters < 1) return batch_fail(b, NMF_ERR_INVALID_ARG, "iters < 1");
   int slot;
@@ -1941,6 +1941,53 @@ void nmf_batch_destroy(nmf_batch* b) {
   for (nmf_handle* h : b->h) nmf_destroy(h);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
+}
+
+// The batch entry points that build host containers: a host allocation
+// failure (or any other host exception) becomes an error status instead of
+// escaping the C ABI.
+nmf_status nmf_batch_create(int32_t count, const nmf_config* cfgs, const int64_t* const* a_rowptr,
+                            const int32_t* const* a_col, const void* const* a_val, const int64_t* nnz,
+                            const void* const* u0, void* workspace, size_t ws_bytes, void* hip_stream,
+                            nmf_batch** out) {
+  try {
+    return nmf_batch_create_impl(count, cfgs, a_rowptr, a_col, a_val, nnz, u0, workspace, ws_bytes, hip_stream,
+                                 out);
+  } catch (const std::bad_alloc&) {
+    return batch_fail(nullptr, NMF_ERR_DEVICE, "out of host memory");
+  } catch (...) {
+    return batch_fail(nullptr, NMF_ERR_DEVICE, "host error while creating the batch");
+  }
+}
+
+nmf_status nmf_batch_step(nmf_batch* b, int32_t iters, int32_t how) {
+  try {
+    return nmf_batch_step_impl(b, iters, how);
+  } catch (const std::bad_alloc&) {
+    return batch_fail(b, NMF_ERR_DEVICE, "out of host memory");
+  } catch (...) {
+    return batch_fail(b, NMF_ERR_DEVICE, "host error in a batch step");
+  }
+}
+
+nmf_status nmf_batch_set_param(nmf_batch* b, int32_t i, int32_t param, int64_t value) {
+  try {
+    return nmf_batch_set_param_impl(b, i, param, value);
+  } catch (const std::bad_alloc&) {
+    return batch_fail(b, NMF_ERR_DEVICE, "out of host memory");
+  } catch (...) {
+    return batch_fail(b, NMF_ERR_DEVICE, "host error while setting a parameter");
+  }
+}
+
+nmf_status nmf_batch_tune(nmf_batch* b, int32_t iters, int32_t* chosen) {
+  try {
+    return nmf_batch_tune_impl(b, iters, chosen);
+  } catch (const std::bad_alloc&) {
+    return batch_fail(b, NMF_ERR_DEVICE, "out of host memory");
+  } catch (...) {
+    return batch_fail(b, NMF_ERR_DEVICE, "host error while tuning");
+  }
 }
 
 }  // extern "C"
