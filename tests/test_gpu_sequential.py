@@ -55,6 +55,30 @@ def test_sequential_fp64_trajectory(k2, iters):
     prob.close()
 
 
+@pytest.mark.parametrize("k,k2", [(80, 16), (80, 40)])
+def test_sequential_fp64_wide_k(k, k2):
+    """k > 64 (two topics per lane in the full-width kernels) with blocks of
+    k2 <= 64 topics, whose products run over a column window one topic per
+    lane: factors, E and R against the oracle."""
+    NMF, _ = _lib()
+    c = synth.make_corpus(1500, 1100, seed=51, alpha=1.1, nnz=40000, dtype="f64")
+    u0, _ = synth.make_init(1500, 1100, k, seed=51, dtype="f64")
+    A = c.scipy()
+    eta, iters, t_u, t_v = k // k2, 2, 60, 45
+    _say(f"fp64 sequential 1500x1100 k={k} k2={k2} eta={eta} iters/block={iters}")
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=t_u, t_v=t_v, dtype="f64")
+    prob.sequential(k2, iters)
+    U, V = prob.factors()
+    st = oracle.sequential_als(A, u0[:, :k2], t_u, t_v, k2=k2, eta=eta, iters=iters)
+    assert rel_fro(U, st.U) < 1e-9 and rel_fro(V, st.V) < 1e-9
+    np.testing.assert_array_equal(U != 0, st.U != 0)
+    np.testing.assert_array_equal(V != 0, st.V != 0)
+    E, R, _, _ = prob.history()
+    np.testing.assert_allclose(E, st.E, rtol=1e-9)
+    np.testing.assert_allclose(R, st.R, rtol=1e-8)
+    prob.close()
+
+
 def test_sequential_then_algorithm_2():
     """After a sequential run the handle continues with Algorithm 2 from the
     factors it found (the full inverse Gram is rebuilt first)."""
