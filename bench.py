@@ -430,6 +430,46 @@ def compare_rules_wide(total_iters: int = 100):
     return {"workload": f"plain_{c.n}x{c.m}", "nnz": c.nnz, "k": k, "k2": 1, "iters": total_iters, "rules": out}
 
 
+def scale_rate(warm: int = 2, iters: int = 3):
+    """The scale configuration (1M terms x 5M documents, 200 terms per
+    document, 1B nonzeros, k = 100, t = 5000 / 20000 per column, FP32 with
+    FP64 solves; corpus drawn on the GPU by synth.scale): handle creation
+    time, then `iters` iterations after `warm` untimed ones, wall time per
+    iteration and the event-timed stage breakdown of the same iterations."""
+    import torch
+
+    from paper_1510_05237_amd import NMF
+    from synth.scale import make_scale_corpus, make_scale_init
+
+    n, m, d, k, t_u, t_v = 1_000_000, 5_000_000, 200, 100, 5000, 20000
+    dev = torch.device("cuda:0")
+    c = make_scale_corpus(n, m, d, seed=3, alpha=1.05, device=dev)
+    u0 = make_scale_init(n, k, seed=3, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = NMF(n, m, c.indptr, c.indices, c.data, u0, t_u=t_u, t_v=t_v, dtype="f32", device=dev)
+    torch.cuda.synchronize()
+    created = time.perf_counter() - t0
+    del c
+    log(f"scale: handle created in {created:.1f}s (workspace {prob.ws_bytes / 2**30:.1f} GiB)")
+    prob.step(warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.step(iters)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / iters
+    prob.profile(True)
+    prob.step(iters)
+    torch.cuda.synchronize()
+    pr = prob.profile_read()
+    prob.profile(False)
+    E = prob.error()
+    prob.close()
+    return {"workload": f"scale_{n}x{m}_k{k}", "nnz": m * d, "create_s": round(created, 2),
+            "ms_per_iteration": round(ms, 2), "it_per_s": round(1e3 / ms, 2),
+            "stage_ms": {st: round(v[0] / max(v[1], 1), 3) for st, v in pr.items()}, "E": E}
+
+
 def compare_autograd(reps: int = 20):
     """The autograd loss on the 100k x 200k matrix with sparse U, V (t = 1000
     and 2000 per column): NMFLoss forward + backward against the same two
@@ -520,6 +560,10 @@ def main():
                     help="print the clustering-accuracy sweep (Eq. (acc) against t) and exit")
     ap.add_argument("--compare-rules", action="store_true",
                     help="print the whole-matrix / per-column / sequential timing comparison and exit")
+    ap.add_argument("--compare-rules-k50", action="store_true",
+                    help="print only the k = 50 per-column / sequential comparison and exit")
+    ap.add_argument("--scale", action="store_true",
+                    help="print the 1M x 5M (1B nonzeros, k = 100) rate and stage breakdown and exit")
     ap.add_argument("--compare-autograd", action="store_true",
                     help="print the autograd-loss timing against direct ABI calls and exit")
     ap.add_argument("--batch-only", action="store_true",
@@ -538,6 +582,12 @@ def main():
         return
     if args.compare_rules:
         print(json.dumps({"rules_comparison": compare_rules()}), flush=True)
+        return
+    if args.compare_rules_k50:
+        print(json.dumps({"rules_comparison": [compare_rules_wide()]}), flush=True)
+        return
+    if args.scale:
+        print(json.dumps({"scale": scale_rate()}), flush=True)
         return
     if args.sweep_accuracy:
         print(json.dumps({"accuracy_sweep": sweep_accuracy()}), flush=True)
