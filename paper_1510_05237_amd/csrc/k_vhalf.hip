@@ -79,7 +79,7 @@ __device__ __forceinline__ float vh_load1(__amdgpu_buffer_rsrc_t r, uint32_t off
 __device__ __forceinline__ int vh_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Four consecutive topics of a factor row at a byte offset: one 16-byte load
-// from the compact dense copy (rows 64-byte aligned); four 4-byte loads from
+// from the compact dense copy (rows 16-byte aligned); four 4-byte loads from
 // a caller's dense input, whose rows are only 4-byte aligned.
 template <bool DENSE_IN>
 __device__ __forceinline__ vh_f4 vh_row4(__amdgpu_buffer_rsrc_t r, uint32_t off) {

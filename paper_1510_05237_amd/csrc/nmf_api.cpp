@@ -181,7 +181,9 @@ size_t carve(nmf_handle* h, char* base, const nmf_config& c, int64_t nnz, const 
     f.val = cv.take<char>(rows * k * elt);
     f.slot = cv.take<int32_t>(rows);
     f.rowid = cv.take<int32_t>(rows);
-    f.ld = dense_ld(k, elt);
+    // U's copy, when the fused V-half kernel reads it, needs only 16-byte
+    // groups: k rounded up to 4 (a smaller working set for the L2s)
+    f.ld = (vhalf_fits(elt, n, m, k, nnz) && &f != &h->V) ? (k + 3) / 4 * 4 : dense_ld(k, elt);
     f.dense = cv.take<char>(rows * f.ld * elt);
     f.counts = cv.take<int32_t>(4);
     f.meta = cv.take<int2>(rows);

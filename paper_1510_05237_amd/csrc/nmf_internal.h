@@ -99,8 +99,8 @@ inline bool vhalf_fits(size_t elt, int64_t n, int64_t m, int k, int64_t nnz) {
 }
 
 // A factor as stored (row-compressed sparse) plus the gather cache the SpMM
-// reads: every nonempty row expanded to a dense row (64-byte aligned rows, so
-// one lane can load four floats or two doubles of a row at once).
+// reads: every nonempty row expanded to a dense row (rows 16-byte aligned at
+// least, so one lane can load four floats or two doubles of a row at once).
 struct Factor {
   int64_t rows = 0;
   int32_t* row_ptr = nullptr;  // [rows + 1]
@@ -109,7 +109,8 @@ struct Factor {
   int32_t* slot = nullptr;     // [rows]: -1 empty, else compact row index
   int32_t* rowid = nullptr;    // [rows]: compact row index -> row
   void* dense = nullptr;       // [rows][ld] T: compact dense rows 0..R-1, zero past k
-  int32_t ld = 0;              // row pitch of `dense`: k rounded up to 64 bytes
+  int32_t ld = 0;              // row pitch of `dense`: k rounded up to 64 bytes (dense_ld), or
+                               // to 4 for U when the fused V-half kernel serves the problem
   int32_t* counts = nullptr;   // device [0] = nnz, [1] = R (nonempty rows)
   // SpMM gather metadata: per row {compact dense row (rows with more entries
   // than the gathering SpMM's threshold) or first stored entry, entry count};
