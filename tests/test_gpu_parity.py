@@ -346,6 +346,27 @@ def test_k128_fp32_half_steps_vs_oracle():
     prob.close()
 
 
+@pytest.mark.parametrize("k,dtype,expect", [
+    # (wide_v, sparse_row_u, waves_u): float32 k <= 64 (fused V half), float64, k > 64
+    (50, "f32", (0, 1, 8)), (50, "f64", (0, 1, 8)), (80, "f32", (1, 3, 16)), (80, "f64", (1, 3, 16))])
+def test_parameter_defaults(k, dtype, expect):
+    """The SpMM parameters a handle starts with depend on its shape as the
+    header states: for k > 64 the V half's stream takes the wide step and the
+    U half gathers rows of up to three entries entry by entry in 16-wave
+    blocks; otherwise the narrow V step, rows of one entry and 8 waves."""
+    from paper_1510_05237_amd import (NMF_PARAM_SPARSE_ROW_U, NMF_PARAM_SPARSE_ROW_V, NMF_PARAM_WAVES_U,
+                                      NMF_PARAM_WAVES_V, NMF_PARAM_WIDE_U, NMF_PARAM_WIDE_V)
+    c = synth.make_corpus(600, 500, seed=61, alpha=1.1, nnz=12000, dtype=dtype)
+    u0, _ = synth.make_init(600, 500, k, seed=61, dtype=dtype)
+    _say(f"parameter defaults {dtype} k={k}")
+    prob = _problem(c, u0, k, 30, 30, dtype)
+    got = (prob.get_param(NMF_PARAM_WIDE_V), prob.get_param(NMF_PARAM_SPARSE_ROW_U), prob.get_param(NMF_PARAM_WAVES_U))
+    assert got == expect, got
+    assert prob.get_param(NMF_PARAM_SPARSE_ROW_V) == 1 and prob.get_param(NMF_PARAM_WIDE_U) == 1
+    assert prob.get_param(NMF_PARAM_WAVES_V) == 16
+    prob.close()
+
+
 def test_power_of_two_scaling_gpu():
     """Scaling A by 2^p leaves U and every support bit-identical and scales V
     by exactly 2^p on the GPU too (rounding commutes with the scaling)."""
