@@ -148,6 +148,7 @@ def test_fp32_100kx200k_loss_and_gradient(t_u, t_v):
     prob.close()
 
 
+@pytest.mark.timeout(600)  # 50 full-size oracle iterations on the host: about two minutes
 def test_fp32_100kx200k_free_running_trajectory():
     """The headline workload (100k x 200k, 20M nnz, k = 50, t_u = 1000,
     t_v = 2000) run free on the GPU for its 50 iterations beside the FP64 oracle
