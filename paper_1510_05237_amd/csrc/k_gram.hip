@@ -371,36 +371,49 @@ __global__ __launch_bounds__(kFactorThreads) void k_gram_factor_b(const GramArgs
 // the same matrix as sweeping P's pivots one at a time, and its pivots are
 // the same Schur complement diagonals (checked the same way).  Wave w owns
 // rows 4w..4w+3 of the 64 x 64 register matrix, lane = column.  The wave
-// that owns the next block reads its 4 x 4 diagonal block across lanes,
+// that owns the next block reads its 4 x 4 diagonal block (through LDS),
 // sweeps it in registers (b = -B^-1), forms T = B^-1 a_P. for every column
 // and publishes a_P. and T; by symmetry (a_iP = a_Pi) every other wave's
 // update needs only these, so a block of four pivots takes one barrier.
 constexpr int kPiv = 4;
 
-__device__ __forceinline__ double lane_read(double v, int src) {
-  const uint64_t b = static_cast<uint64_t>(__double_as_longlong(v));
-  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b)), src));
-  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(b >> 32)), src));
-  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+// 1 / d for a pivot d > 0: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - d r), each of which squares the
+// relative error; a pivot below 2^-1000 (where the estimate may flush) takes
+// the IEEE division.  d is the same in every lane, so the branch is uniform.
+__device__ __forceinline__ double pivot_recip(double d) {
+  if (!(d >= 0x1p-1000)) return 1.0 / d;
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
 }
 
 // The owner wave of block j: sweep its diagonal block (rows/columns
 // p0..p0+bs-1) into b = -B^-1, then T[q] = (B^-1 a_P.)[q][c] for its lane's
-// column; publishes a_P. (its rows as they stand) and T.  Returns false on a
-// pivot that is not positive.
+// column; publishes a_P. (its rows as they stand) and T.  The diagonal block
+// reaches every lane through `dg` (written by its own lanes, read back by the
+// same wave, whose LDS accesses complete in order).  Returns false on a pivot
+// that is not positive.
 __device__ __forceinline__ bool block_pivot(const double (&e)[kPiv], int p0, int bs, double (&b)[kPiv][kPiv],
-                                            double (&t)[kPiv], double (*rs)[kPiv], double (*ts)[kPiv], int c) {
+                                            double (&t)[kPiv], double (*rs)[kPiv], double (*ts)[kPiv],
+                                            double (*dg)[kPiv], int c) {
+  if (c >= p0 && c < p0 + kPiv)
+#pragma unroll
+    for (int q = 0; q < kPiv; ++q) dg[q][c - p0] = e[q];
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int q = 0; q < kPiv; ++q)
 #pragma unroll
-    for (int l = 0; l < kPiv; ++l) b[q][l] = lane_read(e[q], p0 + l);
+    for (int l = 0; l < kPiv; ++l) b[q][l] = dg[q][l];
   bool ok = true;
 #pragma unroll
   for (int p = 0; p < kPiv; ++p) {
     if (p >= bs) break;
     const double d = b[p][p];
     ok = ok && d > 0.0;
-    const double ip = 1.0 / d;
+    const double ip = pivot_recip(d);
     double rp[kPiv];
 #pragma unroll
     for (int l = 0; l < kPiv; ++l) rp[l] = b[p][l] * ip;
@@ -439,6 +452,7 @@ __device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, in
   static_assert(KM / kPiv * 64 == kFactorThreads, "one wave per block of four rows");
   __shared__ double rs[2][KM][kPiv];  // rs[.][c][l] = a_{p0+l, c}
   __shared__ double ts[2][KM][kPiv];  // ts[.][c][q] = (B^-1 a_P.)[q][c]
+  __shared__ double dg[kPiv][kPiv];   // the owner's diagonal block
   __shared__ int s_dead[KM];
   __shared__ int s_nd, s_bad;
   if (*g.status != 0) return;
@@ -472,7 +486,7 @@ __device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, in
   }
   const int nbk = (k + kPiv - 1) / kPiv;
   double b[kPiv][kPiv], t[kPiv];
-  if (wv == 0 && !block_pivot(e, 0, k < kPiv ? k : kPiv, b, t, rs[0], ts[0], c) && c == 0) s_bad = 1;
+  if (wv == 0 && !block_pivot(e, 0, k < kPiv ? k : kPiv, b, t, rs[0], ts[0], dg, c) && c == 0) s_bad = 1;
   __syncthreads();
   for (int j = 0; j < nbk; ++j) {
     const int buf = j & 1;
@@ -510,7 +524,7 @@ __device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, in
     }
     if (wv == j + 1 && j + 1 < nbk) {
       const int n0 = p0 + kPiv;
-      if (!block_pivot(e, n0, k - n0 < kPiv ? k - n0 : kPiv, b, t, rs[buf ^ 1], ts[buf ^ 1], c) && c == 0) s_bad = 1;
+      if (!block_pivot(e, n0, k - n0 < kPiv ? k - n0 : kPiv, b, t, rs[buf ^ 1], ts[buf ^ 1], dg, c) && c == 0) s_bad = 1;
     }
     __syncthreads();
   }
