@@ -897,8 +897,11 @@ hipError_t spmm_window(nmf_handle* h, const Plan& p, const Factor& F, T* X, cons
                        const Factor& S) {
   if constexpr (sizeof(T) == 4) {
     if (h->use_vhalf && &p == &h->planAt) {
-      // the fused kernel reads 16-byte groups of 64-byte aligned rows
-      const int32_t ldn = dense_ld(win.kw, sizeof(float));
+      // the fused kernel reads 16-byte groups of 16-byte aligned rows: the
+      // window's columns at a pitch of kw rounded up to 4, which never
+      // exceeds the pitch of S's own dense copy (k rounded up to 4 or more)
+      const int32_t ldn = (win.kw + 3) / 4 * 4;
+      if (F.rows * ldn > S.rows * S.ld) return hipErrorInvalidValue;
       hipError_t e = narrow_rows(h, F, win.c0, win.kw, ldn, static_cast<float*>(S.dense));
       if (e != hipSuccess) return e;
       Factor Fn = F;

@@ -486,7 +486,7 @@ hipError_t vhalf(nmf_handle* h, const Plan& p, const Factor& F, const float* den
 
 hipError_t vhalf_window(nmf_handle* h, const Plan& p, const Factor& F, float* X, const ColWindow& win) {
   if (win.kw < 1 || win.kw > kVhTopics || win.x_c0 < 0 || win.x_c0 + win.kw > win.x_ld || F.ld < win.kw ||
-      F.ld % 16 != 0 || p.hot_ld > kMaxHot || (p.rows + kVhTile) * p.hot_ld * 4 >= (int64_t{1} << 32) ||
+      F.ld % 4 != 0 || p.hot_ld > kMaxHot || (p.rows + kVhTile) * p.hot_ld * 4 >= (int64_t{1} << 32) ||
       (p.rows + kVhTile) * win.x_ld * 4 >= (int64_t{1} << 32) || (p.nnz + 4) * 4 >= (int64_t{1} << 32) ||
       F.rows * F.ld * 4 >= (int64_t{1} << 32))
     return hipErrorInvalidValue;

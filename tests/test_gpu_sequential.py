@@ -115,6 +115,31 @@ def test_sequential_fp32_error_curve():
     prob.close()
 
 
+@pytest.mark.parametrize("k,k2,t_u", [(2, 1, 150), (6, 3, 60), (12, 4, 30)])
+def test_sequential_fp32_small_k_many_rows(k, k2, t_u):
+    """Regression: the float32 V half of a block reads a copy of U's block
+    columns written into the dense storage of U's other buffer.  At the start
+    of every block those columns hold the dense initial guess, so every row of
+    U is nonempty; with k <= 12 a copy padded to 16 columns overran that
+    storage (for k = 2 into the next factor's arrays).  The copy's pitch is
+    now at most U's own.  E curve and factors against the oracle at the
+    stated 1e-4."""
+    NMF, _ = _lib()
+    c = synth.make_corpus(400, 600, seed=97, alpha=1.1, nnz=12000, dtype="f32")
+    u0, _ = synth.make_init(400, 600, k, seed=97, dtype="f32")
+    eta = k // k2
+    _say(f"fp32 sequential 400x600 nnz={c.nnz} k={k} k2={k2} t_u={t_u} t_v=100, 3 iterations per block")
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=t_u, t_v=100, dtype="f32")
+    prob.sequential(k2, 3)
+    E, _, nu, _ = prob.history()
+    st = oracle.sequential_als(c.scipy(), u0[:, :k2], t_u, 100, k2=k2, eta=eta, iters=3)
+    _say(f"  E gpu {E[-1]:.6f} oracle {st.E[-1]:.6f}, nnz(U) {nu[-1]} over {c.n} rows")
+    np.testing.assert_allclose(E, st.E, rtol=1e-4)
+    U, V = prob.factors()
+    assert rel_fro(U, st.U) < 1e-4 and rel_fro(V, st.V) < 1e-4
+    prob.close()
+
+
 def test_sequential_arguments():
     NMF, NMFError = _lib()
     c = synth.make_corpus(200, 150, seed=93, alpha=1.1, nnz=3000, dtype="f64")
