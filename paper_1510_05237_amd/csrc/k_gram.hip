@@ -11,7 +11,7 @@
 //     waves add strided subsets of the block partials in float64 and the
 //     four sums are combined in a fixed order, so G does not depend on
 //     scheduling.
-//  3. k_gram_factor (one block) inverts in float64 (see there):
+//  3. k_gram_block (one block) inverts in float64 (see there):
 //      * dead topics (zero diagonal: an all-zero column of F) get an identity
 //        row and column, which keeps that topic at exactly zero;
 //      * a pivot that is not positive elsewhere (G not positive definite)
@@ -268,113 +268,20 @@ __global__ __launch_bounds__(256) void k_gram_mfma_b(const GramArgs* as, const B
 // Dead topics (G_cc = 0) get identity rows and columns first, which the
 // sweep leaves as -1 on the diagonal (W_cc = 1).
 //
-// The KM x KM matrix lives in registers: thread t of 1024 owns column
-// c = t % KM and the R = KM^2 / 1024 rows (at least one) of its row block
-// t / KM.  By
-// symmetry every update of step p needs only row p (a_pj and a_ip = a_pi):
-// its owners publish it in a double-buffered LDS copy, one barrier a step.
-constexpr int kFactorThreads = 1024;
-
-template <int KM>
-__device__ __forceinline__ void k_gram_factor_body(const GramArgs& g, int blk, int nblk) {
-  constexpr int NB = kFactorThreads / KM;  // row blocks
-  constexpr int R = KM / NB;               // rows per thread
-  __shared__ double rowp[2][KM];
-  __shared__ int s_dead[KM];
-  __shared__ int s_nd;
-  if (*g.status != 0) return;
-  const int k = g.k;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_nd = 0;
-    if (g.max_nnz) {
-      const int64_t cur = static_cast<int64_t>(*g.counts_a) + (g.counts_b ? *g.counts_b : 0);
-      if (cur > *g.max_nnz) *g.max_nnz = cur;
-    }
-  }
-  __syncthreads();
-  for (int c = tid; c < KM; c += kFactorThreads) {
-    const int d = c < k && g.G[c * k + c] == 0.0;
-    s_dead[c] = d;
-    if (d) atomicAdd(&s_nd, 1);
-  }
-  __syncthreads();
-  if (tid == 0) *g.dead = s_nd;
-  const int c = tid % KM;
-  const int r0 = (tid / KM) * R;
-  double e[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int i = r0 + q;
-    double v = 0.0;
-    if (i < k && c < k) v = (s_dead[i] || s_dead[c]) ? (i == c ? 1.0 : 0.0) : g.G[i * k + c];
-    e[q] = v;
-  }
-  bool ok = true;
-  for (int p = 0; p < k; ++p) {
-    const int b = p & 1;
-    if (p / R == r0 / R) {
-      const int qp = p - r0;
-      double v = 0.0;
-#pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (q == qp) v = e[q];
-      rowp[b][c] = v;
-    }
-    __syncthreads();
-    const double d = rowp[b][p];
-    ok = ok && d > 0.0;
-    const double ip = 1.0 / d;
-    const double apc = rowp[b][c] * ip;  // b_pc for c != p
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = r0 + q;
-      const double aip = rowp[b][i];
-      double v;
-      if (i == p)
-        v = c == p ? -ip : apc;
-      else if (c == p)
-        v = aip * ip;
-      else
-        v = fma(-aip, apc, e[q]);
-      e[q] = v;
-    }
-  }
-  if (!ok) {
-    if (tid == 0) atomicCAS(g.status, 0, static_cast<int32_t>(NMF_ERR_NOT_SPD));
-    for (int x = tid; x < k * k; x += kFactorThreads) g.W[x] = 0.0;
-    return;
-  }
-  if (c < k) {
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = r0 + q;
-      if (i < k) g.W[i * k + c] = -e[q];
-    }
-  }
-}
-template <int KM>
-__global__ __launch_bounds__(kFactorThreads) void k_gram_factor(GramArgs g) { k_gram_factor_body<KM>(g, blockIdx.x, gridDim.x); }
-template <int KM>
-__global__ __launch_bounds__(kFactorThreads) void k_gram_factor_b(const GramArgs* as, const BlockMap* map) {
-  const BlockMap m = map[blockIdx.x];
-  const GramArgs g = as[m.prob];
-  k_gram_factor_body<KM>(g, m.blk, m.nblk);
-}
-
-
-// Blocked form for k <= 64: the pivots are swept four at a time.  Sweeping a
-// pivot set P at once (B = a_PP, positive definite as a Schur complement of
-// G) maps a to b with
+// The pivots are swept four at a time.  Sweeping a pivot set P at once
+// (B = a_PP, positive definite as a Schur complement of G) maps a to b with
 //   b_PP = -B^-1,  b_Pj = B^-1 a_Pj,  b_iP = a_iP B^-1,
 //   b_ij = a_ij - a_iP B^-1 a_Pj            (i, j not in P),
 // the same matrix as sweeping P's pivots one at a time, and its pivots are
-// the same Schur complement diagonals (checked the same way).  Wave w owns
-// rows 4w..4w+3 of the 64 x 64 register matrix, lane = column.  The wave
-// that owns the next block reads its 4 x 4 diagonal block (through LDS),
-// sweeps it in registers (b = -B^-1), forms T = B^-1 a_P. for every column
-// and publishes a_P. and T; by symmetry (a_iP = a_Pi) every other wave's
-// update needs only these, so a block of four pivots takes one barrier.
+// the same Schur complement diagonals (checked the same way).  The KM x KM
+// register matrix (KM = 64 H, k <= KM) is split into blocks of four rows;
+// wave w of the 16 owns blocks w and, when H = 2, w + 16, and lane c holds
+// columns c and c + 64.  The wave that owns the next block reads its 4 x 4
+// diagonal block (through LDS), sweeps it in registers (b = -B^-1), forms
+// T = B^-1 a_P. for every column and publishes a_P. and T; by symmetry
+// (a_iP = a_Pi) every other row's update needs only these, so a block of
+// four pivots takes one barrier.
+constexpr int kFactorThreads = 1024;
 constexpr int kPiv = 4;
 
 // 1 / d for a pivot d > 0: the hardware reciprocal estimate refined by two
@@ -390,18 +297,27 @@ __device__ __forceinline__ double pivot_recip(double d) {
   return fma(r, e, r);
 }
 
-// The owner wave of block j: sweep its diagonal block (rows/columns
-// p0..p0+bs-1) into b = -B^-1, then T[q] = (B^-1 a_P.)[q][c] for its lane's
-// column; publishes a_P. (its rows as they stand) and T.  The diagonal block
-// reaches every lane through `dg` (written by its own lanes, read back by the
-// same wave, whose LDS accesses complete in order).  Returns false on a pivot
+// The owner wave of the block of pivots p0..p0+bs-1 (its rows e): sweep the
+// diagonal block into b = -B^-1, then t[q][h] = (B^-1 a_P.)[q][c + 64 h];
+// publishes a_P. (its rows as they stand) and T.  The diagonal block reaches
+// every lane through `dg` (written by its own lanes, read back by the same
+// wave, whose LDS accesses complete in order).  Returns false on a pivot
 // that is not positive.
-__device__ __forceinline__ bool block_pivot(const double (&e)[kPiv], int p0, int bs, double (&b)[kPiv][kPiv],
-                                            double (&t)[kPiv], double (*rs)[kPiv], double (*ts)[kPiv],
+template <int H>
+__device__ __forceinline__ bool block_pivot(const double (&e)[kPiv][H], int p0, int bs, double (&b)[kPiv][kPiv],
+                                            double (&t)[kPiv][H], double (*rs)[kPiv], double (*ts)[kPiv],
                                             double (*dg)[kPiv], int c) {
-  if (c >= p0 && c < p0 + kPiv)
+  // the block's four columns lie in one half (p0 is a multiple of 4)
+  const int h0 = p0 >> 6, cl = p0 & 63;
+  if (c >= cl && c < cl + kPiv)
 #pragma unroll
-    for (int q = 0; q < kPiv; ++q) dg[q][c - p0] = e[q];
+    for (int q = 0; q < kPiv; ++q) {
+      double v = e[q][0];
+#pragma unroll
+      for (int h = 1; h < H; ++h)
+        if (h == h0) v = e[q][h];
+      dg[q][c - cl] = v;
+    }
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int q = 0; q < kPiv; ++q)
@@ -433,23 +349,29 @@ __device__ __forceinline__ bool block_pivot(const double (&e)[kPiv], int p0, int
   }
   // rows/columns of the block past bs are zero padding and stay zero
 #pragma unroll
-  for (int q = 0; q < kPiv; ++q) {
-    double v = 0.0;
+  for (int q = 0; q < kPiv; ++q)
 #pragma unroll
-    for (int l = 0; l < kPiv; ++l) v = fma(-b[q][l], e[l], v);
-    t[q] = v;
-  }
+    for (int h = 0; h < H; ++h) {
+      double v = 0.0;
 #pragma unroll
-  for (int q = 0; q < kPiv; ++q) {
-    rs[c][q] = e[q];
-    ts[c][q] = t[q];
-  }
+      for (int l = 0; l < kPiv; ++l) v = fma(-b[q][l], e[l][h], v);
+      t[q][h] = v;
+    }
+#pragma unroll
+  for (int q = 0; q < kPiv; ++q)
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      rs[c + 64 * h][q] = e[q][h];
+      ts[c + 64 * h][q] = t[q][h];
+    }
   return ok;
 }
 
+template <int H>
 __device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, int nblk) {
-  constexpr int KM = 64;
-  static_assert(KM / kPiv * 64 == kFactorThreads, "one wave per block of four rows");
+  constexpr int KM = 64 * H;
+  constexpr int NW = kFactorThreads / 64;
+  static_assert(NW * kPiv * H == KM, "16 waves of H blocks of four rows");
   __shared__ double rs[2][KM][kPiv];  // rs[.][c][l] = a_{p0+l, c}
   __shared__ double ts[2][KM][kPiv];  // ts[.][c][q] = (B^-1 a_P.)[q][c]
   __shared__ double dg[kPiv][kPiv];   // the owner's diagonal block
@@ -475,56 +397,76 @@ __device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, in
   __syncthreads();
   if (tid == 0) *g.dead = s_nd;
   const int c = lane_id();
-  const int wv = tid >> 6;  // owns rows kPiv * wv ...
-  double e[kPiv];
+  const int wv = tid >> 6;  // owns row blocks wv (and wv + 16)
+  double e[H][kPiv][H];     // e[lb][q][h]: row kPiv (wv + 16 lb) + q, column c + 64 h
 #pragma unroll
-  for (int q = 0; q < kPiv; ++q) {
-    const int i = kPiv * wv + q;
-    double v = 0.0;
-    if (i < k && c < k) v = (s_dead[i] || s_dead[c]) ? (i == c ? 1.0 : 0.0) : g.G[i * k + c];
-    e[q] = v;
-  }
+  for (int lb = 0; lb < H; ++lb)
+#pragma unroll
+    for (int q = 0; q < kPiv; ++q)
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int i = kPiv * (wv + NW * lb) + q, col = c + 64 * h;
+        double v = 0.0;
+        if (i < k && col < k) v = (s_dead[i] || s_dead[col]) ? (i == col ? 1.0 : 0.0) : g.G[i * k + col];
+        e[lb][q][h] = v;
+      }
   const int nbk = (k + kPiv - 1) / kPiv;
-  double b[kPiv][kPiv], t[kPiv];
-  if (wv == 0 && !block_pivot(e, 0, k < kPiv ? k : kPiv, b, t, rs[0], ts[0], dg, c) && c == 0) s_bad = 1;
+  double b[kPiv][kPiv], t[kPiv][H];
+  if (wv == 0 && !block_pivot<H>(e[0], 0, k < kPiv ? k : kPiv, b, t, rs[0], ts[0], dg, c) && c == 0) s_bad = 1;
   __syncthreads();
   for (int j = 0; j < nbk; ++j) {
     const int buf = j & 1;
     const int p0 = kPiv * j;
     const int bs = k - p0 < kPiv ? k - p0 : kPiv;
-    const bool cp = c >= p0 && c < p0 + bs;
-    const int m = (c - p0) & (kPiv - 1);
-    if (wv == j) {
-      // the block's own rows: -B^-1 inside the block, T elsewhere
 #pragma unroll
-      for (int q = 0; q < kPiv; ++q) {
-        if (q >= bs) break;
-        double w = b[q][0];
+    for (int lb = 0; lb < H; ++lb) {
+      const int jb = wv + NW * lb;
+      if (jb >= nbk) continue;
 #pragma unroll
-        for (int l = 1; l < kPiv; ++l)
-          if (m == l) w = b[q][l];
-        e[q] = cp ? w : t[q];
-      }
-    } else if (wv < nbk) {
-      const double t0 = ts[buf][c][0], t1 = ts[buf][c][1], t2 = ts[buf][c][2], t3 = ts[buf][c][3];
+      for (int h = 0; h < H; ++h) {
+        const int col = c + 64 * h;
+        const bool cp = col >= p0 && col < p0 + bs;
+        const int m = (col - p0) & (kPiv - 1);
+        if (jb == j) {
+          // the block's own rows: -B^-1 inside the block, T elsewhere
 #pragma unroll
-      for (int q = 0; q < kPiv; ++q) {
-        const int i = kPiv * wv + q;
-        if (cp) {
-          e[q] = ts[buf][i][m];  // a_iP B^-1 = (B^-1 a_Pi)^T by symmetry
+          for (int q = 0; q < kPiv; ++q) {
+            if (q >= bs) break;
+            double w = b[q][0];
+#pragma unroll
+            for (int l = 1; l < kPiv; ++l)
+              if (m == l) w = b[q][l];
+            e[lb][q][h] = cp ? w : t[q][h];
+          }
         } else {
-          double v = e[q];
-          v = fma(-rs[buf][i][0], t0, v);
-          v = fma(-rs[buf][i][1], t1, v);
-          v = fma(-rs[buf][i][2], t2, v);
-          v = fma(-rs[buf][i][3], t3, v);
-          e[q] = v;
+          const double t0 = ts[buf][col][0], t1 = ts[buf][col][1], t2 = ts[buf][col][2], t3 = ts[buf][col][3];
+#pragma unroll
+          for (int q = 0; q < kPiv; ++q) {
+            const int i = kPiv * jb + q;
+            if (cp) {
+              e[lb][q][h] = ts[buf][i][m];  // a_iP B^-1 = (B^-1 a_Pi)^T by symmetry
+            } else {
+              double v = e[lb][q][h];
+              v = fma(-rs[buf][i][0], t0, v);
+              v = fma(-rs[buf][i][1], t1, v);
+              v = fma(-rs[buf][i][2], t2, v);
+              v = fma(-rs[buf][i][3], t3, v);
+              e[lb][q][h] = v;
+            }
+          }
         }
       }
     }
-    if (wv == j + 1 && j + 1 < nbk) {
+    // the owner of the next block sweeps its diagonal block (a different
+    // wave from this block's: blocks go round the 16 waves)
+    if (j + 1 < nbk && wv == ((j + 1) % NW)) {
       const int n0 = p0 + kPiv;
-      if (!block_pivot(e, n0, k - n0 < kPiv ? k - n0 : kPiv, b, t, rs[buf ^ 1], ts[buf ^ 1], dg, c) && c == 0) s_bad = 1;
+      const int nbs = k - n0 < kPiv ? k - n0 : kPiv;
+      bool ok = true;
+#pragma unroll
+      for (int lb = 0; lb < H; ++lb)
+        if ((j + 1) / NW == lb) ok = block_pivot<H>(e[lb], n0, nbs, b, t, rs[buf ^ 1], ts[buf ^ 1], dg, c);
+      if (!ok && c == 0) s_bad = 1;
     }
     __syncthreads();
   }
@@ -533,19 +475,25 @@ __device__ __forceinline__ void k_gram_block_body(const GramArgs& g, int blk, in
     for (int x = tid; x < k * k; x += kFactorThreads) g.W[x] = 0.0;
     return;
   }
-  if (c < k) {
 #pragma unroll
-    for (int q = 0; q < kPiv; ++q) {
-      const int i = kPiv * wv + q;
-      if (i < k) g.W[i * k + c] = -e[q];
-    }
-  }
+  for (int lb = 0; lb < H; ++lb)
+#pragma unroll
+    for (int q = 0; q < kPiv; ++q)
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int i = kPiv * (wv + NW * lb) + q, col = c + 64 * h;
+        if (i < k && col < k) g.W[i * k + col] = -e[lb][q][h];
+      }
 }
-__global__ __launch_bounds__(kFactorThreads) void k_gram_block(GramArgs g) { k_gram_block_body(g, blockIdx.x, gridDim.x); }
+template <int H>
+__global__ __launch_bounds__(kFactorThreads) void k_gram_block(GramArgs g) {
+  k_gram_block_body<H>(g, blockIdx.x, gridDim.x);
+}
+template <int H>
 __global__ __launch_bounds__(kFactorThreads) void k_gram_block_b(const GramArgs* as, const BlockMap* map) {
   const BlockMap m = map[blockIdx.x];
   const GramArgs g = as[m.prob];
-  k_gram_block_body(g, m.blk, m.nblk);
+  k_gram_block_body<H>(g, m.blk, m.nblk);
 }
 
 
@@ -575,8 +523,8 @@ hipError_t launch(nmf_handle* h, GramArgs& g, int64_t rows_bound) {
   const unsigned rblocks = static_cast<unsigned>((ne + kReduceEntries - 1) / kReduceEntries);
   if ((e = launch_rec(h, k_gram_reduce<T>, k_gram_reduce_b<T>, rblocks, 256, 0, g)) != hipSuccess) return e;
   if (!g.W) return hipSuccess;
-  if (k <= 64) return launch_rec(h, k_gram_block, k_gram_block_b, 1, kFactorThreads, 0, g);
-  return launch_rec(h, k_gram_factor<128>, k_gram_factor_b<128>, 1, kFactorThreads, 0, g);
+  if (k <= 64) return launch_rec(h, k_gram_block<1>, k_gram_block_b<1>, 1, kFactorThreads, 0, g);
+  return launch_rec(h, k_gram_block<2>, k_gram_block_b<2>, 1, kFactorThreads, 0, g);
 }
 
 }  // namespace
@@ -655,9 +603,9 @@ hipError_t block_inverse(nmf_handle* h, const double* G, int k1, int k2, double*
   g.dead = dead;
   g.status = h->status;
   if (k2 <= 64)
-    hipLaunchKernelGGL(k_gram_block, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+    hipLaunchKernelGGL(k_gram_block<1>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
   else
-    hipLaunchKernelGGL(k_gram_factor<128>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
+    hipLaunchKernelGGL(k_gram_block<2>, dim3(1), dim3(kFactorThreads), 0, h->stream, g);
   return hipGetLastError();
 }
 
