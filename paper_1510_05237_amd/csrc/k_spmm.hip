@@ -63,6 +63,8 @@ constexpr int kQueueBatch = 8;
 // Claim table of the ordered entry-by-entry adds (one per wave): slot
 // (row, topic) of the accumulator hashes to entry (topic + 16 row) % 128.
 constexpr int kClaims = 128;
+// Piece sums of a long row in flight at once in k_spmm_heavy.
+constexpr int kHeavyLoads = 32;
 // Sub-rounds before the claim table is cleared and the tag restarts (tags
 // stay far from overflowing the 32-bit entries).
 constexpr int32_t kTagMax = 1 << 22;
@@ -752,14 +754,16 @@ __device__ __forceinline__ void spmm_heavy_body(const SpmmArgs& a, int blk, int 
     for (int q = 0; q < KPL; ++q) {
       const int c = lane + 64 * q;
       if (c < k) {
+        // kHeavyLoads loads in flight (the longest rows of a billion-nonzero
+        // corpus have thousands of pieces), added in piece order
         T s = T(0);
         int j = 0;
-        for (; j + 8 <= nch; j += 8) {  // eight loads in flight, added in order
-          T v[8];
+        for (; j + kHeavyLoads <= nch; j += kHeavyLoads) {
+          T v[kHeavyLoads];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = part[static_cast<int64_t>(p0 + j + u) * k + c];
+          for (int u = 0; u < kHeavyLoads; ++u) v[u] = part[static_cast<int64_t>(p0 + j + u) * k + c];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) s += v[u];
+          for (int u = 0; u < kHeavyLoads; ++u) s += v[u];
         }
         for (; j < nch; ++j) s += part[static_cast<int64_t>(p0 + j) * k + c];
         tile[c * RG] = s;
