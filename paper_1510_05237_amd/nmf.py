@@ -159,6 +159,54 @@ def _ptr(x) -> Optional[int]:
     raise TypeError(f"unsupported array type {type(x)}")
 
 
+def _shape_size(x):
+    """(shape, bytes per element) of a numpy array or torch tensor."""
+    if isinstance(x, np.ndarray):
+        return tuple(x.shape), x.itemsize
+    import torch
+
+    if isinstance(x, torch.Tensor):
+        return tuple(x.shape), x.element_size()
+    raise TypeError(f"unsupported array type {type(x)}")
+
+
+# The library receives bare pointers and cannot see an array's length or
+# element type, so the binding refuses what the library would misread: a
+# wrong element size with TypeError, a wrong length or shape with
+# NMFError(NMF_ERR_INVALID_ARG), the status the library gives a bad size.
+
+
+def _check_csr(n: int, elt: int, indptr, indices, data) -> int:
+    """A as n + 1 int64 row offsets, then int32 column indices and values of
+    `elt` bytes, at least as many as the offsets end at; returns nnz."""
+    shape, size = _shape_size(indptr)
+    if size != 8:
+        raise TypeError("indptr must hold int64 row offsets")
+    if shape != (n + 1,):
+        raise NMFError(NMF_ERR_INVALID_ARG, f"indptr must have n + 1 = {n + 1} entries, got shape {shape}")
+    nnz = int(indptr[-1])
+    for name, x, want, what in (("indices", indices, 4, "int32 column indices"),
+                                ("data", data, elt, f"{elt}-byte values")):
+        shape, size = _shape_size(x)
+        if size != want:
+            raise TypeError(f"{name} must hold {what}")
+        if len(shape) != 1 or shape[0] < nnz:
+            raise NMFError(NMF_ERR_INVALID_ARG, f"{name} must hold the {nnz} entries indptr ends at, "
+                                                f"got shape {shape}")
+    return nnz
+
+
+def _check_factor(x, name: str, rows: int, k: int, elt: int):
+    """A factor (or initial guess) as a rows x k matrix of `elt`-byte values."""
+    if x is None:
+        return
+    shape, size = _shape_size(x)
+    if size != elt:
+        raise TypeError(f"{name} must hold {elt}-byte values")
+    if shape != (rows, k):
+        raise NMFError(NMF_ERR_INVALID_ARG, f"{name} must be {rows} x {k}, got shape {shape}")
+
+
 def _stream_ptr(stream) -> Optional[int]:
     import torch
 
@@ -431,7 +479,10 @@ class NMF:
         self.n, self.m, self.k = int(n), int(m), k
         self.cfg = nmf_config(n=int(n), m=int(m), k=k, mode=_MODES[mode], t_u=int(t_u), t_v=int(t_v),
                               dtype=NMF_F32 if dtype == "f32" else NMF_F64, flags=int(flags))
-        nnz = int(indptr[-1])
+        elt = 4 if dtype == "f32" else 8
+        nnz = _check_csr(self.n, elt, indptr, indices, data)
+        _check_factor(u0, "u0", self.n, k, elt)
+        _check_factor(v0, "v0", self.m, k, elt)
         self.nnz = nnz
         with torch.cuda.device(self.device):
             self.ws_bytes = nmf_workspace_size(self.cfg, nnz)
@@ -496,6 +547,10 @@ class NMF:
         return out
 
     def set_factors(self, u, u_prev=None, v=None):
+        elt = 4 if self.dtype == "f32" else 8
+        _check_factor(u, "u", self.n, self.k, elt)
+        _check_factor(u_prev, "u_prev", self.n, self.k, elt)
+        _check_factor(v, "v", self.m, self.k, elt)
         nmf_set_factors(self.h, u, u_prev, v)
 
     def set_param(self, param: int, value: int):
@@ -672,12 +727,14 @@ class NMFBatch:
         self.device = torch.device(device)
         self.dtype = dtype
         cfgs, nnz = [], []
+        elt = 4 if dtype == "f32" else 8
         for p in problems:
             k = int(p["u0"].shape[1])
             cfgs.append(nmf_config(n=int(p["n"]), m=int(p["m"]), k=k, mode=_MODES[mode], t_u=int(p["t_u"]),
                                    t_v=int(p["t_v"]), dtype=NMF_F32 if dtype == "f32" else NMF_F64,
                                    flags=int(flags)))
-            nnz.append(int(p["indptr"][-1]))
+            nnz.append(_check_csr(int(p["n"]), elt, p["indptr"], p["indices"], p["data"]))
+            _check_factor(p["u0"], "u0", int(p["n"]), k, elt)
         self.count = len(cfgs)
         with torch.cuda.device(self.device):
             self.ws_bytes = nmf_batch_workspace_size(cfgs, nnz)
