@@ -709,6 +709,12 @@ nmf_status do_create(nmf_handle* h, const int64_t* rp_in, const int32_t* col_in,
   h->planA.nnz = nnz;
   h->planAt.nnz = nnz_t;
   HIPCHK(h, hipMemcpy(h->planAt.val, cval, nnz_t * sizeof(T), hipMemcpyHostToDevice));
+  if (h->use_vhalf) {
+    // the fused V-half kernel's four spare entries past the padded stream
+    // (its aligned reads at a document's end reach them): no term, value 0
+    HIPCHK(h, hipMemset(h->planAt.col + nnz_t, 0xFF, 4 * sizeof(int32_t)));
+    HIPCHK(h, hipMemset(static_cast<char*>(h->planAt.val) + nnz_t * sizeof(T), 0, 4 * sizeof(T)));
+  }
   if (n_hot && (h->planAt.hot == nullptr || h->planAt.hot_col == nullptr))
     return fail(h, NMF_ERR_WORKSPACE, "internal: no room for the hot block");
   h->planAt.n_hot = n_hot;
