@@ -430,6 +430,52 @@ def compare_rules_wide(total_iters: int = 100):
     return {"workload": f"plain_{c.n}x{c.m}", "nnz": c.nnz, "k": k, "k2": 1, "iters": total_iters, "rules": out}
 
 
+def scale_oracle_sample(docs=(25_000, 100_000), iters: int = 2):
+    """The FP64 oracle beside the scale configuration (1M terms, 200 terms
+    per document, k = 100, alpha = 1.05), on document samples of the same
+    recipe drawn on the host: per sample one untimed iteration from U0, then
+    `iters` timed ones; t_u = 5000 as in the configuration, t_v scaled with
+    the documents (20000 per 5M).  An oracle iteration costs a part fixed by
+    the 1M terms (U's dense pre-selection matrix, its solve and its select)
+    plus a part linear in the documents, so the two samples give the
+    5M-document figure on a straight line.  Host only: no GPU is touched."""
+    import numpy as np
+    import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from synth.scale import make_scale_corpus, make_scale_init
+
+    n, m_full, d, k, t_u, t_v_full = 1_000_000, 5_000_000, 200, 100, 5000, 20000
+    u0 = make_scale_init(n, k, seed=3, device="cpu").double().numpy()
+    pts = []
+    with threadpool_limits(limits=os.cpu_count() or 1):
+        for m in docs:
+            c = make_scale_corpus(n, m, d, seed=3, alpha=1.05, device="cpu")
+            A = sp.csr_matrix((c.data.double().numpy(), c.indices.numpy().astype(np.int64), c.indptr.numpy()),
+                              shape=(n, m))
+            del c
+            t_v = max(1, t_v_full * m // m_full)
+            st = oracle.als(A, u0, t_u, t_v, 1)
+            times = []
+            for _ in range(iters):
+                t0 = time.perf_counter()
+                st = oracle.als(A, u0, t_u, t_v, 1, state=st)
+                times.append(time.perf_counter() - t0)
+            med = statistics.median(times)
+            pts.append({"docs": m, "nnz": m * d, "t_v": t_v, "s_per_iteration": round(med, 2)})
+            log(f"scale oracle sample: {m} documents, {med:.2f} s per steady-state iteration")
+        threads = _blas_threads()
+    (m0, s0), (m1, s1) = [(q["docs"], q["s_per_iteration"]) for q in pts[:2]]
+    est = s0 + (s1 - s0) / (m1 - m0) * (m_full - m0)
+    return {"workload": f"scale_{n}x{m_full}_k{k}", "kind": "oracle", "samples": pts,
+            "s_per_iteration_extrapolated": round(est, 1), "it_per_s_extrapolated": round(1.0 / est, 5),
+            "cores": threads, "host": host_info(),
+            "note": ("FP64 numpy/scipy oracle, BLAS on all host threads (sparse products single-threaded); "
+                     "each sample: 1 untimed iteration from U0, then the median of the timed ones; "
+                     "extrapolated linearly in the document count to 5M documents (1B nonzeros)")}
+
+
 def scale_rate(warm: int = 2, iters: int = 3):
     """The scale configuration (1M terms x 5M documents, 200 terms per
     document, 1B nonzeros, k = 100, t = 5000 / 20000 per column, FP32 with
@@ -564,6 +610,9 @@ def main():
                     help="print only the k = 50 per-column / sequential comparison and exit")
     ap.add_argument("--scale", action="store_true",
                     help="print the 1M x 5M (1B nonzeros, k = 100) rate and stage breakdown and exit")
+    ap.add_argument("--scale-oracle", action="store_true",
+                    help="print the FP64 oracle's time per iteration at the 1M x 5M scale, extrapolated from "
+                         "document samples timed on the host (no GPU), and exit")
     ap.add_argument("--compare-autograd", action="store_true",
                     help="print the autograd-loss timing against direct ABI calls and exit")
     ap.add_argument("--batch-only", action="store_true",
@@ -574,6 +623,9 @@ def main():
         print("bench.py measures one GPU: the library runs the ALS iteration on a single MI355X "
               "(there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.scale_oracle:
+        print(json.dumps({"scale_oracle": scale_oracle_sample()}), flush=True)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
