@@ -58,3 +58,32 @@ def test_gathered_counts_match_the_factors(flags):
         assert gv == want_v and gu == want_u, (it, gv, want_v, gu, want_u)
         U_in = U
     p.close()
+
+
+def test_conditioning_record_is_the_largest_diagonal_product():
+    """NMF_HIST_COND_U/V: the largest G_cc (G^-1)_cc over the live topics of
+    the factor's Gram matrix G at the end of the iteration (1 when G is
+    diagonal, larger as the columns overlap), against numpy's inverse of the
+    Gram matrix of the GPU's own final factors."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_05237_amd import NMF
+
+    c = synth.make_corpus(500, 400, seed=35, alpha=1.1, nnz=5000, dtype="f64")
+    u0, _ = synth.make_init(500, 400, 5, seed=35, dtype="f64")
+    _say("fp64 500x400 k=5: conditioning record against numpy's inverse of the final Gram matrices")
+    prob = NMF(c.n, c.m, c.indptr, c.indices, c.data, u0, t_u=30, t_v=20, dtype="f64")
+    prob.step(4)
+    U, V = prob.factors()
+    for F, field in ((U, "cond_u"), (V, "cond_v")):
+        G = F.T @ F
+        live = np.diag(G) > 0
+        Gl = G[np.ix_(live, live)]
+        ref = float(np.max(np.diag(Gl) * np.diag(np.linalg.inv(Gl))))
+        got = prob.history_field(field)
+        assert len(got) == 4, (field, got)
+        assert ref > 1.0
+        assert got[-1] == pytest.approx(ref, rel=1e-9), (field, got[-1], ref)
+    prob.close()
